@@ -1,0 +1,202 @@
+"""Throughput benchmark of the LJ cell-list MD step on one MI355X.
+
+One step = velocity-Verlet half kick + drift + wrap + cell-list rebuild
+(histogram, scan, scatter, in-cell order) + LJ forces over the 27-cell
+neighbourhood + half kick, with FP64 energy/virial/kinetic reductions every
+--thermo-every steps. Default workload: N = 256000 LJ fluid (40^3 FCC start,
+rho = 0.8442, T* = 0.722, r_c = 2.5 sigma, dt = 0.005), synthetic.
+
+Prints one JSON line with the whole-job atom-steps/s, the roofline of the
+force kernel (timed live with HIP events on the launch stream) and the FP64
+oracle's throughput on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "atom-steps/s LJ cell-list FP32 + % FP32 peak; batched & adjoint vs plain"
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X: 256 CUs x 2.4 GHz x 256 FP32 flop/clk
+FLOP_PER_CANDIDATE = 8           # displacement (3) + r^2 (5)
+FLOP_PER_ACCEPTED = 17           # rsqrt, powers, shifted magnitude, 3 accumulating FMAs
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="lj256k")
+    ap.add_argument("--thermo-every", type=int, default=100)
+    ap.add_argument("--force-reps", type=int, default=200, help="md_forces launches timed for the roofline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def algorithmic_force_flops(sys_, torch):
+    """8 flops per candidate pair the 27-cell method tests plus 17 more per
+    accepted ordered pair, counted on the current state."""
+    import numpy as np
+
+    start, _ = sys_.cell_lists()
+    cnt = np.diff(start.cpu().numpy().astype(np.int64))
+    nc = sys_.cells_per_dim
+    grid = cnt.reshape(nc, nc, nc)  # [z][y][x]
+    hood = np.zeros_like(grid)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                hood += np.roll(grid, shift=(dz, dy, dx), axis=(0, 1, 2))
+    candidates = int((grid * hood).sum())
+    counts, _ = sys_.neighbors(max_per_atom=1)  # counts only; rows truncate (flag cleared below)
+    accepted = int(counts.sum().item())
+    sys_.check(raise_on_error=False)
+    return candidates, accepted, FLOP_PER_CANDIDATE * candidates + FLOP_PER_ACCEPTED * accepted
+
+
+def cpu_baseline(pos4, box, target_s):
+    """FP64 oracle: force rows of the same state (each row = all N partners),
+    repeated until about target_s seconds; one oracle MD step costs one row
+    per atom, so rows/s is its atom-steps/s."""
+    import numpy as np
+
+    import oracle
+
+    oracle.build(force=False)
+    p = oracle.params(box)
+    n = len(pos4)
+    rng = np.random.default_rng(123)
+    rows_done, chunk = 0, 512
+    t0 = time.perf_counter()
+    while True:
+        rows = rng.choice(n, size=chunk, replace=False)
+        oracle.forces_rows(p, pos4, rows)
+        rows_done += chunk
+        el = time.perf_counter() - t0
+        if el >= target_s:
+            break
+        if el < 0.25 * target_s:
+            chunk = min(chunk * 2, 65536)
+    return {
+        "value": rows_done / el,
+        "unit": "atom-steps/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{rows_done} uniformly sampled force rows of the N={n} state, each against all N atoms "
+                  f"(FP64 brute force, minimum image), {el:.1f} s on the host; an oracle step costs one row per atom",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding design notes); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import ljsynth
+    from paper_0709_3225_amd import LJSystem
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = ljsynth.WORKLOADS[args.workload]
+    pos4, vel4, box = ljsynth.make_state(w)
+    s = LJSystem(w.n, box, epsilon=w.epsilon, sigma=w.sigma, mass=w.mass, rc_over_sigma=w.rc_over_sigma, dt=w.dt)
+    s.load(torch.from_numpy(pos4).cuda(), torch.from_numpy(vel4).cuda())
+    if args.warmup:
+        s.step(args.warmup)
+    s.check()
+
+    # ---- timed region: K whole steps
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    thermo = s.step(args.steps, thermo_every=args.thermo_every)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    s.check()
+    elapsed = max(wall, gpu_s)
+    value = w.n * args.steps / elapsed
+
+    # ---- force kernel alone (md_forces without output = one kernel launch)
+    reps = args.force_reps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.forces()  # warm
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        from paper_0709_3225_amd import md_forces
+
+        md_forces(s.params, s.ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    force_us = e0.elapsed_time(e1) * 1e3 / reps
+    s.check()
+    candidates, accepted, flops = algorithmic_force_flops(s, torch)
+    achieved_tflops = flops / (force_us * 1e-6) / 1e12
+
+    e_th = None
+    if thermo is not None:
+        th = thermo.cpu().numpy()
+        e_th = {"U_per_atom": float(th[-1, 0] / w.n), "K_per_atom": float(th[-1, 1] / w.n),
+                "W_per_atom": float(th[-1, 2] / w.n)}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.name}: LJ fluid N={w.n} ({w.n_fcc}^3 FCC start), rho={w.density}, T*={w.temperature}, "
+                        f"rc=2.5 sigma force-shifted, dt={w.dt}, NVE, cell list rebuilt every step, "
+                        f"FP64 U/K/W every {args.thermo_every} steps",
+            "n": w.n,
+            "box": box,
+            "cells_per_dim": s.cells_per_dim,
+            "thermo_every": args.thermo_every,
+        },
+        "roofline": {
+            "kernel": "k_forces<false,false,true> (md_forces)",
+            "bound": "alu",
+            "achieved": achieved_tflops,
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
+            "traffic": None,
+            "kernel_us": force_us,
+            "flops_per_launch": flops,
+            "candidates": candidates,
+            "accepted_pairs": accepted,
+        },
+        "thermo_last": e_th,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(s.state()[0].cpu().numpy(), box, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * mdlj: short-range Lennard-Jones molecular dynamics over a cell list on one
+ * AMD Instinct MI355X (gfx950) GPU.
+ *
+ * The method (van Meel, Arnold, Frenkel, Portegies Zwart, Belleman,
+ * "Harvesting graphics power for MD simulations"):
+ *   - pair force: LJ force truncated at r_c = 2.5 sigma and shifted so that it
+ *     vanishes at the cutoff (section 2, equations for f_LJ and f(r));
+ *   - force on particle i: sum over the other particles of f(r_ij) along the
+ *     unit vector from j to i (section 2, force-sum equation);
+ *   - partners found through cells whose side is at least the interaction
+ *     range, so they lie in the home cell or its 26 neighbours, with
+ *     n_x = int(L / r_c) cells per dimension (section 3 and section 3.2);
+ *   - cell lists kept up to date as particles move (section 3.1);
+ *   - velocity-Verlet time integration (section 2).
+ *
+ * Conventions for every entry point:
+ *   - All functions are C ABI, never throw, and return an md_status.
+ *   - Pointers named *_dev, ws and every particle array are DEVICE pointers
+ *     owned by the caller; the library never allocates or frees memory.
+ *   - Work is enqueued asynchronously on `stream` (0 = the null stream);
+ *     only md_check synchronises.
+ *   - Particle arrays are float4 [n] (16-byte aligned); the w component of
+ *     inputs is ignored. "User order" means the order of md_build_cells' input.
+ *   - Argument and box validation happens on the host before any HIP call;
+ *     a non-OK return enqueues nothing. md_last_error() then describes it.
+ *   - Problems only the device can see (non-finite coordinates or forces,
+ *     calls out of order) set bits in a device error word inside the
+ *     workspace; md_check reads and clears it.
+ *   - Calls that share one workspace must be ordered on one stream.
+ */
+#ifndef MDLJ_MD_H
+#define MDLJ_MD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum md_status {
+    MD_OK = 0,
+    MD_ERR_ARG = 1,       /* invalid argument (null, non-finite, out of range) */
+    MD_ERR_BOX = 2,       /* box shorter than two cutoffs: L < 2 r_c */
+    MD_ERR_WORKSPACE = 3, /* workspace null, misaligned (256 B) or too small */
+    MD_ERR_HIP = 5,       /* a HIP launch or runtime call failed */
+    MD_ERR_DEVICE = 6     /* md_check found device error bits (see below) */
+} md_status;
+
+/* Device error bits reported through md_check's flags_out. */
+#define MD_DEV_NONFINITE 1 /* a coordinate, velocity or force was not finite */
+#define MD_DEV_ORDER 2     /* md_forces before md_build_cells, or md_step
+                              before md_forces: the call did nothing */
+#define MD_DEV_NB_OVERFLOW 4 /* md_neighbors: a row exceeded max_per_atom */
+
+/* Physical and numerical parameters, reduced LJ units. */
+typedef struct md_params {
+    int32_t n;             /* particle count, 1 <= n <= 2^27 */
+    float box;             /* cubic periodic box side L; this FP32 value is
+                              authoritative for images and the cell grid */
+    float epsilon;         /* LJ well depth, > 0 */
+    float sigma;           /* LJ length, > 0 */
+    float mass;            /* particle mass, > 0 */
+    float rc_over_sigma;   /* cutoff r_c / sigma; 0 selects 2.5 (section 2) */
+    float dt;              /* time step, finite, >= 0 */
+    float cell_min;        /* minimum cell side; 0 selects r_c */
+    int32_t shift_mode;    /* 0: force shifted to zero at r_c (section 2);
+                              1: plain truncated force, energy shifted */
+    int32_t flags;         /* reserved, must be 0 */
+} md_params;
+
+/*
+ * Bytes of device workspace for these parameters (0 if they are invalid).
+ * Host only; needs no device. The workspace holds the cell-sorted state
+ * (positions, velocities, forces), the cell lists, scratch and a small
+ * header; its contents are private.
+ */
+size_t md_workspace_bytes(const md_params* p);
+
+/*
+ * Cell grid the library uses (host only). Cells per dimension is
+ * n_c = int(L / max(r_c, cell_min)) as in section 3.2, lowered by one when
+ * the resulting side L/n_c exceeds the minimum by less than 2^-18 L (so that
+ * FP32 rounding of a cell index can never hide a partner); side = L / n_c.
+ * Returns MD_ERR_BOX if L < 2 r_c.
+ */
+md_status md_cell_grid(const md_params* p, int32_t* cells_per_dim, float* cell_side);
+
+/*
+ * Load a state and build the cell list (section 3: cells of side >= r_c;
+ * section 3.1: membership rebuilt from current positions).
+ *   pos4_dev: float4 [n] positions; wrapped into [0, L) on load.
+ *   vel4_dev: float4 [n] velocities, or NULL for zero velocities.
+ * Steps on the device: wrap + cell index + atomic histogram, prefix scan of
+ * the histogram into cell offsets, scatter into cell-sorted order, and a
+ * stable order inside every cell by user index (so the layout, and every
+ * later floating-point sum, is independent of atomic timing).
+ * (Re)initialises the workspace and clears its device error bits.
+ * Forces are not computed: call md_forces before md_step.
+ */
+md_status md_build_cells(const md_params* p, void* ws, size_t ws_bytes, const float* pos4_dev,
+                         const float* vel4_dev, hipStream_t stream);
+
+/*
+ * Forces on the current workspace state (section 2 force sum with the
+ * truncated, shifted LJ force; partners from the 27 cells around each home
+ * cell, minimum image). Stores them inside the workspace, which makes
+ * md_step valid, and, if force4_dev is not NULL, writes float4 [n] forces in
+ * user order (w = 0).
+ */
+md_status md_forces(const md_params* p, void* ws, size_t ws_bytes, float* force4_dev,
+                    hipStream_t stream);
+
+/*
+ * Advance nsteps velocity-Verlet steps (section 2). Each step: half kick
+ * with the stored forces, drift, wrap into [0, L), cell-list rebuild
+ * (histogram, scan, scatter, in-cell order), new forces, half kick.
+ * Velocities are synchronous with positions after every call.
+ * thermo_every > 0 with thermo_dev != NULL records (U, K, W) as doubles
+ * after every thermo_every-th step: row r (0-based) holds step
+ * (r + 1) * thermo_every, so thermo_dev needs 3 * (nsteps / thermo_every)
+ * doubles. Needs md_forces since the last md_build_cells; otherwise sets
+ * MD_DEV_ORDER and leaves the state unchanged.
+ */
+md_status md_step(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps,
+                  int32_t thermo_every, double* thermo_dev, hipStream_t stream);
+
+/*
+ * Potential energy U, kinetic energy K = m/2 sum v^2 and virial
+ * W = sum over pairs r phi(r) (positive = repulsive) of the current state,
+ * written as out3_dev[0..2] (device doubles). Pair and per-atom terms are
+ * FP32; all sums are FP64 in a fixed order, so the result is reproducible.
+ * The paper prints no energy; U uses the energy that matches the shifted
+ * force: u(r) = u_LJ(r) - u_LJ(r_c) + (r - r_c) f_LJ(r_c) (shift_mode 0), or
+ * u_LJ(r) - u_LJ(r_c) (shift_mode 1).
+ */
+md_status md_energy_virial(const md_params* p, void* ws, size_t ws_bytes, double* out3_dev,
+                           hipStream_t stream);
+
+/* Copy the current positions (wrapped) and velocities out in user order;
+ * either pointer may be NULL. float4 [n], w = 0. */
+md_status md_get_state(const md_params* p, const void* ws, size_t ws_bytes, float* pos4_dev,
+                       float* vel4_dev, hipStream_t stream);
+
+/*
+ * Test export of the neighbour sets the force kernel uses: for every atom i
+ * (user order) the user indices j != i with r_ij^2 < r_c^2 (FP32 test on the
+ * minimum-image displacement). counts_dev: int32 [n]. idx_dev: int32
+ * [n * max_per_atom], row i at i * max_per_atom, order within a row
+ * unspecified. A row longer than max_per_atom is truncated and sets
+ * MD_DEV_NB_OVERFLOW (its count is still the full count).
+ */
+md_status md_neighbors(const md_params* p, const void* ws, size_t ws_bytes, int32_t* counts_dev,
+                       int32_t* idx_dev, int32_t max_per_atom, hipStream_t stream);
+
+/*
+ * Test export of the cell list: cell_start_dev int32 [n_c^3 + 1] (CSR offsets
+ * of every cell into the sorted order) and order_dev int32 [n] (user index of
+ * the atom at each sorted slot). Either pointer may be NULL.
+ */
+md_status md_cell_lists(const md_params* p, const void* ws, size_t ws_bytes,
+                        int32_t* cell_start_dev, int32_t* order_dev, hipStream_t stream);
+
+/*
+ * Synchronise `stream`, then read and clear the device error word.
+ * flags_out (host pointer, nullable) receives the MD_DEV_* bits.
+ * Returns MD_ERR_DEVICE if any bit was set, MD_ERR_HIP on a runtime error.
+ */
+md_status md_check(void* ws, size_t ws_bytes, hipStream_t stream, int32_t* flags_out);
+
+/* Text for the last non-OK status on this thread (never NULL). */
+const char* md_last_error(void);
+
+/* Stable name of a status code (never NULL). */
+const char* md_status_name(md_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDLJ_MD_H */

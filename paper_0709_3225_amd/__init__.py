@@ -1,0 +1,26 @@
+"""MI355X-native short-range Lennard-Jones MD over a cell list.
+
+The compute path is the HIP library ``libmdlj.so`` (C-ABI in include/md.h);
+this package is its ctypes binding plus a small owner class. Importing it
+loads the library and fails if it has not been built.
+"""
+from ._lib import (  # noqa: F401
+    MDError,
+    MDParams,
+    SYMBOLS,
+    lib,
+    make_params,
+    md_build_cells,
+    md_cell_grid,
+    md_cell_lists,
+    md_check,
+    md_energy_virial,
+    md_forces,
+    md_get_state,
+    md_neighbors,
+    md_step,
+    md_workspace_bytes,
+)
+from .system import LJSystem  # noqa: F401
+
+lib()

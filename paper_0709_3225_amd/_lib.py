@@ -1,0 +1,236 @@
+"""ctypes binding of the C-ABI in include/md.h.
+
+Argument marshalling only: every step of the MD path runs in the HIP kernels
+of ``libmdlj.so``. Device buffers are torch tensors on a ROCm device; the
+library is handed raw pointers and torch's current HIP stream. There is no
+CPU fallback: if the library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmdlj.so")
+
+MD_OK = 0
+MD_ERR_ARG = 1
+MD_ERR_BOX = 2
+MD_ERR_WORKSPACE = 3
+MD_ERR_HIP = 5
+MD_ERR_DEVICE = 6
+
+MD_DEV_NONFINITE = 1
+MD_DEV_ORDER = 2
+MD_DEV_NB_OVERFLOW = 4
+
+# Symbols declared in include/md.h, in declaration order.
+SYMBOLS = (
+    "md_workspace_bytes",
+    "md_cell_grid",
+    "md_build_cells",
+    "md_forces",
+    "md_step",
+    "md_energy_virial",
+    "md_get_state",
+    "md_neighbors",
+    "md_cell_lists",
+    "md_check",
+    "md_last_error",
+    "md_status_name",
+)
+
+
+class MDError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{_status_name(code)}: {message}")
+        self.code = code
+
+
+class MDParams(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("box", ctypes.c_float),
+        ("epsilon", ctypes.c_float),
+        ("sigma", ctypes.c_float),
+        ("mass", ctypes.c_float),
+        ("rc_over_sigma", ctypes.c_float),
+        ("dt", ctypes.c_float),
+        ("cell_min", ctypes.c_float),
+        ("shift_mode", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+    ]
+
+
+def make_params(n, box, epsilon=1.0, sigma=1.0, mass=1.0, rc_over_sigma=2.5, dt=0.005, cell_min=0.0,
+                shift_mode=0, flags=0) -> MDParams:
+    return MDParams(int(n), float(box), float(epsilon), float(sigma), float(mass), float(rc_over_sigma),
+                    float(dt), float(cell_min), int(shift_mode), int(flags))
+
+
+_lib = None
+
+
+def lib():
+    """Load libmdlj.so (built in-tree by build.py); raise if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_0709_3225_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(MDParams)
+        vp = ctypes.c_void_p
+        sz = ctypes.c_size_t
+        i32 = ctypes.c_int32
+        L.md_workspace_bytes.argtypes = [P]
+        L.md_workspace_bytes.restype = sz
+        L.md_cell_grid.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
+        L.md_build_cells.argtypes = [P, vp, sz, vp, vp, vp]
+        L.md_forces.argtypes = [P, vp, sz, vp, vp]
+        L.md_step.argtypes = [P, vp, sz, i32, i32, vp, vp]
+        L.md_energy_virial.argtypes = [P, vp, sz, vp, vp]
+        L.md_get_state.argtypes = [P, vp, sz, vp, vp, vp]
+        L.md_neighbors.argtypes = [P, vp, sz, vp, vp, i32, vp]
+        L.md_cell_lists.argtypes = [P, vp, sz, vp, vp, vp]
+        L.md_check.argtypes = [vp, sz, vp, ctypes.POINTER(i32)]
+        for name in ("md_cell_grid", "md_build_cells", "md_forces", "md_step", "md_energy_virial",
+                     "md_get_state", "md_neighbors", "md_cell_lists", "md_check"):
+            getattr(L, name).restype = ctypes.c_int
+        L.md_last_error.argtypes = []
+        L.md_last_error.restype = ctypes.c_char_p
+        L.md_status_name.argtypes = [ctypes.c_int]
+        L.md_status_name.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _status_name(code: int) -> str:
+    try:
+        return lib().md_status_name(int(code)).decode()
+    except Exception:  # the name is only decoration for the message
+        return f"status {code}"
+
+
+def _check(code: int):
+    if code != MD_OK:
+        raise MDError(code, lib().md_last_error().decode())
+
+
+# ------------------------------------------------------------------ marshalling
+
+def _ptr(t, name, dtype=None, shape=None):
+    """Raw device pointer of a CUDA/HIP tensor after shape/dtype checks."""
+    if t is None:
+        return None
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(getattr(stream, "cuda_stream", stream))
+
+
+def _ws(ws):
+    import torch
+
+    p = _ptr(ws, "workspace", torch.uint8)
+    return p, ctypes.c_size_t(ws.numel())
+
+
+def md_workspace_bytes(p: MDParams) -> int:
+    return int(lib().md_workspace_bytes(ctypes.byref(p)))
+
+
+def md_cell_grid(p: MDParams):
+    nc = ctypes.c_int32()
+    side = ctypes.c_float()
+    _check(lib().md_cell_grid(ctypes.byref(p), ctypes.byref(nc), ctypes.byref(side)))
+    return nc.value, side.value
+
+
+def md_build_cells(p: MDParams, ws, pos4, vel4=None, stream=None):
+    import torch
+
+    wp, wn = _ws(ws)
+    _check(lib().md_build_cells(ctypes.byref(p), wp, wn, _ptr(pos4, "pos4", torch.float32, (p.n, 4)),
+                                _ptr(vel4, "vel4", torch.float32, (p.n, 4)), _stream(stream)))
+
+
+def md_forces(p: MDParams, ws, force4=None, stream=None):
+    import torch
+
+    wp, wn = _ws(ws)
+    _check(lib().md_forces(ctypes.byref(p), wp, wn, _ptr(force4, "force4", torch.float32, (p.n, 4)),
+                           _stream(stream)))
+
+
+def md_step(p: MDParams, ws, nsteps: int, thermo_every: int = 0, thermo=None, stream=None):
+    import torch
+
+    wp, wn = _ws(ws)
+    tp = None
+    if thermo is not None:
+        rows = nsteps // thermo_every if thermo_every > 0 else 0
+        if thermo.numel() < 3 * rows:
+            raise ValueError(f"thermo needs {3 * rows} doubles")
+        tp = _ptr(thermo, "thermo", torch.float64)
+    _check(lib().md_step(ctypes.byref(p), wp, wn, int(nsteps), int(thermo_every), tp, _stream(stream)))
+
+
+def md_energy_virial(p: MDParams, ws, out3, stream=None):
+    import torch
+
+    wp, wn = _ws(ws)
+    _check(lib().md_energy_virial(ctypes.byref(p), wp, wn, _ptr(out3, "out3", torch.float64, (3,)),
+                                  _stream(stream)))
+
+
+def md_get_state(p: MDParams, ws, pos4=None, vel4=None, stream=None):
+    import torch
+
+    wp, wn = _ws(ws)
+    _check(lib().md_get_state(ctypes.byref(p), wp, wn, _ptr(pos4, "pos4", torch.float32, (p.n, 4)),
+                              _ptr(vel4, "vel4", torch.float32, (p.n, 4)), _stream(stream)))
+
+
+def md_neighbors(p: MDParams, ws, counts, idx, max_per_atom: int, stream=None):
+    import torch
+
+    wp, wn = _ws(ws)
+    _check(lib().md_neighbors(ctypes.byref(p), wp, wn, _ptr(counts, "counts", torch.int32, (p.n,)),
+                              _ptr(idx, "idx", torch.int32, (p.n * max_per_atom,)), int(max_per_atom),
+                              _stream(stream)))
+
+
+def md_cell_lists(p: MDParams, ws, cell_start=None, order=None, stream=None):
+    import torch
+
+    wp, wn = _ws(ws)
+    _check(lib().md_cell_lists(ctypes.byref(p), wp, wn, _ptr(cell_start, "cell_start", torch.int32),
+                               _ptr(order, "order", torch.int32, (p.n,)), _stream(stream)))
+
+
+def md_check(ws, stream=None, raise_on_error: bool = True) -> int:
+    """Synchronise and read/clear the device error bits; returns them."""
+    wp, wn = _ws(ws)
+    flags = ctypes.c_int32()
+    code = lib().md_check(wp, wn, _stream(stream), ctypes.byref(flags))
+    if code == MD_ERR_DEVICE and not raise_on_error:
+        return flags.value
+    _check(code)
+    return flags.value

@@ -1,0 +1,91 @@
+// Device helpers shared by the kernels: periodic wrap, cell index,
+// wavefront-aggregated histogram ranks, wave reductions, XCD-aware block order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "md_internal.h"
+
+namespace mdlj {
+
+constexpr int kWave = 64;
+
+// Bring one FP32 coordinate into [0, L). x - L*floor(x/L) can round to L
+// exactly; then subtract L once more, and fall back to 0 for the last ulp.
+__device__ __forceinline__ float wrap_coord(float x, float L, float invL) {
+    x = x - L * floorf(x * invL);
+    if (x >= L) x -= L;
+    if (x < 0.0f || x >= L) x = 0.0f;
+    return x;
+}
+
+__device__ __forceinline__ int cell_coord(float x, float inv_s, int nc) {
+    int i = static_cast<int>(x * inv_s);
+    return i < 0 ? 0 : (i >= nc ? nc - 1 : i);
+}
+
+__device__ __forceinline__ int cell_index(float x, float y, float z, const SimArgs& a) {
+    return cell_coord(x, a.inv_s, a.nc) + a.nc * (cell_coord(y, a.inv_s, a.nc) + a.nc * cell_coord(z, a.inv_s, a.nc));
+}
+
+// Arrival rank of each lane's atom in cell c (c < 0: no atom). Lanes holding
+// the same cell in a contiguous run share one atomicAdd of the run length on
+// the histogram; input that is already cell-sorted (every step after the
+// first) turns most per-atom atomics into one per run. Must be called by all
+// 64 lanes of the wave.
+__device__ __forceinline__ int histogram_rank(int* count, int c) {
+    const int lane = __lane_id();
+    const int prev = __shfl_up(c, 1);
+    const bool head = (lane == 0) || (prev != c);
+    const uint64_t heads = __ballot(head);
+    const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const uint64_t above = heads & ~upto;
+    const int next_head = above ? (__ffsll(static_cast<unsigned long long>(above)) - 1) : kWave;
+    const int my_head = 63 - __clzll(static_cast<long long>(heads & upto));
+    int base = 0;
+    if (head && c >= 0) base = atomicAdd(&count[c], next_head - lane);
+    base = __shfl(base, my_head);
+    return base + (lane - my_head);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        int t = __shfl_up(v, off);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each with
+// its own L2. Renumber blocks so that every XCD receives one contiguous range
+// of work items (here: cells in z-major order, i.e. a slab of the box), which
+// keeps the 27-cell neighbourhoods a block stages in the L2 its neighbours use.
+__device__ __forceinline__ int xcd_block_order(int b, int nblocks) {
+    const int q = nblocks >> 3, r = nblocks & 7;
+    const int x = b & 7, k = b >> 3;
+    return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+// True if the workspace holds a built state for exactly these arguments
+// (cells built, or forces too when need_forces).
+__device__ __forceinline__ bool state_ok(const SimArgs& a, bool need_forces) {
+    const int st = a.hdr[HDR_STATE];
+    const bool built = need_forces ? (st == STATE_FORCES) : (st == STATE_CELLS || st == STATE_FORCES);
+    return built && a.hdr[HDR_N] == a.n && a.hdr[HDR_NC] == a.nc;
+}
+
+__device__ __forceinline__ bool finite3(float x, float y, float z) {
+    return isfinite(x) && isfinite(y) && isfinite(z);
+}
+
+}  // namespace mdlj

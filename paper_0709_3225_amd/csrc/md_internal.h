@@ -1,0 +1,82 @@
+// Internal declarations shared by the HIP kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mdlj {
+
+// Header words at the start of the workspace.
+// HDR_N and HDR_NC record the particle count and cell grid the workspace was
+// built for; kernels refuse a workspace whose record differs from their
+// arguments (its array offsets would not match).
+enum : int { HDR_ERROR = 0, HDR_STATE = 1, HDR_N = 2, HDR_NC = 3, HDR_WORDS = 64 };
+
+// Workspace states. Distinctive values so that an uninitialised workspace is
+// never mistaken for a built one.
+enum : int { STATE_BUILDING = 0x4D440000, STATE_CELLS = 0x4D440001, STATE_FORCES = 0x4D440002 };
+
+// Device error bits (same values as the public MD_DEV_* macros).
+enum : int { DEV_NONFINITE = 1, DEV_ORDER = 2, DEV_NB_OVERFLOW = 4 };
+
+// Everything a kernel needs, passed by value.
+struct SimArgs {
+    int* hdr;
+    float4* pos0;    // cell-sorted positions, w = user index bits
+    float4* vel0;    // cell-sorted velocities
+    float4* pos1;    // unsorted staging (after load or drift), w = user index bits
+    float4* vel1;
+    float4* force;   // cell-sorted forces
+    int* cell;       // cell of each staging slot
+    int* rank;       // arrival rank of each staging slot within its cell
+    int* key;        // sorted slot -> staging slot (before the in-cell order)
+    int* count;      // per-cell histogram (kept zero between builds)
+    int* start;      // per-cell CSR offsets, ncells + 1 entries
+    double* epart;   // per-block energy partials, 3 doubles per force block
+
+    int n;
+    int nc;          // cells per dimension
+    int ncells;      // nc^3
+    float box;
+    float s;         // cell side box / nc
+    float inv_s;     // nc / box
+
+    float rc2;       // r_c^2 (FP32)
+    float rc;
+    float sig2;      // sigma^2
+    float eps24;     // 24 epsilon
+    float eps4;      // 4 epsilon
+    float fc;        // f_LJ(r_c) for the force shift, 0 for energy shift
+    float uc;        // u_LJ(r_c)
+
+    float dt;
+    float hdt_m;     // dt / (2 m)
+    float half_m;    // m / 2
+};
+
+// Workspace layout (byte offsets, each 256-byte aligned).
+struct Layout {
+    int n, nc, ncells, nforce_blocks;
+    float s, inv_s;
+    size_t hdr, pos0, vel0, pos1, vel1, force, cell, rank, key, count, start, epart, total;
+};
+
+// Kernel launchers (each returns hipGetLastError() after its launch).
+hipError_t launch_build_init(const SimArgs& a, hipStream_t st);
+hipError_t launch_load(const SimArgs& a, const float4* pos_in, const float4* vel_in, hipStream_t st);
+hipError_t launch_scan(const SimArgs& a, hipStream_t st);
+hipError_t launch_scatter(const SimArgs& a, hipStream_t st);
+hipError_t launch_cell_order(const SimArgs& a, bool from_step, hipStream_t st);
+hipError_t launch_integrate(const SimArgs& a, hipStream_t st);
+hipError_t launch_forces(const SimArgs& a, bool kick, bool energy, bool write_force, bool from_step,
+                         hipStream_t st);
+hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st);
+hipError_t launch_gather_user(const SimArgs& a, float4* pos_out, float4* vel_out, float4* force_out,
+                              hipStream_t st);
+hipError_t launch_neighbors(const SimArgs& a, int* counts, int* idx, int max_per_atom,
+                            hipStream_t st);
+hipError_t launch_cell_lists(const SimArgs& a, int* cell_start, int* order, hipStream_t st);
+
+}  // namespace mdlj

@@ -1,0 +1,72 @@
+"""A thin Python owner of one LJ system on the GPU.
+
+Holds the parameters and the workspace tensor and forwards to the C-ABI
+entry points; it computes nothing itself.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib as L
+
+
+class LJSystem:
+    """Cubic periodic LJ system of n particles in a box of side ``box``."""
+
+    def __init__(self, n, box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_over_sigma=2.5, dt=0.005,
+                 cell_min=0.0, shift_mode=0, device="cuda"):
+        self.params = L.make_params(n, box, epsilon, sigma, mass, rc_over_sigma, dt, cell_min, shift_mode)
+        self.cells_per_dim, self.cell_side = L.md_cell_grid(self.params)  # raises on invalid params
+        self.nbytes = L.md_workspace_bytes(self.params)
+        self.device = torch.device(device)
+        self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        self.n = int(n)
+
+    @property
+    def n_cells(self) -> int:
+        return self.cells_per_dim ** 3
+
+    def load(self, pos4: torch.Tensor, vel4: torch.Tensor | None = None, forces: bool = True):
+        """md_build_cells on the given state, then (by default) md_forces."""
+        L.md_build_cells(self.params, self.ws, pos4.contiguous(), None if vel4 is None else vel4.contiguous())
+        if forces:
+            L.md_forces(self.params, self.ws)
+
+    def forces(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty((self.n, 4), dtype=torch.float32, device=self.device)
+        L.md_forces(self.params, self.ws, out)
+        return out
+
+    def step(self, nsteps: int, thermo_every: int = 0):
+        thermo = None
+        if thermo_every > 0 and nsteps >= thermo_every:
+            thermo = torch.empty((nsteps // thermo_every, 3), dtype=torch.float64, device=self.device)
+        L.md_step(self.params, self.ws, nsteps, thermo_every if thermo is not None else 0, thermo)
+        return thermo
+
+    def energy(self) -> torch.Tensor:
+        out = torch.empty(3, dtype=torch.float64, device=self.device)
+        L.md_energy_virial(self.params, self.ws, out)
+        return out
+
+    def state(self):
+        pos = torch.empty((self.n, 4), dtype=torch.float32, device=self.device)
+        vel = torch.empty((self.n, 4), dtype=torch.float32, device=self.device)
+        L.md_get_state(self.params, self.ws, pos, vel)
+        return pos, vel
+
+    def neighbors(self, max_per_atom: int = 128):
+        counts = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        idx = torch.full((self.n * max_per_atom,), -1, dtype=torch.int32, device=self.device)
+        L.md_neighbors(self.params, self.ws, counts, idx, max_per_atom)
+        return counts, idx.view(self.n, max_per_atom)
+
+    def cell_lists(self):
+        start = torch.empty(self.n_cells + 1, dtype=torch.int32, device=self.device)
+        order = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        L.md_cell_lists(self.params, self.ws, start, order)
+        return start, order
+
+    def check(self, raise_on_error: bool = True) -> int:
+        return L.md_check(self.ws, raise_on_error=raise_on_error)

@@ -1,0 +1,123 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+include/md.h declares, and validates arguments on the host before any HIP
+call. Also pins the cell-grid rule to the paper's worked example."""
+import json
+import os
+import re
+
+import pytest
+
+import paper_0709_3225_amd as md
+from paper_0709_3225_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "md.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(md_[a-z_]+)\s*\(", text, flags=re.M)
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert len(names) >= 10
+    lib = _lib.lib()
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(names) == sorted(_lib.SYMBOLS)
+
+
+def test_paper_worked_example_cell_grid():
+    """Section 3.2: L = 11 sigma, r_c = 2.5 sigma -> 4 cells of side 2.75."""
+    g = json.load(open(os.path.join(GOLDEN, "paper_cell_example.json")))
+    p = md.make_params(100, g["box"])
+    nc, side = md.md_cell_grid(p)
+    assert nc == g["cells_per_dim"]
+    assert side == pytest.approx(g["cell_side"], rel=1e-7)
+
+
+@pytest.mark.parametrize("n,rho,nc_expect", [(4000, 0.8442, 6), (256000, 0.8442, 26), (2048000, 0.8442, 53),
+                                             (32000, 0.8442, 13), (256, 0.8442, 2)])
+def test_cell_grid_of_workloads(n, rho, nc_expect):
+    import ljsynth
+
+    L = ljsynth.box_length(n, rho)
+    nc, side = md.md_cell_grid(md.make_params(n, L))
+    assert nc == nc_expect
+    assert side >= 2.5
+    assert md.md_workspace_bytes(md.make_params(n, L)) > 80 * n
+
+
+def test_cell_side_margin_rule():
+    """A side that exceeds r_c by less than 2^-18 L drops one cell, so that an
+    FP32 cell index can never be off by enough to hide a partner."""
+    nc, side = md.md_cell_grid(md.make_params(10, 10.0))  # 10 / 4 = 2.5 exactly
+    assert nc == 3
+    nc, side = md.md_cell_grid(md.make_params(10, 10.1))
+    assert nc == 4 and side > 2.5
+
+
+def test_cell_min_parameter():
+    nc, side = md.md_cell_grid(md.make_params(10, 30.0, cell_min=4.9))
+    assert nc == 6 and side == pytest.approx(5.0)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=0), _lib.MD_ERR_ARG),
+    (dict(n=-5), _lib.MD_ERR_ARG),
+    (dict(box=float("nan")), _lib.MD_ERR_ARG),
+    (dict(box=4.99), _lib.MD_ERR_BOX),
+    (dict(epsilon=0.0), _lib.MD_ERR_ARG),
+    (dict(sigma=-1.0), _lib.MD_ERR_ARG),
+    (dict(mass=float("inf")), _lib.MD_ERR_ARG),
+    (dict(dt=-0.1), _lib.MD_ERR_ARG),
+    (dict(shift_mode=2), _lib.MD_ERR_ARG),
+    (dict(flags=1), _lib.MD_ERR_ARG),
+    (dict(rc_over_sigma=float("nan")), _lib.MD_ERR_ARG),
+])
+def test_invalid_params_rejected_on_host(kw, code):
+    base = dict(n=100, box=10.0)
+    base.update(kw)
+    p = md.make_params(**base)
+    assert md.md_workspace_bytes(p) == 0
+    with pytest.raises(md.MDError) as e:
+        md.md_cell_grid(p)
+    assert e.value.code == code
+    # entry points that take device pointers fail the same way before any HIP call
+    lib = _lib.lib()
+    import ctypes
+
+    assert lib.md_build_cells(ctypes.byref(p), None, 0, None, None, None) == code
+    assert lib.md_forces(ctypes.byref(p), None, 0, None, None) == code
+    assert lib.md_step(ctypes.byref(p), None, 0, 1, 0, None, None) == code
+    assert lib.md_energy_virial(ctypes.byref(p), None, 0, None, None) == code
+
+
+def test_workspace_and_pointer_checks_on_host():
+    import ctypes
+
+    lib = _lib.lib()
+    p = md.make_params(100, 10.0)
+    need = md.md_workspace_bytes(p)
+    fake = ctypes.c_void_p(1 << 40)  # never dereferenced: validation fails first
+    assert lib.md_build_cells(ctypes.byref(p), None, need, fake, None, None) == _lib.MD_ERR_WORKSPACE
+    assert lib.md_build_cells(ctypes.byref(p), ctypes.c_void_p((1 << 40) + 64), need, fake, None, None) \
+        == _lib.MD_ERR_WORKSPACE
+    assert lib.md_build_cells(ctypes.byref(p), fake, need - 1, fake, None, None) == _lib.MD_ERR_WORKSPACE
+    assert lib.md_build_cells(ctypes.byref(p), fake, need, None, None, None) == _lib.MD_ERR_ARG
+    assert lib.md_build_cells(ctypes.byref(p), fake, need, ctypes.c_void_p((1 << 40) + 4), None, None) \
+        == _lib.MD_ERR_ARG
+    assert lib.md_step(ctypes.byref(p), fake, need, -1, 0, None, None) == _lib.MD_ERR_ARG
+    assert lib.md_step(ctypes.byref(p), fake, need, 4, 2, None, None) == _lib.MD_ERR_ARG
+    assert lib.md_neighbors(ctypes.byref(p), fake, need, fake, fake, 0, None) == _lib.MD_ERR_ARG
+    assert lib.md_check(None, 0, None, None) == _lib.MD_ERR_WORKSPACE
+    assert b"workspace" in lib.md_last_error()
+
+
+def test_status_names():
+    lib = _lib.lib()
+    assert lib.md_status_name(0) == b"MD_OK"
+    assert lib.md_status_name(2) == b"MD_ERR_BOX"
+    assert lib.md_status_name(99) == b"MD_UNKNOWN"
