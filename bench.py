@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--force-reps", type=int, default=200, help="md_forces launches timed for the roofline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device-to-device copy of this size (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -193,6 +195,16 @@ def main():
         },
         "thermo_last": e_th,
     }
+    if args.copy_calibration_mib > 0:
+        # one plain copy of known size: FETCH_SIZE/WRITE_SIZE of this dispatch give the
+        # counter-to-bytes factor for the traffic figures
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = nbytes
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s.state()[0].cpu().numpy(), box, args.cpu_seconds)
     print(json.dumps(out), flush=True)

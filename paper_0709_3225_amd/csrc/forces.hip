@@ -21,7 +21,7 @@ namespace mdlj {
 
 namespace {
 
-constexpr int kTile = 1024;  // staged atoms per LDS pass (16 KiB)
+constexpr int kTile = 1024;  // staged atoms per LDS pass of the neighbour export (16 KiB)
 
 struct Neighbourhood {
     int pref[28];   // exclusive prefix of the 27 cell counts; pref[27] = total
@@ -62,16 +62,80 @@ __device__ __forceinline__ void load_neighbourhood(const SimArgs& a, int c, Neig
 }
 
 // Stage neighbourhood atoms [t0, t0 + tn) into the tile, frame-translated.
+// w carries the user index (ID_IN_W) or |x|^2 in the frame (for the screen).
+// Loads are issued four per lane before their LDS stores, so a wavefront waits
+// on global memory about tn / 256 times instead of tn / 64.
+template <bool ID_IN_W>
 __device__ __forceinline__ void stage_tile(const SimArgs& a, const Neighbourhood& nb, float4* tile,
                                            int t0, int tn) {
-    for (int t = threadIdx.x; t < tn; t += kWave) {
-        const int g = t0 + t;
-        int k = 0;  // largest k with pref[k] <= g
+    constexpr int kBatch = 4;
+    for (int t = threadIdx.x; t < tn; t += kWave * kBatch) {
+        float4 q[kBatch];
+        int kk[kBatch];
 #pragma unroll
-        for (int step = 16; step > 0; step >>= 1)
-            if (k + step < 27 && nb.pref[k + step] <= g) k += step;
-        const float4 q = a.pos0[nb.first[k] + (g - nb.pref[k])];
-        tile[t] = make_float4(q.x - nb.bx[k], q.y - nb.by[k], q.z - nb.bz[k], q.w);
+        for (int u = 0; u < kBatch; ++u) {
+            const int tt = t + u * kWave;
+            const int g = t0 + (tt < tn ? tt : 0);
+            int k = 0;  // largest k with pref[k] <= g
+#pragma unroll
+            for (int step = 16; step > 0; step >>= 1)
+                if (k + step < 27 && nb.pref[k + step] <= g) k += step;
+            kk[u] = k;
+            q[u] = a.pos0[nb.first[k] + (g - nb.pref[k])];
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int tt = t + u * kWave;
+            if (tt < tn) {
+                const int k = kk[u];
+                const float x = q[u].x - nb.bx[k], y = q[u].y - nb.by[k], z = q[u].z - nb.bz[k];
+                tile[tt] = make_float4(x, y, z, ID_IN_W ? q[u].w : x * x + y * y + z * z);
+            }
+        }
+    }
+}
+
+// Force kernel. One wavefront per home cell; lane = (home atom h, slice s)
+// with ns = floor(64 / home atoms) slices, so a cell of 15 atoms keeps 60
+// lanes busy. The staged candidates are screened in spans of up to 128 per
+// lane:
+//  screen : lane (h, s) tests the s-th contiguous chunk of the span with
+//           r^2 - |x_i|^2 = |x_j|^2 - 2 x_i.x_j (three FMAs) against a bound a
+//           little above r_c^2, and shifts each verdict into a 32-bit accept
+//           word (one add-with-carry). Lanes of one slice read the same
+//           candidate, so every LDS read of the screen is a broadcast.
+//  pairs  : every lane walks the set bits of its words, recomputes the exact
+//           displacement, keeps r^2 < r_c^2 with r^2 > 0 (which drops the atom
+//           itself) and accumulates the truncated, shifted LJ force of
+//           section 2.
+// Slice partials are summed in slice order, so the result does not depend on
+// timing.
+constexpr int kWords = 4;              // accept words per lane per span
+constexpr int kSpan = 32 * kWords;     // candidates per lane per span
+constexpr int kMaxSlices = 16;
+constexpr int kTilePad = 48;           // far-away entries after the staged atoms (>= kMaxSlices + 31)
+
+template <bool ENERGY>
+__device__ __forceinline__ void pair_force(const SimArgs& a, const float4 q, float xi, float yi, float zi,
+                                           bool live, float& fx, float& fy, float& fz, float& u_loc,
+                                           float& w_loc) {
+    const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const bool ok = live && (r2 < a.rc2) && (r2 > 0.0f);
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float ir2 = rinv * rinv;
+    const float s2 = a.sig2 * ir2;
+    const float s6 = s2 * s2 * s2;
+    float fr = fmaf(a.eps24 * ir2, s6 * fmaf(2.0f, s6, -1.0f), -a.fc * rinv);
+    fr = ok ? fr : 0.0f;
+    fx = fmaf(fr, dx, fx);
+    fy = fmaf(fr, dy, fy);
+    fz = fmaf(fr, dz, fz);
+    if (ENERGY) {
+        const float r = r2 * rinv;
+        const float u = a.eps4 * s6 * (s6 - 1.0f) - a.uc + (r - a.rc) * a.fc;
+        u_loc += ok ? u : 0.0f;
+        w_loc += fr * r2;
     }
 }
 
@@ -83,8 +147,9 @@ __global__ void __launch_bounds__(kWave) k_forces(SimArgs a, bool from_step) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&a.hdr[HDR_ERROR], DEV_ORDER);
         return;
     }
-    __shared__ float4 tile[kTile];
+    extern __shared__ float4 tile[];  // a.tile_cap + kTilePad entries
     __shared__ Neighbourhood nb;
+    __shared__ float red[5 * kWave];
     const int lane = threadIdx.x;
     const int c = xcd_block_order(blockIdx.x, a.ncells);
     float ox, oy, oz;
@@ -96,57 +161,100 @@ __global__ void __launch_bounds__(kWave) k_forces(SimArgs a, bool from_step) {
     double u_acc = 0.0, w_acc = 0.0, k_acc = 0.0;
     bool bad = false;
     for (int h0 = 0; h0 < n_home; h0 += kWave) {
-        const int h = h0 + lane;
-        const bool act = h < n_home;
+        const int nh = min(kWave, n_home - h0);
+        const int ns = min(kMaxSlices, kWave / nh);
+        const int h = lane % nh, s = lane / nh;
+        const bool act = s < ns;
         float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (act) pi = a.pos0[home_first + h];
+        if (act) pi = a.pos0[home_first + h0 + h];
         const float xi = pi.x - ox, yi = pi.y - oy, zi = pi.z - oz;
-        const int idi = __float_as_int(pi.w);
-        float fx = 0.f, fy = 0.f, fz = 0.f;
-        float u_loc = 0.f, w_loc = 0.f;
-        for (int t0 = 0; t0 < total; t0 += kTile) {
-            const int tn = min(kTile, total - t0);
+        const float ai = fmaf(zi, zi, fmaf(yi, yi, xi * xi));
+        // idle lanes get a bound no candidate can meet (q.w - thr_i = +inf)
+        const float thr_i = act ? a.screen2 - ai : -__builtin_huge_valf();
+        const float mx = -2.0f * xi, my = -2.0f * yi, mz = -2.0f * zi;
+        float fx = 0.f, fy = 0.f, fz = 0.f, u_loc = 0.f, w_loc = 0.f;
+        for (int t0 = 0; t0 < total; t0 += a.tile_cap) {
+            const int tn = min(a.tile_cap, total - t0);
             __syncthreads();
-            stage_tile(a, nb, tile, t0, tn);
+            stage_tile<false>(a, nb, tile, t0, tn);
+            if (lane < kTilePad) tile[tn + lane] = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
             __syncthreads();
-            if (act) {
-                for (int j = 0; j < tn; ++j) {
-                    const float4 q = tile[j];
-                    const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
-                    const float r2 = dx * dx + dy * dy + dz * dz;
-                    if (r2 < a.rc2 && __float_as_int(q.w) != idi) {
-                        const float rinv = rsqrtf(r2);
-                        const float ir2 = rinv * rinv;
-                        const float s2 = a.sig2 * ir2;
-                        const float s6 = s2 * s2 * s2;
-                        const float fr = a.eps24 * ir2 * s6 * (2.0f * s6 - 1.0f) - a.fc * rinv;
-                        fx += fr * dx;
-                        fy += fr * dy;
-                        fz += fr * dz;
-                        if (ENERGY) {
-                            const float r = r2 * rinv;
-                            u_loc += a.eps4 * s6 * (s6 - 1.0f) - a.uc + (r - a.rc) * a.fc;
-                            w_loc += fr * r2;
+            for (int p0 = 0; p0 < tn; p0 += kSpan * ns) {
+                const int pn = min(kSpan * ns, tn - p0);
+                const int chunk = (pn + ns - 1) / ns;  // <= kSpan, uniform
+                const int base = p0 + (act ? s * chunk : 0);
+                const float4* cand = tile + base;
+                uint32_t wd[kWords];
+#pragma unroll
+                for (int w = 0; w < kWords; ++w) {
+                    uint32_t bits = 0;
+                    if (w * 32 < chunk) {
+#pragma unroll 8
+                        for (int k = 0; k < 32; ++k) {
+                            const float4 q = cand[w * 32 + k];
+                            // negative iff accepted; its sign bit is shifted into the word
+                            const float d = fmaf(mx, q.x, fmaf(my, q.y, fmaf(mz, q.z, q.w - thr_i)));
+                            bits = __builtin_amdgcn_alignbit(bits, __float_as_uint(d), 31);
                         }
+                        // drop candidates past this slice's chunk (they belong to the next slice)
+                        const int valid = chunk - w * 32;
+                        if (valid < 32) bits &= ~(0xffffffffu >> valid);
                     }
+                    wd[w] = bits;
+                }
+                // walk the accepted bits: word index w, current word m
+                int w = 0;
+                uint32_t m = wd[0];
+                while (__any(m != 0u || w < kWords - 1)) {
+                    while (m == 0u && w < kWords - 1) {
+                        ++w;
+                        m = (w == 1) ? wd[1] : (w == 2) ? wd[2] : wd[3];
+                    }
+                    const bool live = m != 0u;
+                    const int k = live ? __builtin_clz(m) : 0;
+                    m &= ~(0x80000000u >> k);
+                    // finished lanes re-read their first candidate (always staged)
+                    const float4 q = cand[live ? w * 32 + k : 0];
+                    pair_force<ENERGY>(a, q, xi, yi, zi, live, fx, fy, fz, u_loc, w_loc);
                 }
             }
         }
-        if (act) {
-            const int k = home_first + h;
-            if (!finite3(fx, fy, fz)) bad = true;
-            if (WRITE) a.force[k] = make_float4(fx, fy, fz, 0.f);
+        // sum the slice partials of each home atom in slice order
+        __syncthreads();
+        red[0 * kWave + lane] = fx;
+        red[1 * kWave + lane] = fy;
+        red[2 * kWave + lane] = fz;
+        if (ENERGY) {
+            red[3 * kWave + lane] = u_loc;
+            red[4 * kWave + lane] = w_loc;
+        }
+        __syncthreads();
+        if (s == 0) {
+            float gx = 0.f, gy = 0.f, gz = 0.f, gu = 0.f, gw = 0.f;
+            for (int q = 0; q < ns; ++q) {
+                const int l = h + q * nh;
+                gx += red[0 * kWave + l];
+                gy += red[1 * kWave + l];
+                gz += red[2 * kWave + l];
+                if (ENERGY) {
+                    gu += red[3 * kWave + l];
+                    gw += red[4 * kWave + l];
+                }
+            }
+            const int k = home_first + h0 + h;
+            if (!finite3(gx, gy, gz)) bad = true;
+            if (WRITE) a.force[k] = make_float4(gx, gy, gz, 0.f);
             if (KICK || ENERGY) {
                 float4 v = a.vel0[k];
                 if (KICK) {
-                    v.x += a.hdt_m * fx;
-                    v.y += a.hdt_m * fy;
-                    v.z += a.hdt_m * fz;
+                    v.x += a.hdt_m * gx;
+                    v.y += a.hdt_m * gy;
+                    v.z += a.hdt_m * gz;
                     a.vel0[k] = v;
                 }
                 if (ENERGY) {
-                    u_acc += static_cast<double>(u_loc);
-                    w_acc += static_cast<double>(w_loc);
+                    u_acc += static_cast<double>(gu);
+                    w_acc += static_cast<double>(gw);
                     k_acc += static_cast<double>(a.half_m) * (static_cast<double>(v.x) * v.x +
                                                               static_cast<double>(v.y) * v.y +
                                                               static_cast<double>(v.z) * v.z);
@@ -227,7 +335,7 @@ __global__ void __launch_bounds__(kWave) k_neighbors(SimArgs a, int* counts, int
         for (int t0 = 0; t0 < total; t0 += kTile) {
             const int tn = min(kTile, total - t0);
             __syncthreads();
-            stage_tile(a, nb, tile, t0, tn);
+            stage_tile<true>(a, nb, tile, t0, tn);
             __syncthreads();
             if (act) {
                 for (int j = 0; j < tn; ++j) {
@@ -252,14 +360,15 @@ __global__ void __launch_bounds__(kWave) k_neighbors(SimArgs a, int* counts, int
 hipError_t launch_forces(const SimArgs& a, bool kick, bool energy, bool write_force, bool from_step,
                          hipStream_t st) {
     const dim3 g(a.ncells), b(kWave);
+    const size_t lds = sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
     if (kick && energy && write_force) {
-        hipLaunchKernelGGL((k_forces<true, true, true>), g, b, 0, st, a, from_step);
+        hipLaunchKernelGGL((k_forces<true, true, true>), g, b, lds, st, a, from_step);
     } else if (kick && !energy && write_force) {
-        hipLaunchKernelGGL((k_forces<true, false, true>), g, b, 0, st, a, from_step);
+        hipLaunchKernelGGL((k_forces<true, false, true>), g, b, lds, st, a, from_step);
     } else if (!kick && energy && !write_force) {
-        hipLaunchKernelGGL((k_forces<false, true, false>), g, b, 0, st, a, from_step);
+        hipLaunchKernelGGL((k_forces<false, true, false>), g, b, lds, st, a, from_step);
     } else if (!kick && !energy && write_force) {
-        hipLaunchKernelGGL((k_forces<false, false, true>), g, b, 0, st, a, from_step);
+        hipLaunchKernelGGL((k_forces<false, false, true>), g, b, lds, st, a, from_step);
     } else {
         return hipErrorInvalidValue;
     }

@@ -148,6 +148,14 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     a.eps4 = static_cast<float>(4.0 * eps);
     a.fc = p->shift_mode == 0 ? static_cast<float>(flj_rc) : 0.f;
     a.uc = static_cast<float>(ulj_rc);
+    // Screen bound: frame coordinates lie within [-s, 2s) per axis, so |x|^2 <= 12 s^2;
+    // the FP32 dot-product form of r^2 errs by a few ulp of that. 2^-17 * 12 s^2 leaves a
+    // wide margin, so the screen never drops a pair that the exact test accepts.
+    a.screen2 = static_cast<float>(rc * rc + std::ldexp(12.0 * L.s * L.s, -17));
+    // One LDS pass holds the mean 27-cell neighbourhood plus 30% and a wavefront.
+    const double hood = 27.0 * static_cast<double>(p->n) / L.ncells;
+    int cap = static_cast<int>(std::ceil((1.3 * hood + 64.0) / 64.0)) * 64;
+    a.tile_cap = std::min(2048, std::max(128, cap));
     a.dt = p->dt;
     a.hdt_m = static_cast<float>(0.5 * p->dt / p->mass);
     a.half_m = static_cast<float>(0.5 * p->mass);

@@ -50,6 +50,8 @@ struct SimArgs {
     float eps4;      // 4 epsilon
     float fc;        // f_LJ(r_c) for the force shift, 0 for energy shift
     float uc;        // u_LJ(r_c)
+    float screen2;   // conservative bound on r^2 for the dot-product screen
+    int tile_cap;    // staged atoms per LDS pass of the force kernel
 
     float dt;
     float hdt_m;     // dt / (2 m)
