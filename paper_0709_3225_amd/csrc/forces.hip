@@ -99,11 +99,13 @@ __device__ __forceinline__ void stage_tile(const SimArgs& a, const Neighbourhood
 // with ns = floor(64 / home atoms) slices, so a cell of 15 atoms keeps 60
 // lanes busy. The staged candidates are screened in spans of up to 128 per
 // lane:
-//  screen : lane (h, s) tests the s-th contiguous chunk of the span with
+//  screen : lane (h, s) tests candidates s, s + ns, s + 2 ns, ... (slices
+//           interleave, so every slice samples the whole neighbourhood and
+//           the slices of one atom find similar numbers of partners) with
 //           r^2 - |x_i|^2 = |x_j|^2 - 2 x_i.x_j (three FMAs) against a bound a
-//           little above r_c^2, and shifts each verdict into a 32-bit accept
-//           word (one add-with-carry). Lanes of one slice read the same
-//           candidate, so every LDS read of the screen is a broadcast.
+//           little above r_c^2, and shifts each verdict's sign bit into a
+//           32-bit accept word (one v_alignbit). Lanes of one slice read the
+//           same candidate, so every LDS read of the screen is a broadcast.
 //  pairs  : every lane walks the set bits of its words, recomputes the exact
 //           displacement, keeps r^2 < r_c^2 with r^2 > 0 (which drops the atom
 //           itself) and accumulates the truncated, shifted LJ force of
@@ -111,9 +113,41 @@ __device__ __forceinline__ void stage_tile(const SimArgs& a, const Neighbourhood
 // Slice partials are summed in slice order, so the result does not depend on
 // timing.
 constexpr int kWords = 4;              // accept words per lane per span
-constexpr int kSpan = 32 * kWords;     // candidates per lane per span
+constexpr int kGroups = 32 * kWords;   // candidates per lane per span
 constexpr int kMaxSlices = 16;
-constexpr int kTilePad = 48;           // far-away entries after the staged atoms (>= kMaxSlices + 31)
+constexpr int kScreenUnroll = 4;
+constexpr int kTilePad = kMaxSlices * (kScreenUnroll + 1);  // far-away entries after the staged atoms
+
+// Screen of one span: word w, bit 31 - k holds the verdict on the lane's
+// candidate 32 w + k, i.e. tile entry first + (32 w + k) * ns. groups is the
+// largest candidate count of any slice (uniform); entries past the staged
+// atoms are padding that never passes. NS > 0 fixes the stride at compile
+// time (immediate LDS offsets); NS = 0 takes it from ns.
+template <int NS>
+__device__ __forceinline__ void screen_span(const float4* tile, int first, int ns_rt, int groups, float mx,
+                                            float my, float mz, float thr_i, uint32_t (&wd)[kWords]) {
+    const int ns = NS > 0 ? NS : ns_rt;
+    const float4* cand = tile + first;
+#pragma unroll
+    for (int w = 0; w < kWords; ++w) {
+        uint32_t bits = 0;
+        const int n = min(32, groups - 32 * w);  // uniform
+        if (n > 0) {
+            for (int k0 = 0; k0 < n; k0 += kScreenUnroll) {
+#pragma unroll
+                for (int u = 0; u < kScreenUnroll; ++u) {
+                    const float4 q = cand[(32 * w + k0 + u) * ns];
+                    // negative iff accepted; its sign bit is shifted into the word
+                    const float d = fmaf(mx, q.x, fmaf(my, q.y, fmaf(mz, q.z, q.w - thr_i)));
+                    bits = __builtin_amdgcn_alignbit(bits, __float_as_uint(d), 31);
+                }
+            }
+            const int done = (n + kScreenUnroll - 1) / kScreenUnroll * kScreenUnroll;
+            if (done < 32) bits <<= (32 - done);
+        }
+        wd[w] = bits;
+    }
+}
 
 template <bool ENERGY>
 __device__ __forceinline__ void pair_force(const SimArgs& a, const float4 q, float xi, float yi, float zi,
@@ -136,6 +170,32 @@ __device__ __forceinline__ void pair_force(const SimArgs& a, const float4 q, flo
         const float u = a.eps4 * s6 * (s6 - 1.0f) - a.uc + (r - a.rc) * a.fc;
         u_loc += ok ? u : 0.0f;
         w_loc += fr * r2;
+    }
+}
+
+// Walk the accepted bits of one span and accumulate their forces.
+template <bool ENERGY>
+__device__ __forceinline__ void walk_span(const SimArgs& a, const float4* tile, int first, int ns,
+                                          const uint32_t (&wd)[kWords], float xi, float yi, float zi,
+                                          float& fx, float& fy, float& fz, float& u_loc, float& w_loc) {
+    const char* base = reinterpret_cast<const char*>(tile + first);
+    const uint32_t cstep = static_cast<uint32_t>(ns) * sizeof(float4);  // bytes between candidates
+    uint32_t wbase = 0;                                                  // byte offset of the word's candidate 0
+    int w = 0;
+    uint32_t m = wd[0];
+    while (__any(m != 0u || w < kWords - 1)) {
+        while (m == 0u && w < kWords - 1) {
+            ++w;
+            wbase += 32 * cstep;
+            m = (w == 1) ? wd[1] : (w == 2) ? wd[2] : wd[3];
+        }
+        const bool live = m != 0u;
+        const uint32_t k = live ? __builtin_clz(m) : 0u;
+        m &= ~(0x80000000u >> k);
+        // finished lanes re-read their first candidate (always staged)
+        const uint32_t off = live ? wbase + k * cstep : 0u;
+        const float4 q = *reinterpret_cast<const float4*>(base + off);
+        pair_force<ENERGY>(a, q, xi, yi, zi, live, fx, fy, fz, u_loc, w_loc);
     }
 }
 
@@ -177,46 +237,22 @@ __global__ void __launch_bounds__(kWave) k_forces(SimArgs a, bool from_step) {
             const int tn = min(a.tile_cap, total - t0);
             __syncthreads();
             stage_tile<false>(a, nb, tile, t0, tn);
-            if (lane < kTilePad) tile[tn + lane] = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
+            for (int t = lane; t < kTilePad; t += kWave) tile[tn + t] = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
             __syncthreads();
-            for (int p0 = 0; p0 < tn; p0 += kSpan * ns) {
-                const int pn = min(kSpan * ns, tn - p0);
-                const int chunk = (pn + ns - 1) / ns;  // <= kSpan, uniform
-                const int base = p0 + (act ? s * chunk : 0);
-                const float4* cand = tile + base;
+            const int groups_all = (tn + ns - 1) / ns;  // candidates of the largest slice
+            for (int g0 = 0; g0 < groups_all; g0 += kGroups) {
+                const int groups = min(kGroups, groups_all - g0);
+                const int first = g0 * ns + (act ? s : 0);
                 uint32_t wd[kWords];
-#pragma unroll
-                for (int w = 0; w < kWords; ++w) {
-                    uint32_t bits = 0;
-                    if (w * 32 < chunk) {
-#pragma unroll 8
-                        for (int k = 0; k < 32; ++k) {
-                            const float4 q = cand[w * 32 + k];
-                            // negative iff accepted; its sign bit is shifted into the word
-                            const float d = fmaf(mx, q.x, fmaf(my, q.y, fmaf(mz, q.z, q.w - thr_i)));
-                            bits = __builtin_amdgcn_alignbit(bits, __float_as_uint(d), 31);
-                        }
-                        // drop candidates past this slice's chunk (they belong to the next slice)
-                        const int valid = chunk - w * 32;
-                        if (valid < 32) bits &= ~(0xffffffffu >> valid);
-                    }
-                    wd[w] = bits;
+                switch (ns) {
+                    case 2: screen_span<2>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
+                    case 3: screen_span<3>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
+                    case 4: screen_span<4>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
+                    case 5: screen_span<5>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
+                    case 6: screen_span<6>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
+                    default: screen_span<0>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
                 }
-                // walk the accepted bits: word index w, current word m
-                int w = 0;
-                uint32_t m = wd[0];
-                while (__any(m != 0u || w < kWords - 1)) {
-                    while (m == 0u && w < kWords - 1) {
-                        ++w;
-                        m = (w == 1) ? wd[1] : (w == 2) ? wd[2] : wd[3];
-                    }
-                    const bool live = m != 0u;
-                    const int k = live ? __builtin_clz(m) : 0;
-                    m &= ~(0x80000000u >> k);
-                    // finished lanes re-read their first candidate (always staged)
-                    const float4 q = cand[live ? w * 32 + k : 0];
-                    pair_force<ENERGY>(a, q, xi, yi, zi, live, fx, fy, fz, u_loc, w_loc);
-                }
+                walk_span<ENERGY>(a, tile, first, ns, wd, xi, yi, zi, fx, fy, fz, u_loc, w_loc);
             }
         }
         // sum the slice partials of each home atom in slice order
