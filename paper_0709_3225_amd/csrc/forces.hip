@@ -173,21 +173,24 @@ __device__ __forceinline__ void pair_force(const SimArgs& a, const float4 q, flo
     }
 }
 
-// Walk the accepted bits of one span and accumulate their forces.
+// Walk the accepted bits of one span and accumulate their forces. The words
+// are rotated through four registers (never indexed, which would put them in
+// scratch memory).
 template <bool ENERGY>
 __device__ __forceinline__ void walk_span(const SimArgs& a, const float4* tile, int first, int ns,
-                                          const uint32_t (&wd)[kWords], float xi, float yi, float zi,
-                                          float& fx, float& fy, float& fz, float& u_loc, float& w_loc) {
+                                          uint32_t m, uint32_t n1, uint32_t n2, uint32_t n3, float xi,
+                                          float yi, float zi, float& fx, float& fy, float& fz, float& u_loc,
+                                          float& w_loc) {
     const char* base = reinterpret_cast<const char*>(tile + first);
     const uint32_t cstep = static_cast<uint32_t>(ns) * sizeof(float4);  // bytes between candidates
     uint32_t wbase = 0;                                                  // byte offset of the word's candidate 0
-    int w = 0;
-    uint32_t m = wd[0];
-    while (__any(m != 0u || w < kWords - 1)) {
-        while (m == 0u && w < kWords - 1) {
-            ++w;
-            wbase += 32 * cstep;
-            m = (w == 1) ? wd[1] : (w == 2) ? wd[2] : wd[3];
+    while (__any((m | n1 | n2 | n3) != 0u)) {
+        while (m == 0u && (n1 | n2 | n3) != 0u) {
+            m = n1;
+            n1 = n2;
+            n2 = n3;
+            n3 = 0u;
+            wbase += 32u * cstep;
         }
         const bool live = m != 0u;
         const uint32_t k = live ? __builtin_clz(m) : 0u;
@@ -252,7 +255,8 @@ __global__ void __launch_bounds__(kWave) k_forces(SimArgs a, bool from_step) {
                     case 6: screen_span<6>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
                     default: screen_span<0>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
                 }
-                walk_span<ENERGY>(a, tile, first, ns, wd, xi, yi, zi, fx, fy, fz, u_loc, w_loc);
+                walk_span<ENERGY>(a, tile, first, ns, wd[0], wd[1], wd[2], wd[3], xi, yi, zi, fx, fy, fz, u_loc,
+                                  w_loc);
             }
         }
         // sum the slice partials of each home atom in slice order
