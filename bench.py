@@ -64,6 +64,32 @@ def algorithmic_force_flops(sys_, torch):
     return candidates, accepted, FLOP_PER_CANDIDATE * candidates + FLOP_PER_ACCEPTED * accepted
 
 
+FORCE_SOURCES = ("paper_0709_3225_amd/csrc/forces.hip", "paper_0709_3225_amd/csrc/md_device.h",
+                 "paper_0709_3225_amd/csrc/md_internal.h")
+
+
+def recorded_traffic(workload):
+    """HBM bytes per force-kernel launch from the committed counter summary,
+    or None if the force-kernel sources changed since the counters were taken
+    (or no summary exists for this workload)."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"k_forces_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ":" in line and line.split(":", 1)[0] in ("forces_source_sha256", "traffic_bytes_per_launch"):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in FORCE_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if rec.get("forces_source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in rec:
+        return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(pos4, box, target_s):
     """FP64 oracle: force rows of the same state (each row = all N partners),
     repeated until about target_s seconds; one oracle MD step costs one row
@@ -187,7 +213,8 @@ def main():
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": recorded_traffic(args.workload),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel_us": force_us,
             "flops_per_launch": flops,
             "candidates": candidates,
