@@ -106,9 +106,9 @@ __device__ __forceinline__ void stage_tile(const SimArgs& a, const Neighbourhood
 //           little above r_c^2, and shifts each verdict's sign bit into a
 //           32-bit accept word (one v_alignbit). Lanes of one slice read the
 //           same candidate, so every LDS read of the screen is a broadcast.
-//  pairs  : every lane walks the set bits of its words, recomputes the exact
-//           displacement, keeps r^2 < r_c^2 with r^2 > 0 (which drops the atom
-//           itself) and accumulates the truncated, shifted LJ force of
+//  pairs  : the home atom's own bit is cleared; every lane walks the set bits
+//           of its words, recomputes the exact displacement, keeps
+//           r^2 < r_c^2 and accumulates the truncated, shifted LJ force of
 //           section 2.
 // Slice partials are summed in slice order, so the result does not depend on
 // timing.
@@ -155,7 +155,8 @@ __device__ __forceinline__ void pair_force(const SimArgs& a, const float4 q, flo
                                            float& w_loc) {
     const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-    const bool ok = live && (r2 < a.rc2) && (r2 > 0.0f);
+    // the atom itself never reaches this point (its screen bit is cleared)
+    const bool ok = live && (r2 < a.rc2);
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float ir2 = rinv * rinv;
     const float s2 = a.sig2 * ir2;
@@ -174,8 +175,9 @@ __device__ __forceinline__ void pair_force(const SimArgs& a, const float4 q, flo
 }
 
 // Walk the accepted bits of one span and accumulate their forces. The words
-// are rotated through four registers (never indexed, which would put them in
-// scratch memory).
+// rotate through four registers (never indexed, which would put them in
+// scratch memory); an exhausted word is replaced by the next one without a
+// branch. The loop runs until every lane has spent its bit count.
 template <bool ENERGY>
 __device__ __forceinline__ void walk_span(const SimArgs& a, const float4* tile, int first, int ns,
                                           uint32_t m, uint32_t n1, uint32_t n2, uint32_t n3, float xi,
@@ -183,23 +185,40 @@ __device__ __forceinline__ void walk_span(const SimArgs& a, const float4* tile, 
                                           float& w_loc) {
     const char* base = reinterpret_cast<const char*>(tile + first);
     const uint32_t cstep = static_cast<uint32_t>(ns) * sizeof(float4);  // bytes between candidates
-    uint32_t wbase = 0;                                                  // byte offset of the word's candidate 0
-    while (__any((m | n1 | n2 | n3) != 0u)) {
-        while (m == 0u && (n1 | n2 | n3) != 0u) {
-            m = n1;
-            n1 = n2;
-            n2 = n3;
-            n3 = 0u;
-            wbase += 32u * cstep;
-        }
+    const uint32_t wstep = 32u * cstep;                                  // bytes between words
+    uint32_t wb = 0;                                                     // byte offset of the word's candidate 0
+    uint32_t left = __builtin_popcount(m) + __builtin_popcount(n1) + __builtin_popcount(n2) +
+                    __builtin_popcount(n3);
+    if (!__any(left != 0u)) return;
+    do {
+        const bool next = (m == 0u);
+        m = next ? n1 : m;
+        n1 = next ? n2 : n1;
+        n2 = next ? n3 : n2;
+        n3 = next ? 0u : n3;
+        wb = next ? wb + wstep : wb;
         const bool live = m != 0u;
         const uint32_t k = live ? __builtin_clz(m) : 0u;
         m &= ~(0x80000000u >> k);
-        // finished lanes re-read their first candidate (always staged)
-        const uint32_t off = live ? wbase + k * cstep : 0u;
-        const float4 q = *reinterpret_cast<const float4*>(base + off);
+        left -= live ? 1u : 0u;
+        const float4 q = *reinterpret_cast<const float4*>(base + wb + k * cstep);
         pair_force<ENERGY>(a, q, xi, yi, zi, live, fx, fy, fz, u_loc, w_loc);
-    }
+    } while (__any(left != 0u));
+}
+
+// Clear the screen bit of the home atom itself (tile index self_t) if it lies
+// in this lane's span: span candidates are first + g * ns for g < groups.
+__device__ __forceinline__ void clear_self(int self_t, int first, int ns, int groups, uint32_t (&wd)[kWords]) {
+    const int off = self_t - first;
+    if (off < 0 || off % ns != 0) return;
+    const int g = off / ns;
+    if (g >= groups) return;
+    const uint32_t bit = 0x80000000u >> (g & 31);
+    const int w = g >> 5;
+    wd[0] &= (w == 0) ? ~bit : ~0u;
+    wd[1] &= (w == 1) ? ~bit : ~0u;
+    wd[2] &= (w == 2) ? ~bit : ~0u;
+    wd[3] &= (w == 3) ? ~bit : ~0u;
 }
 
 template <bool KICK, bool ENERGY, bool WRITE>
@@ -243,6 +262,7 @@ __global__ void __launch_bounds__(kWave) k_forces(SimArgs a, bool from_step) {
             for (int t = lane; t < kTilePad; t += kWave) tile[tn + t] = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
             __syncthreads();
             const int groups_all = (tn + ns - 1) / ns;  // candidates of the largest slice
+            const int self_t = nb.pref[13] + h0 + h - t0;  // the home atom's own tile index (may be outside)
             for (int g0 = 0; g0 < groups_all; g0 += kGroups) {
                 const int groups = min(kGroups, groups_all - g0);
                 const int first = g0 * ns + (act ? s : 0);
@@ -255,6 +275,7 @@ __global__ void __launch_bounds__(kWave) k_forces(SimArgs a, bool from_step) {
                     case 6: screen_span<6>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
                     default: screen_span<0>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
                 }
+                if (act) clear_self(self_t, first, ns, groups, wd);
                 walk_span<ENERGY>(a, tile, first, ns, wd[0], wd[1], wd[2], wd[3], xi, yi, zi, fx, fy, fz, u_loc,
                                   w_loc);
             }
