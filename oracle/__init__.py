@@ -72,6 +72,12 @@ def _load():
         lib.oracle_neighbors.restype = i64
         lib.oracle_run.argtypes = [P, i64, dp, dp, ctypes.c_int32, dp]
         lib.oracle_run.restype = ctypes.c_int
+        lib.oracle_hvp.argtypes = [P, i64, dp, dp, dp]
+        lib.oracle_hvp.restype = ctypes.c_int
+        lib.oracle_dforce_dparams.argtypes = [P, i64, dp, dp, dp]
+        lib.oracle_dforce_dparams.restype = ctypes.c_int
+        lib.oracle_virial_grad.argtypes = [P, i64, dp, dp, dp]
+        lib.oracle_virial_grad.restype = ctypes.c_int
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -168,3 +174,33 @@ def run(p: OracleParams, pos, vel, nsteps: int):
     if rc != 0:
         raise ValueError(f"oracle_run failed ({rc})")
     return x, v, th
+
+
+def hvp(p: OracleParams, pos, u):
+    """J u, J = dF/dr of the force sum (force-shift mode)."""
+    x = _xyz(pos)
+    uu = _xyz(u)
+    out = np.zeros_like(x)
+    if _load().oracle_hvp(ctypes.byref(p), x.shape[0], _dp(x), _dp(uu), _dp(out)) != 0:
+        raise ValueError("oracle_hvp needs shift_mode 0 and L >= 2 r_c")
+    return out
+
+
+def dforce_dparams(p: OracleParams, pos, a):
+    """(sum_i a_i . dF_i/d eps, sum_i a_i . dF_i/d sigma), r_c = 2.5 sigma."""
+    x = _xyz(pos)
+    aa = _xyz(a)
+    out = np.zeros(2)
+    if _load().oracle_dforce_dparams(ctypes.byref(p), x.shape[0], _dp(x), _dp(aa), _dp(out)) != 0:
+        raise ValueError("oracle_dforce_dparams needs shift_mode 0 and L >= 2 r_c")
+    return float(out[0]), float(out[1])
+
+
+def virial_grad(p: OracleParams, pos):
+    """(dW/dr [N,3], dW/d eps, dW/d sigma)."""
+    x = _xyz(pos)
+    g = np.zeros_like(x)
+    dw = np.zeros(2)
+    if _load().oracle_virial_grad(ctypes.byref(p), x.shape[0], _dp(x), _dp(g), _dp(dw)) != 0:
+        raise ValueError("oracle_virial_grad needs shift_mode 0 and L >= 2 r_c")
+    return g, float(dw[0]), float(dw[1])

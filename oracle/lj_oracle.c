@@ -38,9 +38,19 @@
  *   - Velocity Verlet is kick(dt/2) - drift(dt) - wrap into [0, L) - force -
  *     kick(dt/2).
  *
+ * Derivatives for the adjoint (force-shift mode only; with the energy shift
+ * the truncated force jumps at r_c and has no derivative there):
+ *   - oracle_hvp: the Jacobian of the force sum applied to a vector,
+ *     (J u)_i = sum_j [g (u_i - u_j) + B d (d . (u_i - u_j))], g = phi/r,
+ *     B = (phi' - g)/r^2, d = r_i - r_j (minimum image);
+ *   - oracle_dforce_dparams: sum_i a_i . dF_i/d(eps) and sum_i a_i . dF_i/d(sigma),
+ *     with r_c = 2.5 sigma moving with sigma (no boundary term since phi(r_c) = 0);
+ *   - oracle_virial_grad: the gradient of W with respect to the positions and
+ *     dW/d(eps), dW/d(sigma).
+ *
  * Parity status: every function below is pinned by CPU tests against closed
  * forms, textbook lattice sums, finite differences, invariances and brute
- * force on tiny inputs (tests/test_oracle.py).
+ * force on tiny inputs (tests/test_oracle.py, tests/test_oracle_adjoint.py).
  */
 #include <math.h>
 #include <stdint.h>
@@ -270,4 +280,109 @@ int oracle_run(const oracle_params* p, int64_t n, double* pos, double* vel, int3
     }
     free(f);
     return rc;
+}
+
+/* phi'(r) = f_LJ'(r) = (24 eps / r^2) [-26 (sigma/r)^12 + 7 (sigma/r)^6]; the shift is constant in r. */
+static double dphi_dr(const oracle_params* p, double r) {
+    double sr = p->sigma / r;
+    double sr6 = sr * sr * sr * sr * sr * sr;
+    return 24.0 * p->epsilon / (r * r) * (-26.0 * sr6 * sr6 + 7.0 * sr6);
+}
+
+/* d phi / d sigma at fixed r, with r_c = rc_over_sigma * sigma moving along:
+ * d f_LJ(r)/d sigma = (24 eps / (r sigma)) [24 (sigma/r)^12 - 6 (sigma/r)^6],
+ * and f_LJ(r_c(sigma); sigma) is proportional to eps / sigma, so its total
+ * derivative is -f_LJ(r_c)/sigma. */
+static double dphi_dsigma(const oracle_params* p, double r) {
+    double sr = p->sigma / r;
+    double sr6 = sr * sr * sr * sr * sr * sr;
+    double d = 24.0 * p->epsilon / (r * p->sigma) * (24.0 * sr6 * sr6 - 6.0 * sr6);
+    if (p->shift_mode == 0) d += f_lj(p, p->rc) / p->sigma;
+    return d;
+}
+
+/* out = J u with J = dF/dr (force-shift mode). u, out: n x 3. */
+int oracle_hvp(const oracle_params* p, int64_t n, const double* pos, const double* u, double* out) {
+    if (p->shift_mode != 0 || !(p->box >= 2.0 * p->rc)) return -1;
+    const double rc2 = p->rc * p->rc;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3];
+            min_image(p, pos + 3 * i, pos + 3 * j, d);
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (!(r2 < rc2)) continue;
+            double r = sqrt(r2);
+            double phi, uu;
+            pair_terms(p, r, &phi, &uu);
+            double g = phi / r;
+            double B = (dphi_dr(p, r) - g) / r2;
+            double du[3], dd = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                du[c] = u[3 * i + c] - u[3 * j + c];
+                dd += d[c] * du[c];
+            }
+            for (int c = 0; c < 3; ++c) acc[c] += g * du[c] + B * d[c] * dd;
+        }
+        for (int c = 0; c < 3; ++c) out[3 * i + c] = acc[c];
+    }
+    return 0;
+}
+
+/* out2[0] = sum_i a_i . dF_i/d eps, out2[1] = sum_i a_i . dF_i/d sigma. */
+int oracle_dforce_dparams(const oracle_params* p, int64_t n, const double* pos, const double* a, double* out2) {
+    if (p->shift_mode != 0 || !(p->box >= 2.0 * p->rc)) return -1;
+    const double rc2 = p->rc * p->rc;
+    double se = 0.0, ss = 0.0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : se, ss)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3];
+            min_image(p, pos + 3 * i, pos + 3 * j, d);
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (!(r2 < rc2)) continue;
+            double r = sqrt(r2);
+            double phi, uu;
+            pair_terms(p, r, &phi, &uu);
+            double da = d[0] * a[3 * i] + d[1] * a[3 * i + 1] + d[2] * a[3 * i + 2];
+            se += phi / p->epsilon / r * da; /* phi is linear in eps, shift included */
+            ss += dphi_dsigma(p, r) / r * da;
+        }
+    }
+    out2[0] = se;
+    out2[1] = ss;
+    return 0;
+}
+
+/* grad: n x 3 gradient of W = sum over pairs r phi(r); dw2 = {dW/d eps, dW/d sigma}. */
+int oracle_virial_grad(const oracle_params* p, int64_t n, const double* pos, double* grad, double* dw2) {
+    if (p->shift_mode != 0 || !(p->box >= 2.0 * p->rc)) return -1;
+    const double rc2 = p->rc * p->rc;
+    double we = 0.0, ws = 0.0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : we, ws)
+    for (int64_t i = 0; i < n; ++i) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3];
+            min_image(p, pos + 3 * i, pos + 3 * j, d);
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (!(r2 < rc2)) continue;
+            double r = sqrt(r2);
+            double phi, uu;
+            pair_terms(p, r, &phi, &uu);
+            /* d(r phi)/dr = phi + r phi', along the unit vector d/r */
+            double s = (phi + r * dphi_dr(p, r)) / r;
+            for (int c = 0; c < 3; ++c) acc[c] += s * d[c];
+            we += 0.5 * r * phi / p->epsilon;
+            ws += 0.5 * r * dphi_dsigma(p, r);
+        }
+        for (int c = 0; c < 3; ++c) grad[3 * i + c] = acc[c];
+    }
+    dw2[0] = we;
+    dw2[1] = ws;
+    return 0;
 }
