@@ -40,7 +40,43 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this size (HBM counter calibration)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint throughput leg")
     return ap.parse_args()
+
+
+def adjoint_leg(torch):
+    """Forward + backward of L = K_T/N + W_T/(3V) through 200 Verlet steps at
+    N = 32000 (checkpoints every 20 steps), against plain md_step at the same
+    size. Both in atom-steps/s (N x 200 / time)."""
+    import ljsynth
+    from paper_0709_3225_amd import LJSystem, trajectory_gradients
+
+    w = ljsynth.WORKLOADS["lj32k_adjoint"]
+    pos4, vel4, box = ljsynth.make_state(w)
+    x, v = torch.from_numpy(pos4).cuda(), torch.from_numpy(vel4).cuda()
+    trajectory_gradients(x, v, box, nsteps=20, every=20)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss, gr, gv, ge, gs = trajectory_gradients(x, v, box, nsteps=w.steps, every=20)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    s = LJSystem(w.n, box, dt=w.dt)
+    s.load(x, v)
+    s.step(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(w.steps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    s.check()
+    adj = w.n * w.steps / t_adj
+    plain = w.n * w.steps / t_plain
+    return {
+        "workload": f"{w.name}: N={w.n}, rho={w.density}, T*={w.temperature}, {w.steps} steps, checkpoints every 20, "
+                    "loss K_T/N + W_T/(3V), gradients w.r.t. r0, v0, eps, sigma",
+        "value": adj, "unit": "atom-steps/s (forward + backward)", "plain_value": plain,
+        "ratio_vs_plain": adj / plain, "loss": loss, "dL_deps": ge, "dL_dsigma": gs,
+    }
 
 
 def algorithmic_force_flops(sys_, torch):
@@ -232,6 +268,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = nbytes
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s.state()[0].cpu().numpy(), box, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -165,6 +165,44 @@ md_status md_cell_lists(const md_params* p, const void* ws, size_t ws_bytes,
                         int32_t* cell_start_dev, int32_t* order_dev, hipStream_t stream);
 
 /*
+ * ---- Adjoint (differentiation through velocity Verlet) ----
+ * These entry points build the discrete adjoint of md_step: with
+ * h = dt / (2 m), one Verlet step is v' = v + h F(r), r' = r + dt v',
+ * v'' = v' + h F(r'), so its transpose is a kick adjoint at r' (lam_r += h J
+ * lam_v), a drift adjoint (lam_v += dt lam_r) and a kick adjoint at r. J is
+ * the Jacobian of the force sum (section 2, force-sum equation with the
+ * truncated, force-shifted f(r)); it is symmetric. Force-shift mode only
+ * (shift_mode 0): the energy-shift variant has a force jump at r_c and no
+ * derivative there (MD_ERR_ARG). Vectors are float4 [n] in user order.
+ */
+
+/*
+ * Kick adjoint at the current workspace positions (md_build_cells first):
+ *   lam_r4_dev += coef * J w,
+ *   theta_dev[0] += coef * sum_i w_i . dF_i/d(epsilon),
+ *   theta_dev[1] += coef * sum_i w_i . dF_i/d(sigma)   (r_c = rc_over_sigma * sigma
+ *   moves with sigma). theta_dev: 2 device doubles, nullable; FP64 sums in a
+ * fixed order. w4_dev and lam_r4_dev must not alias.
+ */
+md_status md_adjoint_kick(const md_params* p, void* ws, size_t ws_bytes, const float* w4_dev,
+                          float* lam_r4_dev, double* theta_dev, float coef, hipStream_t stream);
+
+/* Drift adjoint: lam_v4_dev += dt * lam_r4_dev (n float4 each; no workspace). */
+md_status md_adjoint_drift(const md_params* p, const float* lam_r4_dev, float* lam_v4_dev,
+                           hipStream_t stream);
+
+/*
+ * Gradient of the loss k_coef * K + w_coef * W at the current workspace
+ * state (K = m/2 sum v^2, W = sum over pairs r phi(r)):
+ *   g_r4_dev = w_coef * dW/dr, g_v4_dev = k_coef * m * v (both written),
+ *   theta_dev[0] += w_coef * dW/d(epsilon), theta_dev[1] += w_coef * dW/d(sigma)
+ * (theta_dev nullable). The mean kinetic energy plus the virial pressure,
+ * K/N + W/(3V), is k_coef = 1/N, w_coef = 1/(3 L^3).
+ */
+md_status md_loss_grad(const md_params* p, void* ws, size_t ws_bytes, float k_coef, float w_coef,
+                       float* g_r4_dev, float* g_v4_dev, double* theta_dev, hipStream_t stream);
+
+/*
  * Synchronise `stream`, then read and clear the device error word.
  * flags_out (host pointer, nullable) receives the MD_DEV_* bits.
  * Returns MD_ERR_DEVICE if any bit was set, MD_ERR_HIP on a runtime error.

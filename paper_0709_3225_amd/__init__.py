@@ -22,5 +22,6 @@ from ._lib import (  # noqa: F401
     md_workspace_bytes,
 )
 from .system import LJSystem  # noqa: F401
+from .adjoint import LJTrajectory, trajectory_gradients  # noqa: F401
 
 lib()

@@ -35,6 +35,9 @@ SYMBOLS = (
     "md_get_state",
     "md_neighbors",
     "md_cell_lists",
+    "md_adjoint_kick",
+    "md_adjoint_drift",
+    "md_loss_grad",
     "md_check",
     "md_last_error",
     "md_status_name",
@@ -93,8 +96,12 @@ def lib():
         L.md_neighbors.argtypes = [P, vp, sz, vp, vp, i32, vp]
         L.md_cell_lists.argtypes = [P, vp, sz, vp, vp, vp]
         L.md_check.argtypes = [vp, sz, vp, ctypes.POINTER(i32)]
+        L.md_adjoint_kick.argtypes = [P, vp, sz, vp, vp, vp, ctypes.c_float, vp]
+        L.md_adjoint_drift.argtypes = [P, vp, vp, vp]
+        L.md_loss_grad.argtypes = [P, vp, sz, ctypes.c_float, ctypes.c_float, vp, vp, vp, vp]
         for name in ("md_cell_grid", "md_build_cells", "md_forces", "md_step", "md_energy_virial",
-                     "md_get_state", "md_neighbors", "md_cell_lists", "md_check"):
+                     "md_get_state", "md_neighbors", "md_cell_lists", "md_check", "md_adjoint_kick",
+                     "md_adjoint_drift", "md_loss_grad"):
             getattr(L, name).restype = ctypes.c_int
         L.md_last_error.argtypes = []
         L.md_last_error.restype = ctypes.c_char_p
@@ -234,3 +241,31 @@ def md_check(ws, stream=None, raise_on_error: bool = True) -> int:
         return flags.value
     _check(code)
     return flags.value
+
+
+def md_adjoint_kick(p: MDParams, ws, w4, lam_r4, theta=None, coef: float = 1.0, stream=None):
+    """lam_r4 += coef * J w4 at the workspace positions; theta[0..1] += coef * w.dF/d(eps, sigma)."""
+    import torch
+
+    wp, wn = _ws(ws)
+    _check(lib().md_adjoint_kick(ctypes.byref(p), wp, wn, _ptr(w4, "w4", torch.float32, (p.n, 4)),
+                                 _ptr(lam_r4, "lam_r4", torch.float32, (p.n, 4)),
+                                 _ptr(theta, "theta", torch.float64, (2,)), float(coef), _stream(stream)))
+
+
+def md_adjoint_drift(p: MDParams, lam_r4, lam_v4, stream=None):
+    """lam_v4 += dt * lam_r4."""
+    import torch
+
+    _check(lib().md_adjoint_drift(ctypes.byref(p), _ptr(lam_r4, "lam_r4", torch.float32, (p.n, 4)),
+                                  _ptr(lam_v4, "lam_v4", torch.float32, (p.n, 4)), _stream(stream)))
+
+
+def md_loss_grad(p: MDParams, ws, k_coef: float, w_coef: float, g_r4, g_v4, theta=None, stream=None):
+    """g_r4 = w_coef dW/dr, g_v4 = k_coef m v; theta += w_coef dW/d(eps, sigma)."""
+    import torch
+
+    wp, wn = _ws(ws)
+    _check(lib().md_loss_grad(ctypes.byref(p), wp, wn, float(k_coef), float(w_coef),
+                              _ptr(g_r4, "g_r4", torch.float32, (p.n, 4)), _ptr(g_v4, "g_v4", torch.float32, (p.n, 4)),
+                              _ptr(theta, "theta", torch.float64, (2,)), _stream(stream)))

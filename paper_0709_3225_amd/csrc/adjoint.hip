@@ -1,0 +1,301 @@
+// Adjoint of the velocity-Verlet LJ trajectory: Hessian-vector products of
+// the force sum, parameter derivatives and the virial gradient.
+//
+// The force on particle i (section 2, force-sum equation with the truncated,
+// force-shifted f(r)) is F_i = sum_j g(r) d, g = phi/r, d = r_i - r_j. Its
+// Jacobian applied to a vector w is
+//   (J w)_i = sum_j [ g (w_i - w_j) + B d (d . (w_i - w_j)) ],
+//   B = (phi' - g) / r^2,  phi' = (24 eps / r^2) (7 (sigma/r)^6 - 26 (sigma/r)^12);
+// the shift constant drops out of phi' but not out of g. With r_c = 2.5 sigma,
+//   d phi / d eps = phi / eps,
+//   d phi / d sigma = (24 eps / (r sigma)) (24 (sigma/r)^12 - 6 (sigma/r)^6) + f_LJ(r_c) / sigma,
+// and no boundary term appears because phi(r_c) = 0. The energy-shift mode has
+// a force jump at r_c and is not differentiable; the entry points refuse it.
+//
+// The kernels reuse the force kernel's cell-pair machinery (neighbourhood
+// staging in the home cell's frame, screen, bit walk); the adjoint vector is
+// staged in a second LDS tile next to the positions.
+#include "cell_pairs.h"
+
+namespace mdlj {
+
+namespace {
+
+enum { OP_ADJ = 0, OP_VGRAD = 1 };
+
+// One pair of the Hessian-vector product, plus the force (for d/d eps) and the
+// sigma derivative projected on w_i.
+struct AdjOp {
+    const SimArgs& a;
+    const char* base;   // position tile at the lane's span start
+    const char* wbase;  // adjoint-vector tile at the lane's span start
+    float xi, yi, zi, wx, wy, wz;
+    float jx = 0.f, jy = 0.f, jz = 0.f, fx = 0.f, fy = 0.f, fz = 0.f, sg = 0.f;
+    float inv_sig;
+    __device__ __forceinline__ void operator()(uint32_t off, bool live) {
+        const float4 q = *reinterpret_cast<const float4*>(base + off);
+        const float4 wj = *reinterpret_cast<const float4*>(wbase + off);
+        const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        const bool ok = live && (r2 < a.rc2);
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        const float ir2 = rinv * rinv;
+        const float s2 = a.sig2 * ir2;
+        const float s6 = s2 * s2 * s2;
+        const float s12 = s6 * s6;
+        const float e_ir2 = a.eps24 * ir2;
+        float g = fmaf(e_ir2, fmaf(2.0f, s12, -s6), -a.fc * rinv);            // phi / r
+        const float phip = e_ir2 * fmaf(7.0f, s6, -26.0f * s12);                 // phi'
+        float bb = (phip - g) * ir2;                                             // (phi' - g) / r^2
+        float dps = fmaf(e_ir2 * inv_sig, fmaf(24.0f, s12, -6.0f * s6), a.fc * inv_sig * rinv);  // (dphi/dsigma)/r
+        g = ok ? g : 0.f;
+        bb = ok ? bb : 0.f;
+        dps = ok ? dps : 0.f;
+        const float ux = wx - wj.x, uy = wy - wj.y, uz = wz - wj.z;
+        const float dd = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
+        const float t = bb * dd;
+        jx = fmaf(g, ux, fmaf(t, dx, jx));
+        jy = fmaf(g, uy, fmaf(t, dy, jy));
+        jz = fmaf(g, uz, fmaf(t, dz, jz));
+        fx = fmaf(g, dx, fx);
+        fy = fmaf(g, dy, fy);
+        fz = fmaf(g, dz, fz);
+        sg = fmaf(dps, fmaf(dz, wz, fmaf(dy, wy, dx * wx)), sg);
+    }
+};
+
+// One pair of the virial gradient: grad_i W = sum_j (phi + r phi') d / r,
+// plus W and r dphi/dsigma for the parameter derivatives.
+struct VGradOp {
+    const SimArgs& a;
+    const char* base;
+    float xi, yi, zi;
+    float gx = 0.f, gy = 0.f, gz = 0.f, wsum = 0.f, wsig = 0.f;
+    float inv_sig;
+    __device__ __forceinline__ void operator()(uint32_t off, bool live) {
+        const float4 q = *reinterpret_cast<const float4*>(base + off);
+        const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        const bool ok = live && (r2 < a.rc2);
+        const float rinv = __builtin_amdgcn_rsqf(r2);
+        const float ir2 = rinv * rinv;
+        const float s2 = a.sig2 * ir2;
+        const float s6 = s2 * s2 * s2;
+        const float s12 = s6 * s6;
+        const float e_ir2 = a.eps24 * ir2;
+        const float g = fmaf(e_ir2, fmaf(2.0f, s12, -s6), -a.fc * rinv);  // phi / r
+        const float phip = e_ir2 * fmaf(7.0f, s6, -26.0f * s12);
+        const float dps = fmaf(e_ir2 * inv_sig, fmaf(24.0f, s12, -6.0f * s6), a.fc * inv_sig * rinv);
+        const float sc = ok ? g + phip : 0.f;  // (phi + r phi') / r
+        gx = fmaf(sc, dx, gx);
+        gy = fmaf(sc, dy, gy);
+        gz = fmaf(sc, dz, gz);
+        wsum += ok ? g * r2 : 0.f;     // r phi
+        wsig += ok ? dps * r2 : 0.f;   // r dphi/dsigma
+    }
+};
+
+template <int OP>
+__global__ void __launch_bounds__(kWave)
+    k_pair_pass(SimArgs a, const float4* __restrict__ wvec, float4* __restrict__ out_r, float4* __restrict__ out_v,
+                float coef, float kcoef) {
+    if (!state_ok(a, false)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&a.hdr[HDR_ERROR], DEV_ORDER);
+        return;
+    }
+    constexpr bool ADJ = (OP == OP_ADJ);
+    extern __shared__ float4 tile[];  // positions, then (ADJ) the adjoint vector: 2 x (tile_cap + kTilePad)
+    __shared__ Neighbourhood nb;
+    __shared__ float red[7 * kWave];
+    float4* wtile = tile + (a.tile_cap + kTilePad);
+    const int lane = threadIdx.x;
+    const int c = xcd_block_order(blockIdx.x, a.ncells);
+    float ox, oy, oz;
+    load_neighbourhood(a, c, nb, ox, oy, oz);
+    const int total = nb.pref[27];
+    const int home_first = nb.first[13];
+    const int n_home = nb.pref[14] - nb.pref[13];
+    const float inv_sig = 1.0f / sqrtf(a.sig2);
+    const float inv_eps = 24.0f / a.eps24;
+
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int h0 = 0; h0 < n_home; h0 += kWave) {
+        const int nh = min(kWave, n_home - h0);
+        const int ns = min(kMaxSlices, kWave / nh);
+        const int h = lane % nh, s = lane / nh;
+        const bool act = s < ns;
+        float4 pi = make_float4(0.f, 0.f, 0.f, 0.f), wi = pi;
+        if (act) {
+            pi = a.pos0[home_first + h0 + h];
+            if (ADJ) wi = wvec[home_first + h0 + h];
+        }
+        const float xi = pi.x - ox, yi = pi.y - oy, zi = pi.z - oz;
+        const float ai = fmaf(zi, zi, fmaf(yi, yi, xi * xi));
+        const float thr_i = act ? a.screen2 - ai : -__builtin_huge_valf();
+        const float mx = -2.0f * xi, my = -2.0f * yi, mz = -2.0f * zi;
+        float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f;
+        for (int t0 = 0; t0 < total; t0 += a.tile_cap) {
+            const int tn = min(a.tile_cap, total - t0);
+            __syncthreads();
+            stage_tile<false, ADJ>(a, nb, tile, t0, tn, wvec, wtile);
+            for (int t = lane; t < kTilePad; t += kWave) {
+                tile[tn + t] = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
+                if (ADJ) wtile[tn + t] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            __syncthreads();
+            const int groups_all = (tn + ns - 1) / ns;
+            const int self_t = nb.pref[13] + h0 + h - t0;
+            for (int g0 = 0; g0 < groups_all; g0 += kGroups) {
+                const int groups = min(kGroups, groups_all - g0);
+                const int first = g0 * ns + (act ? s : 0);
+                uint32_t wd[kWords];
+                screen_span<0>(tile, first, ns, groups, mx, my, mz, thr_i, wd);
+                if (act) clear_self(self_t, first, ns, groups, wd);
+                if (ADJ) {
+                    AdjOp op{a, reinterpret_cast<const char*>(tile + first), reinterpret_cast<const char*>(wtile + first),
+                             xi, yi, zi, wi.x, wi.y, wi.z};
+                    op.inv_sig = inv_sig;
+                    op.jx = v0; op.jy = v1; op.jz = v2; op.fx = v3; op.fy = v4; op.fz = v5; op.sg = v6;
+                    walk_bits(ns, wd[0], wd[1], wd[2], wd[3], op);
+                    v0 = op.jx; v1 = op.jy; v2 = op.jz; v3 = op.fx; v4 = op.fy; v5 = op.fz; v6 = op.sg;
+                } else {
+                    VGradOp op{a, reinterpret_cast<const char*>(tile + first), xi, yi, zi};
+                    op.inv_sig = inv_sig;
+                    op.gx = v0; op.gy = v1; op.gz = v2; op.wsum = v3; op.wsig = v4;
+                    walk_bits(ns, wd[0], wd[1], wd[2], wd[3], op);
+                    v0 = op.gx; v1 = op.gy; v2 = op.gz; v3 = op.wsum; v4 = op.wsig;
+                }
+            }
+        }
+        // slice partials of each home atom, summed in slice order
+        __syncthreads();
+        red[0 * kWave + lane] = v0;
+        red[1 * kWave + lane] = v1;
+        red[2 * kWave + lane] = v2;
+        red[3 * kWave + lane] = v3;
+        red[4 * kWave + lane] = v4;
+        if (ADJ) {
+            red[5 * kWave + lane] = v5;
+            red[6 * kWave + lane] = v6;
+        }
+        __syncthreads();
+        if (s == 0) {
+            float r[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            for (int q = 0; q < ns; ++q) {
+                const int l = h + q * nh;
+#pragma unroll
+                for (int k = 0; k < 7; ++k)
+                    if (ADJ || k < 5) r[k] += red[k * kWave + l];
+            }
+            const int slot = home_first + h0 + h;
+            const int id = __float_as_int(pi.w);
+            if (ADJ) {
+                float4 o = out_r[id];
+                o.x = fmaf(coef, r[0], o.x);
+                o.y = fmaf(coef, r[1], o.y);
+                o.z = fmaf(coef, r[2], o.z);
+                o.w = 0.f;
+                out_r[id] = o;
+                // w_i . dF_i/d eps = w_i . F_i / eps ; w_i . dF_i/d sigma
+                acc0 += static_cast<double>(inv_eps) *
+                        (static_cast<double>(wi.x) * r[3] + static_cast<double>(wi.y) * r[4] +
+                         static_cast<double>(wi.z) * r[5]);
+                acc1 += static_cast<double>(r[6]);
+            } else {
+                out_r[id] = make_float4(coef * r[0], coef * r[1], coef * r[2], 0.f);
+                const float4 v = a.vel0[slot];
+                const float km = kcoef * 2.0f * a.half_m;
+                out_v[id] = make_float4(km * v.x, km * v.y, km * v.z, 0.f);
+                // W = 1/2 sum over ordered pairs of r phi, dW/d eps = W / eps
+                acc0 += 0.5 * static_cast<double>(inv_eps) * static_cast<double>(r[3]);
+                acc1 += 0.5 * static_cast<double>(r[4]);
+            }
+        }
+    }
+    acc0 = wave_sum(acc0);
+    acc1 = wave_sum(acc1);
+    if (lane == 0) {
+        a.epart[3 * blockIdx.x + 0] = acc0;
+        a.epart[3 * blockIdx.x + 1] = acc1;
+    }
+}
+
+// theta[0..1] += coef * (fixed-order sums of the per-block partials).
+constexpr int kRedBlock = 256;
+__global__ void __launch_bounds__(kRedBlock) k_theta_final(SimArgs a, double* theta, double coef) {
+    if (!state_ok(a, false)) return;
+    __shared__ double s0[kRedBlock], s1[kRedBlock];
+    const int t = threadIdx.x;
+    double x0 = 0.0, x1 = 0.0;
+    for (int b = t; b < a.ncells; b += kRedBlock) {
+        x0 += a.epart[3 * b + 0];
+        x1 += a.epart[3 * b + 1];
+    }
+    s0[t] = x0;
+    s1[t] = x1;
+    __syncthreads();
+    for (int off = kRedBlock / 2; off > 0; off >>= 1) {
+        if (t < off) {
+            s0[t] += s0[t + off];
+            s1[t] += s1[t + off];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        theta[0] += coef * s0[0];
+        theta[1] += coef * s1[0];
+    }
+}
+
+// w (user order) -> sorted order, into the staging velocity array.
+__global__ void __launch_bounds__(256) k_gather_vec(SimArgs a, const float4* __restrict__ w_user) {
+    if (!state_ok(a, false)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&a.hdr[HDR_ERROR], DEV_ORDER);
+        return;
+    }
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= a.n) return;
+    const int id = __float_as_int(a.pos0[k].w);
+    a.vel1[k] = (id >= 0 && id < a.n) ? w_user[id] : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Adjoint of the drift r += dt v: lam_v += dt lam_r (user order).
+__global__ void __launch_bounds__(256) k_adjoint_drift(int n, float dt, const float4* __restrict__ lam_r,
+                                                       float4* __restrict__ lam_v) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float4 r = lam_r[i];
+    float4 v = lam_v[i];
+    v.x = fmaf(dt, r.x, v.x);
+    v.y = fmaf(dt, r.y, v.y);
+    v.z = fmaf(dt, r.z, v.z);
+    lam_v[i] = v;
+}
+
+}  // namespace
+
+hipError_t launch_adjoint_kick(const SimArgs& a, const float4* w_user, float4* lam_r, double* theta, float coef,
+                               hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_vec, dim3((a.n + 255) / 256), dim3(256), 0, st, a, w_user);
+    const size_t lds = 2 * sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
+    hipLaunchKernelGGL((k_pair_pass<OP_ADJ>), dim3(a.ncells), dim3(kWave), lds, st, a,
+                       static_cast<const float4*>(a.vel1), lam_r, static_cast<float4*>(nullptr), coef, 0.f);
+    if (theta) hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(kRedBlock), 0, st, a, theta, static_cast<double>(coef));
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_grad(const SimArgs& a, float kcoef, float wcoef, float4* g_r, float4* g_v, double* theta,
+                            hipStream_t st) {
+    const size_t lds = sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
+    hipLaunchKernelGGL((k_pair_pass<OP_VGRAD>), dim3(a.ncells), dim3(kWave), lds, st, a,
+                       static_cast<const float4*>(nullptr), g_r, g_v, wcoef, kcoef);
+    if (theta) hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(kRedBlock), 0, st, a, theta, static_cast<double>(wcoef));
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_drift(int n, float dt, const float4* lam_r, float4* lam_v, hipStream_t st) {
+    hipLaunchKernelGGL(k_adjoint_drift, dim3((n + 255) / 256), dim3(256), 0, st, n, dt, lam_r, lam_v);
+    return hipGetLastError();
+}
+
+}  // namespace mdlj

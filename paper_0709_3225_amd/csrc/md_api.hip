@@ -298,6 +298,52 @@ md_status md_cell_lists(const md_params* p, const void* ws, size_t ws_bytes, int
     return MD_OK;
 }
 
+md_status md_adjoint_kick(const md_params* p, void* ws, size_t ws_bytes, const float* w4, float* lam_r4, double* theta,
+                          float coef, hipStream_t stream) {
+    Layout L{};
+    md_status s = make_layout(p, L);
+    if (s != MD_OK) return s;
+    if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
+    if (p->shift_mode != 0) return fail(MD_ERR_ARG, "the adjoint needs shift_mode 0 (force shift)");
+    if (!w4 || !lam_r4) return fail(MD_ERR_ARG, "adjoint vectors are NULL");
+    if (!aligned16(w4) || !aligned16(lam_r4)) return fail(MD_ERR_ARG, "adjoint vectors must be 16-byte aligned");
+    if (w4 == lam_r4) return fail(MD_ERR_ARG, "w and lam_r must not alias");
+    if (!std::isfinite(coef)) return fail(MD_ERR_ARG, "coef must be finite");
+    const SimArgs a = make_args(p, L, ws);
+    MD_TRY_HIP(launch_adjoint_kick(a, reinterpret_cast<const float4*>(w4), reinterpret_cast<float4*>(lam_r4), theta,
+                                   coef, stream),
+               "adjoint kick");
+    return MD_OK;
+}
+
+md_status md_adjoint_drift(const md_params* p, const float* lam_r4, float* lam_v4, hipStream_t stream) {
+    md_status s = validate(p);
+    if (s != MD_OK) return s;
+    if (!lam_r4 || !lam_v4) return fail(MD_ERR_ARG, "adjoint vectors are NULL");
+    if (!aligned16(lam_r4) || !aligned16(lam_v4)) return fail(MD_ERR_ARG, "adjoint vectors must be 16-byte aligned");
+    MD_TRY_HIP(launch_adjoint_drift(p->n, p->dt, reinterpret_cast<const float4*>(lam_r4),
+                                    reinterpret_cast<float4*>(lam_v4), stream),
+               "adjoint drift");
+    return MD_OK;
+}
+
+md_status md_loss_grad(const md_params* p, void* ws, size_t ws_bytes, float k_coef, float w_coef, float* g_r4,
+                       float* g_v4, double* theta, hipStream_t stream) {
+    Layout L{};
+    md_status s = make_layout(p, L);
+    if (s != MD_OK) return s;
+    if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
+    if (p->shift_mode != 0) return fail(MD_ERR_ARG, "the adjoint needs shift_mode 0 (force shift)");
+    if (!g_r4 || !g_v4) return fail(MD_ERR_ARG, "gradient outputs are NULL");
+    if (!aligned16(g_r4) || !aligned16(g_v4)) return fail(MD_ERR_ARG, "gradient outputs must be 16-byte aligned");
+    if (!std::isfinite(k_coef) || !std::isfinite(w_coef)) return fail(MD_ERR_ARG, "coefficients must be finite");
+    const SimArgs a = make_args(p, L, ws);
+    MD_TRY_HIP(launch_loss_grad(a, k_coef, w_coef, reinterpret_cast<float4*>(g_r4), reinterpret_cast<float4*>(g_v4),
+                                theta, stream),
+               "loss gradient");
+    return MD_OK;
+}
+
 md_status md_check(void* ws, size_t ws_bytes, hipStream_t stream, int32_t* flags_out) {
     if (!ws) return fail(MD_ERR_WORKSPACE, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(MD_ERR_WORKSPACE, "workspace is not 256-byte aligned");

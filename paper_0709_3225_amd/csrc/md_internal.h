@@ -80,5 +80,10 @@ hipError_t launch_gather_user(const SimArgs& a, float4* pos_out, float4* vel_out
 hipError_t launch_neighbors(const SimArgs& a, int* counts, int* idx, int max_per_atom,
                             hipStream_t st);
 hipError_t launch_cell_lists(const SimArgs& a, int* cell_start, int* order, hipStream_t st);
+hipError_t launch_adjoint_kick(const SimArgs& a, const float4* w_user, float4* lam_r, double* theta, float coef,
+                               hipStream_t st);
+hipError_t launch_loss_grad(const SimArgs& a, float kcoef, float wcoef, float4* g_r, float4* g_v, double* theta,
+                            hipStream_t st);
+hipError_t launch_adjoint_drift(int n, float dt, const float4* lam_r, float4* lam_v, hipStream_t st);
 
 }  // namespace mdlj

@@ -1,0 +1,198 @@
+"""GPU parity of the adjoint entry points against the FP64 oracle.
+
+Single-state kernels (Hessian-vector product, force parameter derivatives,
+virial gradient) are compared with the oracle's pinned FP64 functions at
+1e-5 relative. The trajectory gradient of L = K_T/N + W_T/(3V) through 200
+velocity-Verlet steps (N = 256, checkpoints every 20 steps) is compared with
+the torch-float64 reference: FP32 and FP64 trajectories separate
+exponentially over one time unit, so the bound is 1e-3 relative L2 for the
+position and velocity gradients and 1e-4 relative for d/d(eps, sigma).
+"""
+import numpy as np
+import pytest
+
+import ljsynth
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-5
+
+
+def _torch():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _dev(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _loaded(pos4, box, vel4=None):
+    from paper_0709_3225_amd import LJSystem
+
+    s = LJSystem(len(pos4), box)
+    s.load(_dev(pos4), None if vel4 is None else _dev(vel4), forces=False)
+    return s
+
+
+@pytest.mark.parametrize("name", ["lj256_check", "lj4k", "lj32k_adjoint"])
+def test_hvp_and_force_parameter_derivatives(name, orc):
+    torch = _torch()
+    from paper_0709_3225_amd import _lib as L
+
+    pos4, vel4, box = ljsynth.make_state(ljsynth.WORKLOADS[name], jitter_amp=0.05, shuffle=True)
+    _say(f"hvp {name} n={len(pos4)}")
+    w = np.zeros_like(pos4)
+    w[:, :3] = np.random.default_rng(7).normal(size=(len(pos4), 3))
+    s = _loaded(pos4, box)
+    lam = torch.zeros((len(pos4), 4), dtype=torch.float32, device="cuda")
+    theta = torch.zeros(2, dtype=torch.float64, device="cuda")
+    L.md_adjoint_kick(s.params, s.ws, _dev(w), lam, theta, 1.0)
+    assert s.check() == 0
+    ju = lam.cpu().numpy()[:, :3].astype(np.float64)
+    p = orc.params(box)
+    ref = orc.hvp(p, pos4, w)
+    assert rel_l2(ju, ref) <= REL
+    # accumulation: a second call with coef -0.5 halves lam
+    L.md_adjoint_kick(s.params, s.ws, _dev(w), lam, None, -0.5)
+    assert rel_l2(lam.cpu().numpy()[:, :3], 0.5 * ref) <= REL
+    # parameter derivatives projected on the forces themselves (w = F): the sums
+    # sum_i F_i . dF_i/d(eps, sigma) do not cancel, so 1e-5 relative is meaningful
+    # (a random w makes them cancel by orders of magnitude)
+    f, _, _ = orc.forces(p, pos4)
+    wf = np.zeros_like(pos4)
+    wf[:, :3] = f
+    theta.zero_()
+    L.md_adjoint_kick(s.params, s.ws, _dev(wf), lam, theta, 1.0)
+    assert s.check() == 0
+    de, ds = orc.dforce_dparams(p, pos4, f)
+    th = theta.cpu().numpy()
+    assert th[0] == pytest.approx(de, rel=REL)
+    assert th[1] == pytest.approx(ds, rel=REL)
+
+
+def test_hvp_symmetry_and_translation():
+    torch = _torch()
+    from paper_0709_3225_amd import _lib as L
+
+    pos4, vel4, box = ljsynth.make_state(ljsynth.WORKLOADS["lj4k"], jitter_amp=0.05)
+    _say("hvp symmetry lj4k")
+    s = _loaded(pos4, box)
+    rng = np.random.default_rng(8)
+    u = np.zeros_like(pos4)
+    v = np.zeros_like(pos4)
+    u[:, :3] = rng.normal(size=(len(pos4), 3))
+    v[:, :3] = rng.normal(size=(len(pos4), 3))
+    outs = []
+    for a_ in (u, v):
+        lam = torch.zeros((len(pos4), 4), dtype=torch.float32, device="cuda")
+        L.md_adjoint_kick(s.params, s.ws, _dev(a_), lam, None, 1.0)
+        outs.append(lam.cpu().numpy().astype(np.float64))
+    a = float((u * outs[1]).sum())
+    b = float((v * outs[0]).sum())
+    assert a == pytest.approx(b, rel=1e-4)
+    t = np.zeros_like(pos4)
+    t[:, 1] = 1.0
+    lam = torch.zeros((len(pos4), 4), dtype=torch.float32, device="cuda")
+    L.md_adjoint_kick(s.params, s.ws, _dev(t), lam, None, 1.0)
+    assert np.abs(lam.cpu().numpy()).max() <= 1e-6 * np.abs(outs[0]).max()
+    assert s.check() == 0
+
+
+@pytest.mark.parametrize("name", ["lj256_check", "lj4k"])
+def test_loss_gradient(name, orc):
+    torch = _torch()
+    from paper_0709_3225_amd import _lib as L
+
+    pos4, vel4, box = ljsynth.make_state(ljsynth.WORKLOADS[name], jitter_amp=0.05)
+    _say(f"loss gradient {name}")
+    n = len(pos4)
+    s = _loaded(pos4, box, vel4)
+    gr = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+    gv = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+    theta = torch.zeros(2, dtype=torch.float64, device="cuda")
+    kc, wc = 1.0 / n, 1.0 / (3 * box ** 3)
+    L.md_loss_grad(s.params, s.ws, kc, wc, gr, gv, theta)
+    assert s.check() == 0
+    g, dwe, dws = orc.virial_grad(orc.params(box), pos4)
+    assert rel_l2(gr.cpu().numpy()[:, :3], wc * g) <= REL
+    np.testing.assert_allclose(gv.cpu().numpy()[:, :3], kc * vel4[:, :3], rtol=1e-6)
+    th = theta.cpu().numpy()
+    assert th[0] == pytest.approx(wc * dwe, rel=REL)
+    assert th[1] == pytest.approx(wc * dws, rel=REL)
+
+
+def test_adjoint_drift():
+    torch = _torch()
+    from paper_0709_3225_amd import _lib as L, make_params
+
+    _say("adjoint drift")
+    n = 1000
+    p = make_params(n, 10.0, dt=0.005)
+    a = torch.randn((n, 4), device="cuda")
+    b = torch.randn((n, 4), device="cuda")
+    ref = b.clone()
+    ref[:, :3] += 0.005 * a[:, :3]
+    L.md_adjoint_drift(p, a, b)
+    torch.cuda.synchronize()
+    assert torch.allclose(b[:, :3], ref[:, :3], rtol=1e-6, atol=1e-7)
+
+
+def test_energy_shift_mode_refused():
+    torch = _torch()
+    from paper_0709_3225_amd import _lib as L, LJSystem, MDError
+
+    _say("adjoint refuses shift_mode 1")
+    pos4, vel4, box = ljsynth.make_state(ljsynth.WORKLOADS["lj256_check"])
+    s = LJSystem(len(pos4), box, shift_mode=1)
+    s.load(_dev(pos4), forces=False)
+    lam = torch.zeros((len(pos4), 4), dtype=torch.float32, device="cuda")
+    with pytest.raises(MDError):
+        L.md_adjoint_kick(s.params, s.ws, _dev(pos4), lam, None, 1.0)
+
+
+def test_trajectory_gradient_matches_fp64_reference():
+    torch = _torch()
+    from oracle import grad_ref
+    from paper_0709_3225_amd import trajectory_gradients
+
+    w = ljsynth.WORKLOADS["lj256_check"]
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05)
+    _say("trajectory gradient n=256 T=200 every=20")
+    loss, gr, gv, ge, gs = trajectory_gradients(_dev(pos4), _dev(vel4), box, nsteps=200, every=20)
+    rl, rx, rv, re, rs = grad_ref.loss_and_grads(pos4, vel4, box, nsteps=200)
+    assert loss == pytest.approx(rl, rel=1e-4)
+    assert rel_l2(gr.cpu().numpy()[:, :3], rx) <= 1e-3
+    assert rel_l2(gv.cpu().numpy()[:, :3], rv) <= 1e-3
+    assert ge == pytest.approx(re, rel=1e-4)
+    assert gs == pytest.approx(rs, rel=1e-4)
+
+
+def test_autograd_function_matches_direct_call():
+    torch = _torch()
+    from paper_0709_3225_amd import LJTrajectory, trajectory_gradients
+
+    w = ljsynth.WORKLOADS["lj256_check"]
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05)
+    _say("autograd function n=256 T=40")
+    x = _dev(pos4).requires_grad_(True)
+    v = _dev(vel4).requires_grad_(True)
+    e = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    sg = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    loss = LJTrajectory.apply(x, v, e, sg, box, 1.0, 0.005, 40, 10)
+    loss.backward()
+    l2, gr, gv, ge, gs = trajectory_gradients(_dev(pos4), _dev(vel4), box, nsteps=40, every=10)
+    assert float(loss) == l2
+    assert torch.equal(x.grad, gr) and torch.equal(v.grad, gv)
+    assert float(e.grad) == ge and float(sg.grad) == gs
