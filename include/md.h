@@ -203,6 +203,76 @@ md_status md_loss_grad(const md_params* p, void* ws, size_t ws_bytes, float k_co
                        float* g_r4_dev, float* g_v4_dev, double* theta_dev, hipStream_t stream);
 
 /*
+ * ---- Batches of independent replicas ----
+ * Many LJ systems of different size and density advance together: every
+ * phase (drift, histogram, scan, scatter, in-cell order, forces, kick) runs as
+ * one launch over the atoms or cells of all replicas, and md_batch_graph_create
+ * captures a whole multi-step run into one graph that md_graph_launch starts
+ * with a single call. Each replica follows exactly the arithmetic of md_step
+ * on that system alone (same cell grid, LDS pass length and summation order),
+ * so its results are bitwise those of a solo run.
+ *
+ * Shared parameters (epsilon, sigma, mass, rc_over_sigma, dt, cell_min,
+ * shift_mode) come from p; p->n and p->box are ignored. Replica b owns atoms
+ * [A_b, A_b + n_b) of the concatenated float4 arrays, A_b = n_0 + ... +
+ * n_(b-1); every replica needs box >= 2 r_c. The table is re-validated on
+ * every call and must not change between calls on one workspace.
+ */
+typedef struct md_replica {
+    int32_t n;  /* atoms of this replica, >= 1 */
+    float box;  /* its cubic periodic box side */
+} md_replica;
+
+/* Workspace bytes for this batch (0 if invalid). Host only. */
+size_t md_batch_workspace_bytes(const md_params* p, const md_replica* reps, int32_t count);
+
+/* Load all replicas (concatenated float4 arrays, vel4 nullable) and build
+ * their cell lists. Uploads the replica table into the workspace and waits
+ * for that copy (this call synchronises `stream` once). */
+md_status md_batch_build(const md_params* p, const md_replica* reps, int32_t count, void* ws, size_t ws_bytes,
+                         const float* pos4_dev, const float* vel4_dev, hipStream_t stream);
+
+/* Forces of every replica (needed once before md_batch_step); optional
+ * float4 output in concatenated user order. */
+md_status md_batch_forces(const md_params* p, const md_replica* reps, int32_t count, void* ws, size_t ws_bytes,
+                          float* force4_dev, hipStream_t stream);
+
+/* nsteps velocity-Verlet steps of every replica. With thermo_every > 0,
+ * thermo_dev receives (U, K, W) of replica b after step (r + 1) thermo_every at
+ * thermo_dev[3 (r count + b) + 0..2]. */
+md_status md_batch_step(const md_params* p, const md_replica* reps, int32_t count, void* ws, size_t ws_bytes,
+                        int32_t nsteps, int32_t thermo_every, double* thermo_dev, hipStream_t stream);
+
+/* U, K, W of every replica: out_dev[3 b + 0..2] (FP64, fixed-order sums). */
+md_status md_batch_energy_virial(const md_params* p, const md_replica* reps, int32_t count, void* ws,
+                                 size_t ws_bytes, double* out_dev, hipStream_t stream);
+
+/* Positions and velocities in concatenated user order (either nullable). */
+md_status md_batch_get_state(const md_params* p, const md_replica* reps, int32_t count, const void* ws,
+                             size_t ws_bytes, float* pos4_dev, float* vel4_dev, hipStream_t stream);
+
+/* An instantiated graph of a batched run, owned by the caller. */
+typedef struct md_graph_s* md_graph;
+
+/*
+ * Capture nsteps batched steps (with optional thermo output, as in
+ * md_batch_step) on `stream` into a graph and instantiate it; nothing runs
+ * until md_graph_launch. stream must not be the null stream (graph capture
+ * needs a real stream). The graph holds the workspace and thermo pointers:
+ * both must outlive it. Creating a graph allocates host-side runtime objects
+ * only; the library allocates no device memory of its own.
+ */
+md_status md_batch_graph_create(const md_params* p, const md_replica* reps, int32_t count, void* ws,
+                                size_t ws_bytes, int32_t nsteps, int32_t thermo_every, double* thermo_dev,
+                                hipStream_t stream, md_graph* graph_out);
+
+/* Enqueue one run of the graph on `stream`. */
+md_status md_graph_launch(md_graph graph, hipStream_t stream);
+
+/* Release the graph (NULL is ignored). Synchronise any stream that launched it first. */
+md_status md_graph_destroy(md_graph graph);
+
+/*
  * Synchronise `stream`, then read and clear the device error word.
  * flags_out (host pointer, nullable) receives the MD_DEV_* bits.
  * Returns MD_ERR_DEVICE if any bit was set, MD_ERR_HIP on a runtime error.

@@ -23,5 +23,6 @@ from ._lib import (  # noqa: F401
 )
 from .system import LJSystem  # noqa: F401
 from .adjoint import LJTrajectory, trajectory_gradients  # noqa: F401
+from .batch import BatchedLJ  # noqa: F401
 
 lib()

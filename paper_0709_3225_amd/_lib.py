@@ -38,6 +38,15 @@ SYMBOLS = (
     "md_adjoint_kick",
     "md_adjoint_drift",
     "md_loss_grad",
+    "md_batch_workspace_bytes",
+    "md_batch_build",
+    "md_batch_forces",
+    "md_batch_step",
+    "md_batch_energy_virial",
+    "md_batch_get_state",
+    "md_batch_graph_create",
+    "md_graph_launch",
+    "md_graph_destroy",
     "md_check",
     "md_last_error",
     "md_status_name",
@@ -63,6 +72,19 @@ class MDParams(ctypes.Structure):
         ("shift_mode", ctypes.c_int32),
         ("flags", ctypes.c_int32),
     ]
+
+
+class MDReplica(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("box", ctypes.c_float)]
+
+
+def replica_table(reps):
+    """ctypes array of md_replica from (n, box) pairs."""
+    arr = (MDReplica * len(reps))()
+    for i, (n, box) in enumerate(reps):
+        arr[i].n = int(n)
+        arr[i].box = float(box)
+    return arr
 
 
 def make_params(n, box, epsilon=1.0, sigma=1.0, mass=1.0, rc_over_sigma=2.5, dt=0.005, cell_min=0.0,
@@ -99,9 +121,22 @@ def lib():
         L.md_adjoint_kick.argtypes = [P, vp, sz, vp, vp, vp, ctypes.c_float, vp]
         L.md_adjoint_drift.argtypes = [P, vp, vp, vp]
         L.md_loss_grad.argtypes = [P, vp, sz, ctypes.c_float, ctypes.c_float, vp, vp, vp, vp]
+        R = ctypes.POINTER(MDReplica)
+        L.md_batch_workspace_bytes.argtypes = [P, R, i32]
+        L.md_batch_workspace_bytes.restype = sz
+        L.md_batch_build.argtypes = [P, R, i32, vp, sz, vp, vp, vp]
+        L.md_batch_forces.argtypes = [P, R, i32, vp, sz, vp, vp]
+        L.md_batch_step.argtypes = [P, R, i32, vp, sz, i32, i32, vp, vp]
+        L.md_batch_energy_virial.argtypes = [P, R, i32, vp, sz, vp, vp]
+        L.md_batch_get_state.argtypes = [P, R, i32, vp, sz, vp, vp, vp]
+        L.md_batch_graph_create.argtypes = [P, R, i32, vp, sz, i32, i32, vp, vp, ctypes.POINTER(vp)]
+        L.md_graph_launch.argtypes = [vp, vp]
+        L.md_graph_destroy.argtypes = [vp]
         for name in ("md_cell_grid", "md_build_cells", "md_forces", "md_step", "md_energy_virial",
                      "md_get_state", "md_neighbors", "md_cell_lists", "md_check", "md_adjoint_kick",
-                     "md_adjoint_drift", "md_loss_grad"):
+                     "md_adjoint_drift", "md_loss_grad", "md_batch_build", "md_batch_forces", "md_batch_step",
+                     "md_batch_energy_virial", "md_batch_get_state", "md_batch_graph_create", "md_graph_launch",
+                     "md_graph_destroy"):
             getattr(L, name).restype = ctypes.c_int
         L.md_last_error.argtypes = []
         L.md_last_error.restype = ctypes.c_char_p

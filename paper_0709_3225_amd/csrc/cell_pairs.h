@@ -33,7 +33,7 @@ __device__ __forceinline__ void load_neighbourhood(const SimArgs& a, int c, Neig
         if (jx < 0) { jx += nc; bx = ox + a.box; } else if (jx >= nc) { jx -= nc; bx = ox - a.box; }
         if (jy < 0) { jy += nc; by = oy + a.box; } else if (jy >= nc) { jy -= nc; by = oy - a.box; }
         if (jz < 0) { jz += nc; bz = oz + a.box; } else if (jz >= nc) { jz -= nc; bz = oz - a.box; }
-        const int cj = jx + nc * (jy + nc * jz);
+        const int cj = a.cbase + jx + nc * (jy + nc * jz);
         first = a.start[cj];
         cnt = a.start[cj + 1] - first;
     }

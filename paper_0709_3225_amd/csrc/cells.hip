@@ -31,14 +31,15 @@ __global__ void __launch_bounds__(kBlock) k_build_init(SimArgs a) {
     for (int c = t; c < a.ncells; c += gridDim.x * kBlock) a.count[c] = 0;
 }
 
-// Load user-order state into the staging arrays: wrap, cell index, rank.
-__global__ void __launch_bounds__(kBlock) k_load(SimArgs a, const float4* __restrict__ pos_in,
-                                                 const float4* __restrict__ vel_in) {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+// Load one user-order atom i into the staging arrays: wrap, cell index,
+// rank. Called by every lane of the wave (valid = false for lanes past the
+// end); cells are numbered globally (a.cbase + local index).
+__device__ __forceinline__ void load_atom(const SimArgs& a, int i, bool valid, const float4* __restrict__ pos_in,
+                                          const float4* __restrict__ vel_in) {
     const float invL = 1.0f / a.box;
     int c = -1;
     float4 p = make_float4(0.f, 0.f, 0.f, 0.f), v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (i < a.n) {
+    if (valid) {
         p = pos_in[i];
         if (vel_in) v = vel_in[i];
         if (!finite3(p.x, p.y, p.z) || !finite3(v.x, v.y, v.z)) {
@@ -50,10 +51,10 @@ __global__ void __launch_bounds__(kBlock) k_load(SimArgs a, const float4* __rest
         p.z = wrap_coord(p.z, a.box, invL);
         p.w = __int_as_float(i);
         v.w = 0.f;
-        c = cell_index(p.x, p.y, p.z, a);
+        c = a.cbase + cell_index(p.x, p.y, p.z, a);
     }
     const int r = histogram_rank(a.count, c);
-    if (i < a.n) {
+    if (valid) {
         a.pos1[i] = p;
         a.vel1[i] = v;
         a.cell[i] = c;
@@ -61,20 +62,14 @@ __global__ void __launch_bounds__(kBlock) k_load(SimArgs a, const float4* __rest
     }
 }
 
-// Velocity-Verlet first half: v += dt/(2m) F, r += dt v, wrap, then the
-// histogram rank for the rebuild. Reads the sorted state, writes staging.
-__global__ void __launch_bounds__(kBlock) k_integrate(SimArgs a) {
-    // A step needs forces of the current state; while a call-order error is
-    // pending (until md_check clears it) every step kernel does nothing.
-    if (!state_ok(a, true) || (a.hdr[HDR_ERROR] & DEV_ORDER)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&a.hdr[HDR_ERROR], DEV_ORDER);
-        return;
-    }
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+// Velocity-Verlet first half for sorted slot i: v += dt/(2m) F, r += dt v,
+// wrap, then the histogram rank for the rebuild. Reads the sorted state,
+// writes staging. Called by every lane of the wave.
+__device__ __forceinline__ void integrate_atom(const SimArgs& a, int i, bool valid) {
     const float invL = 1.0f / a.box;
     int c = -1;
     float4 p = make_float4(0.f, 0.f, 0.f, 0.f), v = p;
-    if (i < a.n) {
+    if (valid) {
         p = a.pos0[i];
         v = a.vel0[i];
         const float4 f = a.force[i];
@@ -91,15 +86,107 @@ __global__ void __launch_bounds__(kBlock) k_integrate(SimArgs a) {
         p.x = wrap_coord(p.x, a.box, invL);
         p.y = wrap_coord(p.y, a.box, invL);
         p.z = wrap_coord(p.z, a.box, invL);
-        c = cell_index(p.x, p.y, p.z, a);
+        c = a.cbase + cell_index(p.x, p.y, p.z, a);
     }
     const int r = histogram_rank(a.count, c);
-    if (i < a.n) {
+    if (valid) {
         a.pos1[i] = p;
         a.vel1[i] = v;
         a.cell[i] = c;
         a.rank[i] = r;
     }
+}
+
+__global__ void __launch_bounds__(kBlock) k_load(SimArgs a, const float4* __restrict__ pos_in,
+                                                 const float4* __restrict__ vel_in) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    load_atom(a, i, i < a.n, pos_in, vel_in);
+}
+
+__global__ void __launch_bounds__(kBlock) k_integrate(SimArgs a) {
+    // A step needs forces of the current state; while a call-order error is
+    // pending (until md_check clears it) every step kernel does nothing.
+    if (!state_ok(a, true) || (a.hdr[HDR_ERROR] & DEV_ORDER)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&a.hdr[HDR_ERROR], DEV_ORDER);
+        return;
+    }
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    integrate_atom(a, i, i < a.n);
+}
+
+// Batched load and drift: one lane per atom of the whole batch (global
+// index; replica from the per-atom table). a.n of the base is the batch total.
+__global__ void __launch_bounds__(kBlock) k_batch_load(SimArgs base, const Replica* __restrict__ reps,
+                                                       const int* __restrict__ atom_rep,
+                                                       const float4* __restrict__ pos_in,
+                                                       const float4* __restrict__ vel_in) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = i < base.n;
+    const SimArgs a = replica_view(base, reps[valid ? atom_rep[i] : 0]);
+    load_atom(a, i, valid, pos_in, vel_in);
+}
+
+__global__ void __launch_bounds__(kBlock) k_batch_integrate(SimArgs base, const Replica* __restrict__ reps,
+                                                            const int* __restrict__ atom_rep) {
+    if (base.hdr[HDR_STATE] != STATE_FORCES || (base.hdr[HDR_ERROR] & DEV_ORDER)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&base.hdr[HDR_ERROR], DEV_ORDER);
+        return;
+    }
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = i < base.n;
+    const SimArgs a = replica_view(base, reps[valid ? atom_rep[i] : 0]);
+    integrate_atom(a, i, valid);
+}
+
+// Batch set-up: per-atom and per-cell replica tables, zero histogram, header.
+// One workgroup per replica.
+__global__ void __launch_bounds__(kBlock) k_batch_setup(SimArgs base, const Replica* __restrict__ reps,
+                                                        int* __restrict__ atom_rep, int* __restrict__ cell_rep,
+                                                        int count) {
+    const int b = blockIdx.x;
+    const Replica r = reps[b];
+    if (b == 0 && threadIdx.x == 0) {
+        base.hdr[HDR_ERROR] = 0;
+        base.hdr[HDR_STATE] = STATE_BUILDING;
+        base.hdr[HDR_N] = base.n;
+        base.hdr[HDR_NC] = -count;  // marks a batch workspace
+    }
+    for (int i = threadIdx.x; i < r.n; i += kBlock) atom_rep[r.abase + i] = b;
+    for (int c = threadIdx.x; c < r.ncells; c += kBlock) {
+        cell_rep[r.cbase + c] = b;
+        base.count[r.cbase + c] = 0;
+    }
+}
+
+// Batched scan: one workgroup per replica scans its own histogram into
+// start[cbase .. cbase + ncells) (global slots: abase + prefix) and clears it;
+// the last replica also writes the terminal entry.
+__global__ void __launch_bounds__(kBlock) k_batch_scan(SimArgs base, const Replica* __restrict__ reps, int count) {
+    if (base.hdr[HDR_ERROR] & DEV_ORDER) return;
+    __shared__ int wave_tot[kBlock / kWave];
+    const Replica r = reps[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    int carry = r.abase;
+    for (int base_c = 0; base_c < r.ncells; base_c += kBlock) {
+        const int c = base_c + tid;
+        const int v = (c < r.ncells) ? base.count[r.cbase + c] : 0;
+        const int incl = wave_incl_scan(v);
+        if (lane == kWave - 1) wave_tot[wave] = incl;
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) {
+            const int t = wave_tot[w];
+            if (w < wave) off += t;
+            tot += t;
+        }
+        if (c < r.ncells) {
+            base.start[r.cbase + c] = carry + off + incl - v;
+            base.count[r.cbase + c] = 0;
+        }
+        carry += tot;
+        __syncthreads();
+    }
+    if (blockIdx.x == count - 1 && tid == 0) base.start[r.cbase + r.ncells] = carry;
 }
 
 // Exclusive prefix scan of the histogram into start[0..ncells], by one
@@ -265,6 +352,30 @@ hipError_t launch_gather_user(const SimArgs& a, float4* pos_out, float4* vel_out
                               hipStream_t st) {
     hipLaunchKernelGGL(k_gather_user, dim3(blocks_for(a.n, kBlock)), dim3(kBlock), 0, st, a, pos_out,
                        vel_out, force_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_setup(const SimArgs& base, const Replica* reps, int* atom_rep, int* cell_rep, int count,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_setup, dim3(count), dim3(kBlock), 0, st, base, reps, atom_rep, cell_rep, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_load(const SimArgs& base, const Replica* reps, const int* atom_rep, const float4* pos_in,
+                             const float4* vel_in, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_load, dim3(blocks_for(base.n, kBlock)), dim3(kBlock), 0, st, base, reps, atom_rep,
+                       pos_in, vel_in);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_integrate(const SimArgs& base, const Replica* reps, const int* atom_rep, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_integrate, dim3(blocks_for(base.n, kBlock)), dim3(kBlock), 0, st, base, reps,
+                       atom_rep);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_scan(const SimArgs& base, const Replica* reps, int count, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_scan, dim3(count), dim3(kBlock), 0, st, base, reps, count);
     return hipGetLastError();
 }
 

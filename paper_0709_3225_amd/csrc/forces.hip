@@ -60,19 +60,11 @@ struct ForceOp {
     }
 };
 
+// Forces on the atoms of home cell c (local index of the system described by
+// a); one wavefront. Energy partials go to a.epart[3 (a.cbase + c) + 0..2].
 template <bool KICK, bool ENERGY, bool WRITE>
-__global__ void __launch_bounds__(kWave) k_forces(SimArgs a, bool from_step) {
-    if (from_step) {
-        if (a.hdr[HDR_ERROR] & DEV_ORDER) return;
-    } else if (!state_ok(a, false)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&a.hdr[HDR_ERROR], DEV_ORDER);
-        return;
-    }
-    extern __shared__ float4 tile[];  // a.tile_cap + kTilePad entries
-    __shared__ Neighbourhood nb;
-    __shared__ float red[5 * kWave];
+__device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile, Neighbourhood& nb, float* red) {
     const int lane = threadIdx.x;
-    const int c = xcd_block_order(blockIdx.x, a.ncells);
     float ox, oy, oz;
     load_neighbourhood(a, c, nb, ox, oy, oz);
     const int total = nb.pref[27];
@@ -174,12 +166,42 @@ __global__ void __launch_bounds__(kWave) k_forces(SimArgs a, bool from_step) {
         w_acc = wave_sum(w_acc);
         k_acc = wave_sum(k_acc);
         if (lane == 0) {
-            a.epart[3 * blockIdx.x + 0] = u_acc;
-            a.epart[3 * blockIdx.x + 1] = w_acc;
-            a.epart[3 * blockIdx.x + 2] = k_acc;
+            double* e = a.epart + 3 * static_cast<size_t>(a.cbase + c);
+            e[0] = u_acc;
+            e[1] = w_acc;
+            e[2] = k_acc;
         }
     }
-    if (WRITE && blockIdx.x == 0 && lane == 0) a.hdr[HDR_STATE] = STATE_FORCES;
+}
+
+template <bool KICK, bool ENERGY, bool WRITE>
+__global__ void __launch_bounds__(kWave) k_forces(SimArgs a, bool from_step) {
+    if (from_step) {
+        if (a.hdr[HDR_ERROR] & DEV_ORDER) return;
+    } else if (!state_ok(a, false)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&a.hdr[HDR_ERROR], DEV_ORDER);
+        return;
+    }
+    extern __shared__ float4 tile[];  // a.tile_cap + kTilePad entries
+    __shared__ Neighbourhood nb;
+    __shared__ float red[5 * kWave];
+    force_cell<KICK, ENERGY, WRITE>(a, xcd_block_order(blockIdx.x, a.ncells), tile, nb, red);
+    if (WRITE && blockIdx.x == 0 && threadIdx.x == 0) a.hdr[HDR_STATE] = STATE_FORCES;
+}
+
+// Batched forces: one workgroup per cell of any replica (global cell index,
+// XCD-ordered); the replica's own geometry comes from its descriptor.
+template <bool KICK, bool ENERGY, bool WRITE>
+__global__ void __launch_bounds__(kWave)
+    k_batch_forces(SimArgs base, const Replica* __restrict__ reps, const int* __restrict__ cell_rep, int total_cells) {
+    if (base.hdr[HDR_ERROR] & DEV_ORDER) return;
+    extern __shared__ float4 tile[];  // max tile_cap over replicas + kTilePad entries
+    __shared__ Neighbourhood nb;
+    __shared__ float red[5 * kWave];
+    const int gc = xcd_block_order(blockIdx.x, total_cells);
+    const SimArgs a = replica_view(base, reps[cell_rep[gc]]);
+    force_cell<KICK, ENERGY, WRITE>(a, gc - a.cbase, tile, nb, red);
+    if (WRITE && blockIdx.x == 0 && threadIdx.x == 0) base.hdr[HDR_STATE] = STATE_FORCES;
 }
 
 // Fixed-order final sum of the per-block partials: U = 1/2 sum, W = 1/2 sum
@@ -211,6 +233,40 @@ __global__ void __launch_bounds__(kRedBlock) k_energy_final(SimArgs a, double* o
         out3[0] = 0.5 * su[0];
         out3[1] = sk[0];
         out3[2] = 0.5 * sw[0];
+    }
+}
+
+// Batched final sums: one workgroup per replica, fixed order over its cells;
+// out[3 b + 0..2] = U, K, W of replica b.
+__global__ void __launch_bounds__(kRedBlock)
+    k_batch_energy_final(SimArgs base, const Replica* __restrict__ reps, double* out) {
+    if (base.hdr[HDR_ERROR] & DEV_ORDER) return;
+    __shared__ double su[kRedBlock], sw[kRedBlock], sk[kRedBlock];
+    const Replica r = reps[blockIdx.x];
+    const int t = threadIdx.x;
+    double u = 0.0, w = 0.0, k = 0.0;
+    for (int c = t; c < r.ncells; c += kRedBlock) {
+        const double* e = base.epart + 3 * static_cast<size_t>(r.cbase + c);
+        u += e[0];
+        w += e[1];
+        k += e[2];
+    }
+    su[t] = u;
+    sw[t] = w;
+    sk[t] = k;
+    __syncthreads();
+    for (int off = kRedBlock / 2; off > 0; off >>= 1) {
+        if (t < off) {
+            su[t] += su[t + off];
+            sw[t] += sw[t + off];
+            sk[t] += sk[t + off];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[3 * blockIdx.x + 0] = 0.5 * su[0];
+        out[3 * blockIdx.x + 1] = sk[0];
+        out[3 * blockIdx.x + 2] = 0.5 * sw[0];
     }
 }
 
@@ -283,6 +339,29 @@ hipError_t launch_forces(const SimArgs& a, bool kick, bool energy, bool write_fo
 
 hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st) {
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kRedBlock), 0, st, a, out3, true);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_forces(const SimArgs& base, const Replica* reps, const int* cell_rep, int total_cells,
+                               int max_tile_cap, bool kick, bool energy, bool write_force, hipStream_t st) {
+    const dim3 g(total_cells), b(kWave);
+    const size_t lds = sizeof(float4) * static_cast<size_t>(max_tile_cap + kTilePad);
+    if (kick && energy && write_force) {
+        hipLaunchKernelGGL((k_batch_forces<true, true, true>), g, b, lds, st, base, reps, cell_rep, total_cells);
+    } else if (kick && !energy && write_force) {
+        hipLaunchKernelGGL((k_batch_forces<true, false, true>), g, b, lds, st, base, reps, cell_rep, total_cells);
+    } else if (!kick && energy && !write_force) {
+        hipLaunchKernelGGL((k_batch_forces<false, true, false>), g, b, lds, st, base, reps, cell_rep, total_cells);
+    } else if (!kick && !energy && write_force) {
+        hipLaunchKernelGGL((k_batch_forces<false, false, true>), g, b, lds, st, base, reps, cell_rep, total_cells);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_energy_final(const SimArgs& base, const Replica* reps, int count, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_energy_final, dim3(count), dim3(kRedBlock), 0, st, base, reps, out);
     return hipGetLastError();
 }
 

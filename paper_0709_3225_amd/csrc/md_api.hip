@@ -6,6 +6,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <new>
+#include <vector>
 
 #include "md.h"
 #include "md_internal.h"
@@ -114,6 +116,19 @@ md_status check_ws(const Layout& L, const void* ws, size_t ws_bytes) {
 
 bool aligned16(const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; }
 
+// Screen bound: frame coordinates lie within [-s, 2s) per axis, so |x|^2 <= 12 s^2;
+// the FP32 dot-product form of r^2 errs by a few ulp of that. 2^-17 * 12 s^2 leaves a
+// wide margin, so the screen never drops a pair that the exact test accepts.
+float screen_bound(double rc, double s) { return static_cast<float>(rc * rc + std::ldexp(12.0 * s * s, -17)); }
+
+// One LDS pass of the cell-pair kernels holds the mean 27-cell neighbourhood
+// plus 30% and a wavefront.
+int tile_capacity(int n, int ncells) {
+    const double hood = 27.0 * static_cast<double>(n) / ncells;
+    const int cap = static_cast<int>(std::ceil((1.3 * hood + 64.0) / 64.0)) * 64;
+    return std::min(2048, std::max(128, cap));
+}
+
 SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     char* b = static_cast<char*>(ws);
     SimArgs a{};
@@ -148,14 +163,8 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     a.eps4 = static_cast<float>(4.0 * eps);
     a.fc = p->shift_mode == 0 ? static_cast<float>(flj_rc) : 0.f;
     a.uc = static_cast<float>(ulj_rc);
-    // Screen bound: frame coordinates lie within [-s, 2s) per axis, so |x|^2 <= 12 s^2;
-    // the FP32 dot-product form of r^2 errs by a few ulp of that. 2^-17 * 12 s^2 leaves a
-    // wide margin, so the screen never drops a pair that the exact test accepts.
-    a.screen2 = static_cast<float>(rc * rc + std::ldexp(12.0 * L.s * L.s, -17));
-    // One LDS pass holds the mean 27-cell neighbourhood plus 30% and a wavefront.
-    const double hood = 27.0 * static_cast<double>(p->n) / L.ncells;
-    int cap = static_cast<int>(std::ceil((1.3 * hood + 64.0) / 64.0)) * 64;
-    a.tile_cap = std::min(2048, std::max(128, cap));
+    a.screen2 = screen_bound(rc, L.s);
+    a.tile_cap = tile_capacity(p->n, L.ncells);
     a.dt = p->dt;
     a.hdt_m = static_cast<float>(0.5 * p->dt / p->mass);
     a.half_m = static_cast<float>(0.5 * p->mass);
@@ -172,6 +181,132 @@ md_status rebuild_from_staging(const SimArgs& a, bool from_step, hipStream_t st)
     MD_TRY_HIP(launch_scan(a, st), "scan");
     MD_TRY_HIP(launch_scatter(a, st), "scatter");
     MD_TRY_HIP(launch_cell_order(a, from_step, st), "cell order");
+    return MD_OK;
+}
+
+// ---- batches of independent replicas -------------------------------------
+
+struct BatchPlan {
+    Layout L;                    // shared arrays; n = total atoms, ncells = total cells
+    int count = 0, max_tile = 0;
+    size_t reps = 0, atom_rep = 0, cell_rep = 0;
+    std::vector<Replica> table;  // host copy of the replica table
+};
+
+constexpr int32_t kMaxReplicas = 1 << 16;
+
+// Validate every replica (shared parameters from p, n and box per replica)
+// and lay out the batch workspace.
+md_status batch_plan(const md_params* p, const md_replica* reps, int32_t count, BatchPlan& B) {
+    if (!p) return fail(MD_ERR_ARG, "params is NULL");
+    if (!reps) return fail(MD_ERR_ARG, "replica table is NULL");
+    if (count < 1 || count > kMaxReplicas) return fail(MD_ERR_ARG, "replica count %d outside [1, 65536]", count);
+    B.count = count;
+    B.table.resize(count);
+    int64_t ntot = 0, ctot = 0;
+    for (int32_t b = 0; b < count; ++b) {
+        md_params q = *p;
+        q.n = reps[b].n;
+        q.box = reps[b].box;
+        Layout Lb{};
+        const md_status s = make_layout(&q, Lb);
+        if (s != MD_OK) {
+            char msg[512];
+            snprintf(msg, sizeof(msg), "%s", g_err);
+            return fail(s, "replica %d: %s", b, msg);
+        }
+        Replica& r = B.table[b];
+        r.n = q.n;
+        r.abase = static_cast<int>(ntot);
+        r.nc = Lb.nc;
+        r.ncells = Lb.ncells;
+        r.cbase = static_cast<int>(ctot);
+        r.tile_cap = tile_capacity(q.n, Lb.ncells);
+        r.box = q.box;
+        r.s = Lb.s;
+        r.inv_s = Lb.inv_s;
+        r.screen2 = screen_bound(static_cast<double>(cutoff(&q)), Lb.s);
+        B.max_tile = std::max(B.max_tile, r.tile_cap);
+        ntot += q.n;
+        ctot += Lb.ncells;
+        if (ntot > kMaxAtoms) return fail(MD_ERR_ARG, "batch holds more than 2^27 atoms");
+        if (ctot > (int64_t{1} << 30)) return fail(MD_ERR_ARG, "batch holds more than 2^30 cells");
+    }
+    Layout& L = B.L;
+    L.n = static_cast<int>(ntot);
+    L.nc = -count;  // marks a batch workspace in the device header
+    L.ncells = static_cast<int>(ctot);
+    L.nforce_blocks = L.ncells;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const size_t n = static_cast<size_t>(L.n), c = static_cast<size_t>(L.ncells);
+    L.hdr = take(sizeof(int) * HDR_WORDS);
+    B.reps = take(sizeof(Replica) * static_cast<size_t>(count));
+    B.atom_rep = take(4 * n);
+    B.cell_rep = take(4 * c);
+    L.pos0 = take(16 * n);
+    L.vel0 = take(16 * n);
+    L.pos1 = take(16 * n);
+    L.vel1 = take(16 * n);
+    L.force = take(16 * n);
+    L.cell = take(4 * n);
+    L.rank = take(4 * n);
+    L.key = take(4 * n);
+    L.count = take(4 * c + 16);
+    L.start = take(4 * (c + 1) + 16);
+    L.epart = take(sizeof(double) * 3 * c);
+    L.total = off;
+    return MD_OK;
+}
+
+struct BatchArgs {
+    SimArgs base;
+    const Replica* reps;
+    int* atom_rep;
+    int* cell_rep;
+};
+
+BatchArgs batch_args(const md_params* p, const BatchPlan& B, void* ws) {
+    md_params q = *p;  // shared constants; per-replica geometry lives in the table
+    q.n = B.table[0].n;
+    q.box = B.table[0].box;
+    BatchArgs ba{};
+    ba.base = make_args(&q, B.L, ws);
+    char* b = static_cast<char*>(ws);
+    ba.reps = reinterpret_cast<const Replica*>(b + B.reps);
+    ba.atom_rep = reinterpret_cast<int*>(b + B.atom_rep);
+    ba.cell_rep = reinterpret_cast<int*>(b + B.cell_rep);
+    return ba;
+}
+
+md_status batch_prepare(const md_params* p, const md_replica* reps, int32_t count, const void* ws, size_t ws_bytes,
+                        BatchPlan& B) {
+    md_status s = batch_plan(p, reps, count, B);
+    if (s != MD_OK) return s;
+    return check_ws(B.L, ws, ws_bytes);
+}
+
+// nsteps batched velocity-Verlet steps (kernels only, so the sequence can be
+// captured into a graph).
+md_status batch_steps(const BatchPlan& B, const BatchArgs& ba, int32_t nsteps, int32_t thermo_every, double* thermo,
+                      hipStream_t st) {
+    for (int32_t k = 1; k <= nsteps; ++k) {
+        const bool energy = thermo && thermo_every > 0 && (k % thermo_every) == 0;
+        MD_TRY_HIP(launch_batch_integrate(ba.base, ba.reps, ba.atom_rep, st), "batch integrate");
+        MD_TRY_HIP(launch_batch_scan(ba.base, ba.reps, B.count, st), "batch scan");
+        MD_TRY_HIP(launch_scatter(ba.base, st), "batch scatter");
+        MD_TRY_HIP(launch_cell_order(ba.base, true, st), "batch cell order");
+        MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, true, energy, true, st),
+                   "batch forces");
+        if (energy)
+            MD_TRY_HIP(launch_batch_energy_final(ba.base, ba.reps, B.count,
+                                                 thermo + 3 * static_cast<size_t>(B.count) * (k / thermo_every - 1), st),
+                       "batch energy");
+    }
     return MD_OK;
 }
 
@@ -341,6 +476,138 @@ md_status md_loss_grad(const md_params* p, void* ws, size_t ws_bytes, float k_co
     MD_TRY_HIP(launch_loss_grad(a, k_coef, w_coef, reinterpret_cast<float4*>(g_r4), reinterpret_cast<float4*>(g_v4),
                                 theta, stream),
                "loss gradient");
+    return MD_OK;
+}
+
+size_t md_batch_workspace_bytes(const md_params* p, const md_replica* reps, int32_t count) {
+    BatchPlan B;
+    if (batch_plan(p, reps, count, B) != MD_OK) return 0;
+    return B.L.total;
+}
+
+md_status md_batch_build(const md_params* p, const md_replica* reps, int32_t count, void* ws, size_t ws_bytes,
+                         const float* pos4, const float* vel4, hipStream_t stream) {
+    BatchPlan B;
+    md_status s = batch_prepare(p, reps, count, ws, ws_bytes, B);
+    if (s != MD_OK) return s;
+    if (!pos4) return fail(MD_ERR_ARG, "positions are NULL");
+    if (!aligned16(pos4) || (vel4 && !aligned16(vel4))) return fail(MD_ERR_ARG, "particle arrays must be 16-byte aligned");
+    const BatchArgs ba = batch_args(p, B, ws);
+    // the replica table lives in the workspace; wait for the copy so the host table can go
+    MD_TRY_HIP(hipMemcpyAsync(const_cast<Replica*>(ba.reps), B.table.data(), sizeof(Replica) * B.table.size(),
+                              hipMemcpyHostToDevice, stream),
+               "replica table upload");
+    MD_TRY_HIP(hipStreamSynchronize(stream), "replica table upload");
+    MD_TRY_HIP(launch_batch_setup(ba.base, ba.reps, ba.atom_rep, ba.cell_rep, B.count, stream), "batch setup");
+    MD_TRY_HIP(launch_batch_load(ba.base, ba.reps, ba.atom_rep, reinterpret_cast<const float4*>(pos4),
+                                 reinterpret_cast<const float4*>(vel4), stream),
+               "batch load");
+    MD_TRY_HIP(launch_batch_scan(ba.base, ba.reps, B.count, stream), "batch scan");
+    MD_TRY_HIP(launch_scatter(ba.base, stream), "batch scatter");
+    MD_TRY_HIP(launch_cell_order(ba.base, false, stream), "batch cell order");
+    return MD_OK;
+}
+
+md_status md_batch_forces(const md_params* p, const md_replica* reps, int32_t count, void* ws, size_t ws_bytes,
+                          float* force4, hipStream_t stream) {
+    BatchPlan B;
+    md_status s = batch_prepare(p, reps, count, ws, ws_bytes, B);
+    if (s != MD_OK) return s;
+    if (force4 && !aligned16(force4)) return fail(MD_ERR_ARG, "force array must be 16-byte aligned");
+    const BatchArgs ba = batch_args(p, B, ws);
+    MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, false, false, true, stream),
+               "batch forces");
+    if (force4) MD_TRY_HIP(launch_gather_user(ba.base, nullptr, nullptr, reinterpret_cast<float4*>(force4), stream), "gather");
+    return MD_OK;
+}
+
+md_status md_batch_step(const md_params* p, const md_replica* reps, int32_t count, void* ws, size_t ws_bytes,
+                        int32_t nsteps, int32_t thermo_every, double* thermo, hipStream_t stream) {
+    BatchPlan B;
+    md_status s = batch_prepare(p, reps, count, ws, ws_bytes, B);
+    if (s != MD_OK) return s;
+    if (nsteps < 0) return fail(MD_ERR_ARG, "nsteps must be >= 0");
+    if (thermo_every < 0) return fail(MD_ERR_ARG, "thermo_every must be >= 0");
+    if (thermo_every > 0 && !thermo) return fail(MD_ERR_ARG, "thermo_every > 0 needs a thermo buffer");
+    return batch_steps(B, batch_args(p, B, ws), nsteps, thermo_every, thermo, stream);
+}
+
+md_status md_batch_energy_virial(const md_params* p, const md_replica* reps, int32_t count, void* ws, size_t ws_bytes,
+                                 double* out, hipStream_t stream) {
+    BatchPlan B;
+    md_status s = batch_prepare(p, reps, count, ws, ws_bytes, B);
+    if (s != MD_OK) return s;
+    if (!out) return fail(MD_ERR_ARG, "output is NULL");
+    const BatchArgs ba = batch_args(p, B, ws);
+    MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, false, true, false, stream),
+               "batch energy pass");
+    MD_TRY_HIP(launch_batch_energy_final(ba.base, ba.reps, B.count, out, stream), "batch energy");
+    return MD_OK;
+}
+
+md_status md_batch_get_state(const md_params* p, const md_replica* reps, int32_t count, const void* ws,
+                             size_t ws_bytes, float* pos4, float* vel4, hipStream_t stream) {
+    BatchPlan B;
+    md_status s = batch_prepare(p, reps, count, ws, ws_bytes, B);
+    if (s != MD_OK) return s;
+    if ((pos4 && !aligned16(pos4)) || (vel4 && !aligned16(vel4)))
+        return fail(MD_ERR_ARG, "particle arrays must be 16-byte aligned");
+    if (!pos4 && !vel4) return MD_OK;
+    const BatchArgs ba = batch_args(p, B, const_cast<void*>(ws));
+    MD_TRY_HIP(launch_gather_user(ba.base, reinterpret_cast<float4*>(pos4), reinterpret_cast<float4*>(vel4), nullptr,
+                                  stream),
+               "gather");
+    return MD_OK;
+}
+
+struct md_graph_s {
+    hipGraphExec_t exec;
+};
+
+md_status md_batch_graph_create(const md_params* p, const md_replica* reps, int32_t count, void* ws, size_t ws_bytes,
+                                int32_t nsteps, int32_t thermo_every, double* thermo, hipStream_t stream,
+                                md_graph* graph_out) {
+    BatchPlan B;
+    md_status s = batch_prepare(p, reps, count, ws, ws_bytes, B);
+    if (s != MD_OK) return s;
+    if (!graph_out) return fail(MD_ERR_ARG, "graph output is NULL");
+    if (!stream) return fail(MD_ERR_ARG, "graph capture needs a non-null stream");
+    if (nsteps < 1) return fail(MD_ERR_ARG, "nsteps must be >= 1");
+    if (thermo_every < 0) return fail(MD_ERR_ARG, "thermo_every must be >= 0");
+    if (thermo_every > 0 && !thermo) return fail(MD_ERR_ARG, "thermo_every > 0 needs a thermo buffer");
+    const BatchArgs ba = batch_args(p, B, ws);
+    MD_TRY_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    s = batch_steps(B, ba, nsteps, thermo_every, thermo, stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(stream, &graph);
+    if (s != MD_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s != MD_OK ? s : hip_fail(e, "end capture");
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return hip_fail(ei, "graph instantiate");
+    md_graph g = new (std::nothrow) md_graph_s{exec};
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        return fail(MD_ERR_ARG, "out of host memory for the graph handle");
+    }
+    *graph_out = g;
+    return MD_OK;
+}
+
+md_status md_graph_launch(md_graph g, hipStream_t stream) {
+    if (!g) return fail(MD_ERR_ARG, "graph is NULL");
+    MD_TRY_HIP(hipGraphLaunch(g->exec, stream), "graph launch");
+    return MD_OK;
+}
+
+md_status md_graph_destroy(md_graph g) {
+    if (!g) return MD_OK;
+    const hipError_t e = hipGraphExecDestroy(g->exec);
+    delete g;
+    if (e != hipSuccess) return hip_fail(e, "graph destroy");
     return MD_OK;
 }
 

@@ -76,6 +76,22 @@ __device__ __forceinline__ int xcd_block_order(int b, int nblocks) {
     return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// Arguments of one replica of a batch: the batch's arrays and shared
+// constants with the replica's geometry and cell offset.
+__device__ __forceinline__ SimArgs replica_view(const SimArgs& base, const Replica& r) {
+    SimArgs a = base;
+    a.n = r.n;
+    a.nc = r.nc;
+    a.ncells = r.ncells;
+    a.cbase = r.cbase;
+    a.tile_cap = r.tile_cap;
+    a.box = r.box;
+    a.s = r.s;
+    a.inv_s = r.inv_s;
+    a.screen2 = r.screen2;
+    return a;
+}
+
 // True if the workspace holds a built state for exactly these arguments
 // (cells built, or forces too when need_forces).
 __device__ __forceinline__ bool state_ok(const SimArgs& a, bool need_forces) {

@@ -39,6 +39,7 @@ struct SimArgs {
     int n;
     int nc;          // cells per dimension
     int ncells;      // nc^3
+    int cbase;       // first cell of this system in the cell arrays (0 unless batched)
     float box;
     float s;         // cell side box / nc
     float inv_s;     // nc / box
@@ -56,6 +57,13 @@ struct SimArgs {
     float dt;
     float hdt_m;     // dt / (2 m)
     float half_m;    // m / 2
+};
+
+// One replica of a batch: its atoms occupy [abase, abase + n) and its cells
+// [cbase, cbase + ncells) of the batch's arrays; geometry as in SimArgs.
+struct Replica {
+    int n, abase, nc, ncells, cbase, tile_cap;
+    float box, s, inv_s, screen2;
 };
 
 // Workspace layout (byte offsets, each 256-byte aligned).
@@ -85,5 +93,17 @@ hipError_t launch_adjoint_kick(const SimArgs& a, const float4* w_user, float4* l
 hipError_t launch_loss_grad(const SimArgs& a, float kcoef, float wcoef, float4* g_r, float4* g_v, double* theta,
                             hipStream_t st);
 hipError_t launch_adjoint_drift(int n, float dt, const float4* lam_r, float4* lam_v, hipStream_t st);
+
+// Batched replicas: base = the batch's arrays and shared constants (n and
+// ncells are the batch totals), reps = device replica table.
+hipError_t launch_batch_setup(const SimArgs& base, const Replica* reps, int* atom_rep, int* cell_rep, int count,
+                              hipStream_t st);
+hipError_t launch_batch_load(const SimArgs& base, const Replica* reps, const int* atom_rep, const float4* pos_in,
+                             const float4* vel_in, hipStream_t st);
+hipError_t launch_batch_integrate(const SimArgs& base, const Replica* reps, const int* atom_rep, hipStream_t st);
+hipError_t launch_batch_scan(const SimArgs& base, const Replica* reps, int count, hipStream_t st);
+hipError_t launch_batch_forces(const SimArgs& base, const Replica* reps, const int* cell_rep, int total_cells,
+                               int max_tile_cap, bool kick, bool energy, bool write_force, hipStream_t st);
+hipError_t launch_batch_energy_final(const SimArgs& base, const Replica* reps, int count, double* out, hipStream_t st);
 
 }  // namespace mdlj

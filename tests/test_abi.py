@@ -121,3 +121,24 @@ def test_status_names():
     assert lib.md_status_name(0) == b"MD_OK"
     assert lib.md_status_name(2) == b"MD_ERR_BOX"
     assert lib.md_status_name(99) == b"MD_UNKNOWN"
+
+
+def test_batch_validation_on_host():
+    import ctypes
+
+    lib = _lib.lib()
+    p = md.make_params(1, 1.0)
+    ok = _lib.replica_table([(100, 10.0), (4000, 16.8)])
+    bad = _lib.replica_table([(100, 10.0), (50, 4.0)])
+    assert lib.md_batch_workspace_bytes(ctypes.byref(p), ok, 2) > 0
+    assert lib.md_batch_workspace_bytes(ctypes.byref(p), bad, 2) == 0
+    assert lib.md_batch_build(ctypes.byref(p), bad, 2, None, 0, None, None, None) == _lib.MD_ERR_BOX
+    assert b"replica 1" in lib.md_last_error()
+    assert lib.md_batch_workspace_bytes(ctypes.byref(p), ok, 0) == 0
+    g = ctypes.c_void_p()
+    need = lib.md_batch_workspace_bytes(ctypes.byref(p), ok, 2)
+    fake = ctypes.c_void_p(1 << 40)
+    # a null stream cannot be captured: refused before any HIP call
+    assert lib.md_batch_graph_create(ctypes.byref(p), ok, 2, fake, need, 10, 0, None, None, ctypes.byref(g)) \
+        == _lib.MD_ERR_ARG
+    assert lib.md_graph_destroy(None) == 0
