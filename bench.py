@@ -41,7 +41,63 @@ def parse():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device-to-device copy of this size (HBM counter calibration)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint throughput leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-replica throughput leg")
     return ap.parse_args()
+
+
+def batched_leg(torch, nsteps=200, seq_steps=20):
+    """512 replicas (N = 4 n^3, n uniform in [5, 20], rho in [0.70, 0.95],
+    T* in [0.7, 1.5]) advanced nsteps steps by one launch of a captured graph,
+    against the same replicas run one after another with md_step."""
+    import numpy as np
+
+    import ljsynth
+    from paper_0709_3225_amd import BatchedLJ, LJSystem
+
+    ws = ljsynth.batched_replicas(512, 4)
+    states = [ljsynth.make_state(w) for w in ws]
+    table = [(w.n, box) for w, (_, _, box) in zip(ws, states)]
+    pos = torch.from_numpy(np.concatenate([s[0] for s in states])).cuda()
+    vel = torch.from_numpy(np.concatenate([s[1] for s in states])).cuda()
+    b = BatchedLJ(table)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        b.load(pos, vel)
+        graph, _ = b.make_graph(nsteps)
+        graph.launch()  # warm
+    stream.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    graph.launch(stream)
+    e1.record(stream)
+    stream.synchronize()
+    t_batch = max(time.perf_counter() - t0, e0.elapsed_time(e1) / 1e3)
+    graph.close()
+    b.check()
+    # the same replicas one after another (md_step per replica)
+    solos = []
+    for (n, box), (p4, v4, _) in zip(table, states):
+        s = LJSystem(n, box)
+        s.load(torch.from_numpy(p4).cuda(), torch.from_numpy(v4).cuda())
+        solos.append(s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in solos:
+        s.step(seq_steps)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    for s in solos[:4]:
+        s.check()
+    ntot = b.n_total
+    value = ntot * nsteps / t_batch
+    seq = ntot * seq_steps / t_seq
+    return {
+        "workload": f"512 replicas, N = 4 n^3 with n uniform in [5, 20] (total {ntot} atoms), rho in [0.70, 0.95], "
+                    f"T* in [0.7, 1.5], {nsteps} steps in one graph launch",
+        "value": value, "unit": "atom-steps/s", "ms_per_launch": t_batch * 1e3,
+        "sequential_value": seq, "ratio_vs_sequential": value / seq,
+    }
 
 
 def adjoint_leg(torch):
@@ -100,7 +156,8 @@ def algorithmic_force_flops(sys_, torch):
     return candidates, accepted, FLOP_PER_CANDIDATE * candidates + FLOP_PER_ACCEPTED * accepted
 
 
-FORCE_SOURCES = ("paper_0709_3225_amd/csrc/forces.hip", "paper_0709_3225_amd/csrc/md_device.h",
+FORCE_SOURCES = ("paper_0709_3225_amd/csrc/forces.hip", "paper_0709_3225_amd/csrc/cell_pairs.h",
+                 "paper_0709_3225_amd/csrc/md_device.h",
                  "paper_0709_3225_amd/csrc/md_internal.h")
 
 
@@ -270,6 +327,10 @@ def main():
         out["copy_calibration_bytes"] = nbytes
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(torch)
+        out["adjoint"]["ratio_vs_plain_headline"] = out["adjoint"]["value"] / value
+    if not args.no_batched:
+        out["batched"] = batched_leg(torch)
+        out["batched"]["ratio_vs_plain_headline"] = out["batched"]["value"] / value
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s.state()[0].cpu().numpy(), box, args.cpu_seconds)
     print(json.dumps(out), flush=True)
