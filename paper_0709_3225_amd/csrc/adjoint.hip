@@ -112,9 +112,9 @@ __global__ void __launch_bounds__(kWave)
     const int c = xcd_block_order(blockIdx.x, a.ncells);
     float ox, oy, oz;
     load_neighbourhood(a, c, nb, ox, oy, oz);
-    const int total = nb.pref[27];
-    const int home_first = nb.first[13];
-    const int n_home = nb.pref[14] - nb.pref[13];
+    const int total = nb.total;
+    const int home_first = nb.home_first;
+    const int n_home = nb.n_home;
     const float inv_sig = 1.0f / sqrtf(a.sig2);
     const float inv_eps = 24.0f / a.eps24;
 
@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(kWave)
             }
             __syncthreads();
             const int groups_all = (tn + ns - 1) / ns;
-            const int self_t = nb.pref[13] + h0 + h - t0;
+            const int self_t = nb.home_pos + h0 + h - t0;
             for (int g0 = 0; g0 < groups_all; g0 += kGroups) {
                 const int groups = min(kGroups, groups_all - g0);
                 const int first = g0 * ns + (act ? s : 0);

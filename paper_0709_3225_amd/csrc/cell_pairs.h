@@ -11,10 +11,22 @@ namespace {
 
 constexpr int kTile = 1024;  // staged atoms per LDS pass of the neighbour export (16 KiB)
 
+// The 27-cell neighbourhood of a home cell as runs of memory-contiguous cells
+// that share one image shift ("segments"): the three cells of an x-row are
+// consecutive in the sorted arrays unless the row wraps around the box in x,
+// so an interior home cell has 9 segments and a cell on an x face 27 (one per
+// cell). Segments list the cells in the order dx, dy, dz (dx fastest) and
+// tile the neighbourhood index range [0, total) in that order.
 struct Neighbourhood {
-    int pref[28];   // exclusive prefix of the 27 cell counts; pref[27] = total
-    int first[27];  // first sorted slot of each neighbour cell
-    float bx[27], by[27], bz[27];  // frame offset o - sh of each neighbour cell
+    int total;       // atoms in the 27 cells
+    int home_pos;    // neighbourhood index of the home cell's first atom
+    int home_first;  // its sorted slot
+    int n_home;
+    int nseg;
+    int seg_pos[27];    // neighbourhood index of the segment's first atom
+    int seg_first[27];  // its sorted slot
+    int seg_len[27];
+    float sx[27], sy[27], sz[27];  // frame offset o - sh of the segment's cells
 };
 
 // Fill the neighbourhood table of home cell c (lanes 0..26 one cell each).
@@ -38,52 +50,101 @@ __device__ __forceinline__ void load_neighbourhood(const SimArgs& a, int c, Neig
         cnt = a.start[cj + 1] - first;
     }
     const int incl = wave_incl_scan(cnt);
-    if (lane < 27) {
-        nb.pref[lane] = incl - cnt;
-        nb.first[lane] = first;
-        nb.bx[lane] = bx;
-        nb.by[lane] = by;
-        nb.bz[lane] = bz;
+    const int pos = incl - cnt;
+    const bool rows = ix >= 1 && ix <= nc - 2;  // uniform: x-rows are contiguous, unshifted in x
+    const int row_end = __shfl(incl, lane + 2 < kWave ? lane + 2 : lane);
+    if (rows) {
+        if (lane < 27 && lane % 3 == 0) {
+            const int r = lane / 3;
+            nb.seg_pos[r] = pos;
+            nb.seg_first[r] = first;
+            nb.seg_len[r] = row_end - pos;
+            nb.sx[r] = bx;
+            nb.sy[r] = by;
+            nb.sz[r] = bz;
+        }
+    } else if (lane < 27) {
+        nb.seg_pos[lane] = pos;
+        nb.seg_first[lane] = first;
+        nb.seg_len[lane] = cnt;
+        nb.sx[lane] = bx;
+        nb.sy[lane] = by;
+        nb.sz[lane] = bz;
     }
-    if (lane == 26) nb.pref[27] = incl;
+    if (lane == 13) {
+        nb.home_pos = pos;
+        nb.home_first = first;
+        nb.n_home = cnt;
+    }
+    if (lane == 26) nb.total = incl;
+    if (lane == 0) nb.nseg = rows ? 9 : 27;
     __syncthreads();
+}
+
+__device__ __forceinline__ int lane_value(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float lane_value(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
 // Stage neighbourhood atoms [t0, t0 + tn) into the tile, frame-translated.
 // w carries the user index (ID_IN_W) or |x|^2 in the frame (for the screen).
-// With WITH_VEC the matching entries of a per-atom vector (sorted
-// order) are copied into vtile as well. Loads are issued four per lane before
-// their LDS stores, so a wavefront waits on global memory about tn / 256
-// times instead of tn / 64.
+// With WITH_VEC the matching entries of a per-atom vector (sorted order) are
+// copied into vtile as well. A uniform cursor walks the segments in chunks of
+// at most one wavefront; the segment table sits in lanes 0..nseg-1 and is read
+// with readlane, and kBatch chunks have their loads in flight before the LDS
+// stores, so an interior cell's neighbourhood costs one global round trip.
 template <bool ID_IN_W, bool WITH_VEC = false>
 __device__ __forceinline__ void stage_tile(const SimArgs& a, const Neighbourhood& nb, float4* tile,
                                            int t0, int tn, const float4* vec = nullptr,
                                            float4* vtile = nullptr) {
-    constexpr int kBatch = 4;
-    for (int t = threadIdx.x; t < tn; t += kWave * kBatch) {
+    constexpr int kBatch = WITH_VEC ? 5 : 9;  // chunks in flight (register budget)
+    const int lane = threadIdx.x;
+    const int nseg = nb.nseg;
+    int s_pos = 0, s_first = 0, s_len = 0;
+    float s_x = 0.f, s_y = 0.f, s_z = 0.f;
+    if (lane < nseg) {
+        s_pos = nb.seg_pos[lane];
+        s_first = nb.seg_first[lane];
+        s_len = nb.seg_len[lane];
+        s_x = nb.sx[lane];
+        s_y = nb.sy[lane];
+        s_z = nb.sz[lane];
+    }
+    const int t1 = t0 + tn;
+    int sg = 0;  // uniform cursor: segment sg, neighbourhood index g
+    while (sg < nseg && lane_value(s_pos, sg) + lane_value(s_len, sg) <= t0) ++sg;
+    int g = t0;
+    while (g < t1 && sg < nseg) {
         float4 q[kBatch], vq[kBatch];
-        int kk[kBatch];
+        int dst[kBatch], seg[kBatch];
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const int tt = t + u * kWave;
-            const int g = t0 + (tt < tn ? tt : 0);
-            int k = 0;  // largest k with pref[k] <= g
-#pragma unroll
-            for (int step = 16; step > 0; step >>= 1)
-                if (k + step < 27 && nb.pref[k + step] <= g) k += step;
-            kk[u] = k;
-            const int slot = nb.first[k] + (g - nb.pref[k]);
+            dst[u] = -1;
+            seg[u] = 0;
+            int slot = 0;  // lanes without an atom load slot 0 (always valid) and store nothing
+            if (g < t1 && sg < nseg) {
+                const int p = lane_value(s_pos, sg), end = p + lane_value(s_len, sg);
+                const int ce = min(min(g + kWave, end), t1);
+                const int my = g + lane;
+                if (my < ce) {
+                    slot = lane_value(s_first, sg) + (my - p);
+                    dst[u] = my - t0;
+                }
+                seg[u] = sg;
+                g = ce;
+                if (g >= end) ++sg;
+            }
             q[u] = a.pos0[slot];
             if (WITH_VEC) vq[u] = vec[slot];
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
-            const int tt = t + u * kWave;
-            if (tt < tn) {
-                const int k = kk[u];
-                const float x = q[u].x - nb.bx[k], y = q[u].y - nb.by[k], z = q[u].z - nb.bz[k];
-                tile[tt] = make_float4(x, y, z, ID_IN_W ? q[u].w : x * x + y * y + z * z);
-                if (WITH_VEC) vtile[tt] = vq[u];
+            if (dst[u] >= 0) {
+                const float x = q[u].x - lane_value(s_x, seg[u]);
+                const float y = q[u].y - lane_value(s_y, seg[u]);
+                const float z = q[u].z - lane_value(s_z, seg[u]);
+                tile[dst[u]] = make_float4(x, y, z, ID_IN_W ? q[u].w : x * x + y * y + z * z);
+                if (WITH_VEC) vtile[dst[u]] = vq[u];
             }
         }
     }
@@ -168,7 +229,9 @@ __device__ __forceinline__ void walk_bits(int ns, uint32_t m, uint32_t n1, uint3
         const uint32_t k = live ? __builtin_clz(m) : 0u;
         m &= ~(0x80000000u >> k);
         left -= live ? 1u : 0u;
-        op(wb + k * cstep, live);
+        // a spent lane keeps rotating (wb grows past its span): it reads its
+        // span's first candidate instead, which is always staged
+        op(live ? wb + k * cstep : 0u, live);
     } while (__any(left != 0u));
 }
 

@@ -3,13 +3,15 @@
 // drift that feeds it (section 2).
 //
 // One build is four launches, all HBM/L2-bound streaming passes:
-//   load or integrate : wrap + cell index + histogram rank (one atomic per
-//                       run of equal cells in a wavefront)
-//   scan              : exclusive prefix of the histogram -> cell offsets;
-//                       clears the histogram for the next build
-//   scatter           : key[offset + rank] = staging slot
-//   cell order        : one wavefront per cell orders its members by user
-//                       index and moves them into the sorted arrays
+//   load or drift : wrap + cell index + histogram rank (one atomic per run of
+//                   equal cells in a wavefront); inside a multi-step run the
+//                   force kernel's epilogue does this for every step after
+//                   the first, and the drift kernel only starts a run
+//   scan          : exclusive prefix of the histogram -> cell offsets;
+//                   clears the histogram for the next build
+//   scatter       : key[offset + rank] = staging slot
+//   cell order    : a 16-lane group per cell orders its members by user
+//                   index and moves them into the sorted arrays
 // The paper updated each cell with one serial thread per cell (section 3.1);
 // a counting sort has no serial part and no capacity per cell.
 #include "md_device.h"
@@ -62,31 +64,17 @@ __device__ __forceinline__ void load_atom(const SimArgs& a, int i, bool valid, c
     }
 }
 
-// Velocity-Verlet first half for sorted slot i: v += dt/(2m) F, r += dt v,
-// wrap, then the histogram rank for the rebuild. Reads the sorted state,
-// writes staging. Called by every lane of the wave.
+// Velocity-Verlet first half for sorted slot i (half kick, drift, wrap),
+// then the histogram rank for the rebuild. Reads the sorted state, writes
+// staging. Called by every lane of the wave.
 __device__ __forceinline__ void integrate_atom(const SimArgs& a, int i, bool valid) {
-    const float invL = 1.0f / a.box;
     int c = -1;
     float4 p = make_float4(0.f, 0.f, 0.f, 0.f), v = p;
     if (valid) {
         p = a.pos0[i];
         v = a.vel0[i];
         const float4 f = a.force[i];
-        v.x += a.hdt_m * f.x;
-        v.y += a.hdt_m * f.y;
-        v.z += a.hdt_m * f.z;
-        p.x += a.dt * v.x;
-        p.y += a.dt * v.y;
-        p.z += a.dt * v.z;
-        if (!finite3(p.x, p.y, p.z)) {
-            atomicOr(&a.hdr[HDR_ERROR], DEV_NONFINITE);
-            p.x = p.y = p.z = 0.f;
-        }
-        p.x = wrap_coord(p.x, a.box, invL);
-        p.y = wrap_coord(p.y, a.box, invL);
-        p.z = wrap_coord(p.z, a.box, invL);
-        c = a.cbase + cell_index(p.x, p.y, p.z, a);
+        c = half_kick_drift(a, p, v, f.x, f.y, f.z);
     }
     const int r = histogram_rank(a.count, c);
     if (valid) {
@@ -190,94 +178,189 @@ __global__ void __launch_bounds__(kBlock) k_batch_scan(SimArgs base, const Repli
 }
 
 // Exclusive prefix scan of the histogram into start[0..ncells], by one
-// workgroup of 1024 lanes walking the histogram in tiles of 4096 cells:
-// per-lane sums of four cells, a wavefront scan, a scan of the 16 wave totals,
-// and a running carry. Clears the histogram behind it.
+// workgroup of 1024 lanes. One workgroup runs on one CU, whose memory pipeline
+// serves a few cache lines per clock, so every global access here is a
+// coalesced int4 (consecutive lanes, consecutive 16 bytes) and the transpose
+// to "each lane owns 4 kScanVec consecutive cells" goes through LDS. Per tile of
+// 4096 kScanVec cells: coalesced loads into LDS, per-lane sums, a wavefront
+// scan and a scan of the 16 wave totals, exclusive offsets back into LDS,
+// coalesced stores of the offsets and of zeros into the histogram (cleared
+// for the next build). A carry links the tiles.
 constexpr int kScanBlock = 1024;
+constexpr int kScanVec = 3;                       // int4 per lane per tile
+constexpr int kScanTile = kScanBlock * 4 * kScanVec;  // 12288 cells, 48 KiB of LDS
 __global__ void __launch_bounds__(kScanBlock) k_scan(SimArgs a, bool from_step) {
-    if (from_step && (a.hdr[HDR_ERROR] & DEV_ORDER)) return;
+    __shared__ int4 buf[kScanTile / 4];
     __shared__ int wave_tot[kScanBlock / kWave];
+    const int err = a.hdr[HDR_ERROR];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int nc = a.ncells;
     int carry = 0;
-    for (int base = 0; base < a.ncells; base += kScanBlock * 4) {
-        const int c0 = base + tid * 4;
-        int v0 = 0, v1 = 0, v2 = 0, v3 = 0;
-        if (c0 + 3 < a.ncells) {
-            const int4 v = *reinterpret_cast<const int4*>(a.count + c0);
-            v0 = v.x; v1 = v.y; v2 = v.z; v3 = v.w;
-        } else {
-            if (c0 < a.ncells) v0 = a.count[c0];
-            if (c0 + 1 < a.ncells) v1 = a.count[c0 + 1];
-            if (c0 + 2 < a.ncells) v2 = a.count[c0 + 2];
+    for (int base = 0; base < nc; base += kScanTile) {
+        int4 v[kScanVec];
+#pragma unroll
+        for (int q = 0; q < kScanVec; ++q) {
+            const int c = base + 4 * (q * kScanBlock + tid);
+            if (c + 3 < nc) {
+                v[q] = *reinterpret_cast<const int4*>(a.count + c);
+            } else {
+                v[q].x = c < nc ? a.count[c] : 0;
+                v[q].y = c + 1 < nc ? a.count[c + 1] : 0;
+                v[q].z = c + 2 < nc ? a.count[c + 2] : 0;
+                v[q].w = 0;
+            }
         }
-        const int tsum = v0 + v1 + v2 + v3;
+        if (from_step && (err & DEV_ORDER)) return;  // uniform over the workgroup
+#pragma unroll
+        for (int q = 0; q < kScanVec; ++q) buf[q * kScanBlock + tid] = v[q];
+        __syncthreads();
+        // this lane's cells: tile entries kScanVec * tid .. + kScanVec - 1
+        int4 w[kScanVec];
+        int tsum = 0;
+#pragma unroll
+        for (int q = 0; q < kScanVec; ++q) {
+            w[q] = buf[kScanVec * tid + q];
+            tsum += w[q].x + w[q].y + w[q].z + w[q].w;
+        }
         const int incl = wave_incl_scan(tsum);
         if (lane == kWave - 1) wave_tot[wave] = incl;
         __syncthreads();
         int wave_off = 0, tile_tot = 0;
-        for (int w = 0; w < kScanBlock / kWave; ++w) {
-            const int t = wave_tot[w];
-            if (w < wave) wave_off += t;
+#pragma unroll
+        for (int k = 0; k < kScanBlock / kWave; ++k) {
+            const int t = wave_tot[k];
+            if (k < wave) wave_off += t;
             tile_tot += t;
         }
-        const int excl = carry + wave_off + incl - tsum;
-        if (c0 + 3 < a.ncells) {
-            *reinterpret_cast<int4*>(a.start + c0) = make_int4(excl, excl + v0, excl + v0 + v1, excl + v0 + v1 + v2);
-            *reinterpret_cast<int4*>(a.count + c0) = make_int4(0, 0, 0, 0);
-        } else {
-            if (c0 < a.ncells) { a.start[c0] = excl; a.count[c0] = 0; }
-            if (c0 + 1 < a.ncells) { a.start[c0 + 1] = excl + v0; a.count[c0 + 1] = 0; }
-            if (c0 + 2 < a.ncells) { a.start[c0 + 2] = excl + v0 + v1; a.count[c0 + 2] = 0; }
+        int run = carry + wave_off + incl - tsum;
+#pragma unroll
+        for (int q = 0; q < kScanVec; ++q) {
+            const int s0 = run, s1 = s0 + w[q].x, s2 = s1 + w[q].y, s3 = s2 + w[q].z;
+            run = s3 + w[q].w;
+            buf[kScanVec * tid + q] = make_int4(s0, s1, s2, s3);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kScanVec; ++q) {
+            const int c = base + 4 * (q * kScanBlock + tid);
+            const int4 o = buf[q * kScanBlock + tid];
+            if (c + 3 < nc) {
+                *reinterpret_cast<int4*>(a.start + c) = o;
+                *reinterpret_cast<int4*>(a.count + c) = make_int4(0, 0, 0, 0);
+            } else {
+                if (c < nc) { a.start[c] = o.x; a.count[c] = 0; }
+                if (c + 1 < nc) { a.start[c + 1] = o.y; a.count[c + 1] = 0; }
+                if (c + 2 < nc) { a.start[c + 2] = o.z; a.count[c + 2] = 0; }
+            }
         }
         carry += tile_tot;
         __syncthreads();
     }
-    if (tid == 0) a.start[a.ncells] = carry;
+    if (tid == 0) a.start[nc] = carry;
 }
 
+// The error word is read alongside the kernels' first loads (not before them),
+// so a pending order error costs no extra memory round trip; nothing is
+// written, and nothing is read through a loaded index, once it is seen.
 __global__ void __launch_bounds__(kBlock) k_scatter(SimArgs a, bool from_step) {
-    if (from_step && (a.hdr[HDR_ERROR] & DEV_ORDER)) return;
+    const int err = a.hdr[HDR_ERROR];
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < a.n) a.key[a.start[a.cell[i]] + a.rank[i]] = i;
+    int c = 0, r = 0;
+    if (i < a.n) {
+        c = a.cell[i];
+        r = a.rank[i];
+    }
+    if (from_step && (err & DEV_ORDER)) return;
+    if (i < a.n) a.key[a.start[c] + r] = i;
 }
 
-// One wavefront per cell: rank every member by user index among the cell's
-// members (ids are unique), then move position and velocity to
-// start + rank. Chunks of 64 members; ids of other chunks are fetched and
-// broadcast lane by lane.
-__global__ void __launch_bounds__(kWave) k_cell_order(SimArgs a, bool from_step) {
-    if (from_step && (a.hdr[HDR_ERROR] & DEV_ORDER)) return;
-    const int c = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int first = a.start[c];
-    const int n = a.start[c + 1] - first;
-    for (int m0 = 0; m0 < n; m0 += kWave) {
-        const int m = m0 + lane;
-        const bool act = m < n;
-        float4 p = make_float4(0.f, 0.f, 0.f, 0.f), v = p;
-        if (act) {
-            const int src = a.key[first + m];
-            p = a.pos1[src];
-            v = a.vel1[src];
+// In-cell order: the members of cell c (staging slots key[start .. start + n))
+// are ranked by user index and moved to pos0/vel0[start + rank], which makes
+// the sorted layout independent of the arrival order of the histogram
+// atomics. One 16-lane group per cell, 16 cells per workgroup; a lane holds
+// two members (sub and sub + 16) of each 32-member window. A member's rank
+// counts the smaller indices of its cell: each window's indices are put in
+// LDS and every lane reads them back four at a time (a broadcast within the
+// group). Loop bounds are the workgroup's largest cell, so the barriers are
+// uniform.
+constexpr int kOrderBlock = 256;
+constexpr int kOrderGroup = 16;
+constexpr int kOrderWin = 2 * kOrderGroup;
+constexpr int kOrderCells = kOrderBlock / kOrderGroup;
+constexpr int kNoId = 0x7fffffff;  // larger than any user index
+
+__device__ __forceinline__ int staged_id(const SimArgs& a, int first, int m, int n) {
+    return m < n ? __float_as_int(a.pos1[a.key[first + m]].w) : kNoId;
+}
+
+__device__ __forceinline__ int count_below(int4 k, int id) {
+    return (k.x < id ? 1 : 0) + (k.y < id ? 1 : 0) + (k.z < id ? 1 : 0) + (k.w < id ? 1 : 0);
+}
+
+__global__ void __launch_bounds__(kOrderBlock) k_cell_order(SimArgs a, bool from_step) {
+    __shared__ int4 win[kOrderCells][kOrderWin / 4];
+    __shared__ int wave_max[kOrderBlock / kWave];
+    const int err = a.hdr[HDR_ERROR];
+    const int cl = threadIdx.x / kOrderGroup;
+    const int c = blockIdx.x * kOrderCells + cl;
+    const int sub = threadIdx.x & (kOrderGroup - 1);
+    int first = 0, n = 0;
+    if (c < a.ncells) {
+        first = a.start[c];
+        n = a.start[c + 1] - first;
+    }
+    if (from_step && (err & DEV_ORDER)) return;  // uniform over the workgroup
+    int nmax = max(n, __shfl_xor(n, 16));
+    nmax = max(nmax, __shfl_xor(nmax, 32));
+    if ((threadIdx.x & (kWave - 1)) == 0) wave_max[threadIdx.x / kWave] = nmax;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < kOrderBlock / kWave; ++w) nmax = max(nmax, wave_max[w]);
+    int* wids = reinterpret_cast<int*>(win[cl]);
+    for (int m0 = 0; m0 < nmax; m0 += kOrderWin) {
+        const int ma = m0 + sub, mb = ma + kOrderGroup;
+        float4 pa = make_float4(0.f, 0.f, 0.f, 0.f), va = pa, pb = pa, vb = pa;
+        int ida = kNoId, idb = kNoId;
+        if (ma < n) {
+            const int src = a.key[first + ma];
+            pa = a.pos1[src];
+            va = a.vel1[src];
+            ida = __float_as_int(pa.w);
         }
-        const int myid = act ? __float_as_int(p.w) : 0x7fffffff;
-        int r = 0;
-        for (int k0 = 0; k0 < n; k0 += kWave) {
-            int kid;
-            if (k0 == m0) {
-                kid = myid;
-            } else {
-                kid = (k0 + lane < n) ? __float_as_int(a.pos1[a.key[first + k0 + lane]].w) : 0x7fffffff;
+        if (mb < n) {
+            const int src = a.key[first + mb];
+            pb = a.pos1[src];
+            vb = a.vel1[src];
+            idb = __float_as_int(pb.w);
+        }
+        int ra = 0, rb = 0;
+        for (int k0 = 0; k0 < nmax; k0 += kOrderWin) {
+            int ka = ida, kb = idb;
+            if (k0 != m0) {
+                ka = staged_id(a, first, k0 + sub, n);
+                kb = staged_id(a, first, k0 + kOrderGroup + sub, n);
             }
-            const int kn = min(kWave, n - k0);
-            for (int l = 0; l < kn; ++l) r += (__shfl(kid, l) < myid) ? 1 : 0;
+            __syncthreads();  // the previous window has been read
+            wids[sub] = ka;
+            wids[kOrderGroup + sub] = kb;
+            __syncthreads();
+            const int kn = min(kOrderWin, nmax - k0);
+            for (int l = 0; l < kn; l += 4) {
+                const int4 k4 = win[cl][l / 4];
+                ra += count_below(k4, ida);
+                rb += count_below(k4, idb);
+            }
         }
-        if (act) {
-            a.pos0[first + r] = p;
-            a.vel0[first + r] = v;
+        if (ma < n) {
+            a.pos0[first + ra] = pa;
+            a.vel0[first + ra] = va;
+        }
+        if (mb < n) {
+            a.pos0[first + rb] = pb;
+            a.vel0[first + rb] = vb;
         }
     }
-    if (c == 0 && lane == 0 && !from_step) a.hdr[HDR_STATE] = STATE_CELLS;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !from_step) a.hdr[HDR_STATE] = STATE_CELLS;
 }
 
 __global__ void __launch_bounds__(kBlock) k_gather_user(SimArgs a, float4* pos_out, float4* vel_out,
@@ -344,7 +427,8 @@ hipError_t launch_scatter(const SimArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_cell_order(const SimArgs& a, bool from_step, hipStream_t st) {
-    hipLaunchKernelGGL(k_cell_order, dim3(a.ncells), dim3(kWave), 0, st, a, from_step);
+    hipLaunchKernelGGL(k_cell_order, dim3(blocks_for(a.ncells, kOrderCells)), dim3(kOrderBlock), 0, st, a,
+                       from_step);
     return hipGetLastError();
 }
 

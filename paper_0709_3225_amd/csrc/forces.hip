@@ -62,14 +62,19 @@ struct ForceOp {
 
 // Forces on the atoms of home cell c (local index of the system described by
 // a); one wavefront. Energy partials go to a.epart[3 (a.cbase + c) + 0..2].
-template <bool KICK, bool ENERGY, bool WRITE>
+// KICK completes the step's velocity (v += dt/(2m) F). DRIFT (with KICK) goes
+// on into the next step's first half with the same force, as the drift kernel
+// would (half kick, drift, wrap, cell, histogram rank), and writes the staging
+// arrays for the next rebuild instead of vel0; force and vel0 are then left
+// stale, since the rebuild replaces the sorted state.
+template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT>
 __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile, Neighbourhood& nb, float* red) {
     const int lane = threadIdx.x;
     float ox, oy, oz;
     load_neighbourhood(a, c, nb, ox, oy, oz);
-    const int total = nb.pref[27];
-    const int home_first = nb.first[13];
-    const int n_home = nb.pref[14] - nb.pref[13];
+    const int total = nb.total;
+    const int home_first = nb.home_first;
+    const int n_home = nb.n_home;
 
     double u_acc = 0.0, w_acc = 0.0, k_acc = 0.0;
     bool bad = false;
@@ -80,6 +85,8 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         const bool act = s < ns;
         float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
         if (act) pi = a.pos0[home_first + h0 + h];
+        float4 vel = make_float4(0.f, 0.f, 0.f, 0.f);  // fetched now, used by the epilogue
+        if ((KICK || ENERGY) && s == 0) vel = a.vel0[home_first + h0 + h];
         const float xi = pi.x - ox, yi = pi.y - oy, zi = pi.z - oz;
         const float ai = fmaf(zi, zi, fmaf(yi, yi, xi * xi));
         // idle lanes get a bound no candidate can meet (q.w - thr_i = +inf)
@@ -93,7 +100,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
             for (int t = lane; t < kTilePad; t += kWave) tile[tn + t] = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
             __syncthreads();
             const int groups_all = (tn + ns - 1) / ns;  // candidates of the largest slice
-            const int self_t = nb.pref[13] + h0 + h - t0;  // the home atom's own tile index (may be outside)
+            const int self_t = nb.home_pos + h0 + h - t0;  // the home atom's own tile index (may be outside)
             for (int g0 = 0; g0 < groups_all; g0 += kGroups) {
                 const int groups = min(kGroups, groups_all - g0);
                 const int first = g0 * ns + (act ? s : 0);
@@ -127,6 +134,9 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
             red[4 * kWave + lane] = w_loc;
         }
         __syncthreads();
+        const int k = home_first + h0 + h;
+        int c_next = -1;  // DRIFT: the home atom's next cell, -1 on lanes without one
+        float4 p_next = pi, v_next = make_float4(0.f, 0.f, 0.f, 0.f);
         if (s == 0) {
             float gx = 0.f, gy = 0.f, gz = 0.f, gu = 0.f, gw = 0.f;
             for (int q = 0; q < ns; ++q) {
@@ -139,16 +149,15 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                     gw += red[4 * kWave + l];
                 }
             }
-            const int k = home_first + h0 + h;
             if (!finite3(gx, gy, gz)) bad = true;
             if (WRITE) a.force[k] = make_float4(gx, gy, gz, 0.f);
             if (KICK || ENERGY) {
-                float4 v = a.vel0[k];
+                float4 v = vel;
                 if (KICK) {
                     v.x += a.hdt_m * gx;
                     v.y += a.hdt_m * gy;
                     v.z += a.hdt_m * gz;
-                    a.vel0[k] = v;
+                    if (!DRIFT) a.vel0[k] = v;
                 }
                 if (ENERGY) {
                     u_acc += static_cast<double>(gu);
@@ -157,6 +166,19 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                                                               static_cast<double>(v.y) * v.y +
                                                               static_cast<double>(v.z) * v.z);
                 }
+                if (DRIFT) {
+                    v_next = v;
+                    c_next = half_kick_drift(a, p_next, v_next, gx, gy, gz);
+                }
+            }
+        }
+        if (DRIFT) {
+            const int r = histogram_rank(a.count, c_next);  // all lanes
+            if (c_next >= 0) {
+                a.pos1[k] = p_next;
+                a.vel1[k] = v_next;
+                a.cell[k] = c_next;
+                a.rank[k] = r;
             }
         }
     }
@@ -174,7 +196,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
     }
 }
 
-template <bool KICK, bool ENERGY, bool WRITE>
+template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT>
 __global__ void __launch_bounds__(kWave) k_forces(SimArgs a, bool from_step) {
     if (from_step) {
         if (a.hdr[HDR_ERROR] & DEV_ORDER) return;
@@ -185,13 +207,13 @@ __global__ void __launch_bounds__(kWave) k_forces(SimArgs a, bool from_step) {
     extern __shared__ float4 tile[];  // a.tile_cap + kTilePad entries
     __shared__ Neighbourhood nb;
     __shared__ float red[5 * kWave];
-    force_cell<KICK, ENERGY, WRITE>(a, xcd_block_order(blockIdx.x, a.ncells), tile, nb, red);
+    force_cell<KICK, ENERGY, WRITE, DRIFT>(a, xcd_block_order(blockIdx.x, a.ncells), tile, nb, red);
     if (WRITE && blockIdx.x == 0 && threadIdx.x == 0) a.hdr[HDR_STATE] = STATE_FORCES;
 }
 
 // Batched forces: one workgroup per cell of any replica (global cell index,
 // XCD-ordered); the replica's own geometry comes from its descriptor.
-template <bool KICK, bool ENERGY, bool WRITE>
+template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT>
 __global__ void __launch_bounds__(kWave)
     k_batch_forces(SimArgs base, const Replica* __restrict__ reps, const int* __restrict__ cell_rep, int total_cells) {
     if (base.hdr[HDR_ERROR] & DEV_ORDER) return;
@@ -200,7 +222,7 @@ __global__ void __launch_bounds__(kWave)
     __shared__ float red[5 * kWave];
     const int gc = xcd_block_order(blockIdx.x, total_cells);
     const SimArgs a = replica_view(base, reps[cell_rep[gc]]);
-    force_cell<KICK, ENERGY, WRITE>(a, gc - a.cbase, tile, nb, red);
+    force_cell<KICK, ENERGY, WRITE, DRIFT>(a, gc - a.cbase, tile, nb, red);
     if (WRITE && blockIdx.x == 0 && threadIdx.x == 0) base.hdr[HDR_STATE] = STATE_FORCES;
 }
 
@@ -282,9 +304,9 @@ __global__ void __launch_bounds__(kWave) k_neighbors(SimArgs a, int* counts, int
     const int c = blockIdx.x;
     float ox, oy, oz;
     load_neighbourhood(a, c, nb, ox, oy, oz);
-    const int total = nb.pref[27];
-    const int home_first = nb.first[13];
-    const int n_home = nb.pref[14] - nb.pref[13];
+    const int total = nb.total;
+    const int home_first = nb.home_first;
+    const int n_home = nb.n_home;
     bool overflow = false;
     for (int h0 = 0; h0 < n_home; h0 += kWave) {
         const int h = h0 + lane;
@@ -319,21 +341,25 @@ __global__ void __launch_bounds__(kWave) k_neighbors(SimArgs a, int* counts, int
 
 }  // namespace
 
-hipError_t launch_forces(const SimArgs& a, bool kick, bool energy, bool write_force, bool from_step,
+hipError_t launch_forces(const SimArgs& a, bool kick, bool energy, bool write_force, bool from_step, bool drift,
                          hipStream_t st) {
     const dim3 g(a.ncells), b(kWave);
     const size_t lds = sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
-    if (kick && energy && write_force) {
-        hipLaunchKernelGGL((k_forces<true, true, true>), g, b, lds, st, a, from_step);
-    } else if (kick && !energy && write_force) {
-        hipLaunchKernelGGL((k_forces<true, false, true>), g, b, lds, st, a, from_step);
-    } else if (!kick && energy && !write_force) {
-        hipLaunchKernelGGL((k_forces<false, true, false>), g, b, lds, st, a, from_step);
-    } else if (!kick && !energy && write_force) {
-        hipLaunchKernelGGL((k_forces<false, false, true>), g, b, lds, st, a, from_step);
+#define MD_FORCES(K, E, W, D) hipLaunchKernelGGL((k_forces<K, E, W, D>), g, b, lds, st, a, from_step)
+    if (kick && drift && !write_force) {
+        if (energy) MD_FORCES(true, true, false, true);
+        else MD_FORCES(true, false, false, true);
+    } else if (kick && !drift && write_force) {
+        if (energy) MD_FORCES(true, true, true, false);
+        else MD_FORCES(true, false, true, false);
+    } else if (!kick && !drift && energy && !write_force) {
+        MD_FORCES(false, true, false, false);
+    } else if (!kick && !drift && !energy && write_force) {
+        MD_FORCES(false, false, true, false);
     } else {
         return hipErrorInvalidValue;
     }
+#undef MD_FORCES
     return hipGetLastError();
 }
 
@@ -343,20 +369,25 @@ hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st) {
 }
 
 hipError_t launch_batch_forces(const SimArgs& base, const Replica* reps, const int* cell_rep, int total_cells,
-                               int max_tile_cap, bool kick, bool energy, bool write_force, hipStream_t st) {
+                               int max_tile_cap, bool kick, bool energy, bool write_force, bool drift, hipStream_t st) {
     const dim3 g(total_cells), b(kWave);
     const size_t lds = sizeof(float4) * static_cast<size_t>(max_tile_cap + kTilePad);
-    if (kick && energy && write_force) {
-        hipLaunchKernelGGL((k_batch_forces<true, true, true>), g, b, lds, st, base, reps, cell_rep, total_cells);
-    } else if (kick && !energy && write_force) {
-        hipLaunchKernelGGL((k_batch_forces<true, false, true>), g, b, lds, st, base, reps, cell_rep, total_cells);
-    } else if (!kick && energy && !write_force) {
-        hipLaunchKernelGGL((k_batch_forces<false, true, false>), g, b, lds, st, base, reps, cell_rep, total_cells);
-    } else if (!kick && !energy && write_force) {
-        hipLaunchKernelGGL((k_batch_forces<false, false, true>), g, b, lds, st, base, reps, cell_rep, total_cells);
+#define MD_FORCES(K, E, W, D) \
+    hipLaunchKernelGGL((k_batch_forces<K, E, W, D>), g, b, lds, st, base, reps, cell_rep, total_cells)
+    if (kick && drift && !write_force) {
+        if (energy) MD_FORCES(true, true, false, true);
+        else MD_FORCES(true, false, false, true);
+    } else if (kick && !drift && write_force) {
+        if (energy) MD_FORCES(true, true, true, false);
+        else MD_FORCES(true, false, true, false);
+    } else if (!kick && !drift && energy && !write_force) {
+        MD_FORCES(false, true, false, false);
+    } else if (!kick && !drift && !energy && write_force) {
+        MD_FORCES(false, false, true, false);
     } else {
         return hipErrorInvalidValue;
     }
+#undef MD_FORCES
     return hipGetLastError();
 }
 

@@ -296,11 +296,13 @@ md_status batch_steps(const BatchPlan& B, const BatchArgs& ba, int32_t nsteps, i
                       hipStream_t st) {
     for (int32_t k = 1; k <= nsteps; ++k) {
         const bool energy = thermo && thermo_every > 0 && (k % thermo_every) == 0;
-        MD_TRY_HIP(launch_batch_integrate(ba.base, ba.reps, ba.atom_rep, st), "batch integrate");
+        const bool last = k == nsteps;
+        if (k == 1) MD_TRY_HIP(launch_batch_integrate(ba.base, ba.reps, ba.atom_rep, st), "batch integrate");
         MD_TRY_HIP(launch_batch_scan(ba.base, ba.reps, B.count, st), "batch scan");
         MD_TRY_HIP(launch_scatter(ba.base, st), "batch scatter");
         MD_TRY_HIP(launch_cell_order(ba.base, true, st), "batch cell order");
-        MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, true, energy, true, st),
+        MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, true, energy, last,
+                                       !last, st),
                    "batch forces");
         if (energy)
             MD_TRY_HIP(launch_batch_energy_final(ba.base, ba.reps, B.count,
@@ -354,7 +356,7 @@ md_status md_forces(const md_params* p, void* ws, size_t ws_bytes, float* force4
     if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
     if (force4 && !aligned16(force4)) return fail(MD_ERR_ARG, "force array must be 16-byte aligned");
     const SimArgs a = make_args(p, L, ws);
-    MD_TRY_HIP(launch_forces(a, false, false, true, false, stream), "forces");
+    MD_TRY_HIP(launch_forces(a, false, false, true, false, false, stream), "forces");
     if (force4) MD_TRY_HIP(launch_gather_user(a, nullptr, nullptr, reinterpret_cast<float4*>(force4), stream), "gather");
     return MD_OK;
 }
@@ -369,11 +371,14 @@ md_status md_step(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps,
     if (thermo_every < 0) return fail(MD_ERR_ARG, "thermo_every must be >= 0");
     if (thermo_every > 0 && !thermo) return fail(MD_ERR_ARG, "thermo_every > 0 needs a thermo buffer");
     const SimArgs a = make_args(p, L, ws);
+    // The force pass of every step but the last also performs the next step's
+    // half kick and drift, so the drift kernel runs only on the first step.
     for (int32_t k = 1; k <= nsteps; ++k) {
         const bool energy = thermo && thermo_every > 0 && (k % thermo_every) == 0;
-        MD_TRY_HIP(launch_integrate(a, stream), "integrate");
+        const bool last = k == nsteps;
+        if (k == 1) MD_TRY_HIP(launch_integrate(a, stream), "integrate");
         if ((s = rebuild_from_staging(a, true, stream)) != MD_OK) return s;
-        MD_TRY_HIP(launch_forces(a, true, energy, true, true, stream), "forces");
+        MD_TRY_HIP(launch_forces(a, true, energy, last, true, !last, stream), "forces");
         if (energy)
             MD_TRY_HIP(launch_energy_final(a, thermo + 3 * static_cast<size_t>(k / thermo_every - 1), stream),
                        "energy");
@@ -388,7 +393,7 @@ md_status md_energy_virial(const md_params* p, void* ws, size_t ws_bytes, double
     if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
     if (!out3) return fail(MD_ERR_ARG, "output is NULL");
     const SimArgs a = make_args(p, L, ws);
-    MD_TRY_HIP(launch_forces(a, false, true, false, false, stream), "energy pass");
+    MD_TRY_HIP(launch_forces(a, false, true, false, false, false, stream), "energy pass");
     MD_TRY_HIP(launch_energy_final(a, out3, stream), "energy");
     return MD_OK;
 }
@@ -515,7 +520,7 @@ md_status md_batch_forces(const md_params* p, const md_replica* reps, int32_t co
     if (s != MD_OK) return s;
     if (force4 && !aligned16(force4)) return fail(MD_ERR_ARG, "force array must be 16-byte aligned");
     const BatchArgs ba = batch_args(p, B, ws);
-    MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, false, false, true, stream),
+    MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, false, false, true, false, stream),
                "batch forces");
     if (force4) MD_TRY_HIP(launch_gather_user(ba.base, nullptr, nullptr, reinterpret_cast<float4*>(force4), stream), "gather");
     return MD_OK;
@@ -539,7 +544,7 @@ md_status md_batch_energy_virial(const md_params* p, const md_replica* reps, int
     if (s != MD_OK) return s;
     if (!out) return fail(MD_ERR_ARG, "output is NULL");
     const BatchArgs ba = batch_args(p, B, ws);
-    MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, false, true, false, stream),
+    MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, false, true, false, false, stream),
                "batch energy pass");
     MD_TRY_HIP(launch_batch_energy_final(ba.base, ba.reps, B.count, out, stream), "batch energy");
     return MD_OK;

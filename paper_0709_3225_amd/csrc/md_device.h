@@ -30,6 +30,34 @@ __device__ __forceinline__ int cell_index(float x, float y, float z, const SimAr
     return cell_coord(x, a.inv_s, a.nc) + a.nc * (cell_coord(y, a.inv_s, a.nc) + a.nc * cell_coord(z, a.inv_s, a.nc));
 }
 
+__device__ __forceinline__ bool finite3(float x, float y, float z) {
+    return isfinite(x) && isfinite(y) && isfinite(z);
+}
+
+// First half of a velocity-Verlet step for one atom (section 2): v += dt/(2m) f,
+// r += dt v, wrap into the box. A non-finite position raises DEV_NONFINITE and
+// is parked at the origin. Returns the atom's new cell (global index). The
+// drift kernel and the fused force epilogue both use this, so the two paths
+// round identically.
+__device__ __forceinline__ int half_kick_drift(const SimArgs& a, float4& p, float4& v, float fx, float fy,
+                                               float fz) {
+    const float invL = 1.0f / a.box;
+    v.x += a.hdt_m * fx;
+    v.y += a.hdt_m * fy;
+    v.z += a.hdt_m * fz;
+    p.x += a.dt * v.x;
+    p.y += a.dt * v.y;
+    p.z += a.dt * v.z;
+    if (!finite3(p.x, p.y, p.z)) {
+        atomicOr(&a.hdr[HDR_ERROR], DEV_NONFINITE);
+        p.x = p.y = p.z = 0.f;
+    }
+    p.x = wrap_coord(p.x, a.box, invL);
+    p.y = wrap_coord(p.y, a.box, invL);
+    p.z = wrap_coord(p.z, a.box, invL);
+    return a.cbase + cell_index(p.x, p.y, p.z, a);
+}
+
 // Arrival rank of each lane's atom in cell c (c < 0: no atom). Lanes holding
 // the same cell in a contiguous run share one atomicAdd of the run length on
 // the histogram; input that is already cell-sorted (every step after the
@@ -98,10 +126,6 @@ __device__ __forceinline__ bool state_ok(const SimArgs& a, bool need_forces) {
     const int st = a.hdr[HDR_STATE];
     const bool built = need_forces ? (st == STATE_FORCES) : (st == STATE_CELLS || st == STATE_FORCES);
     return built && a.hdr[HDR_N] == a.n && a.hdr[HDR_NC] == a.nc;
-}
-
-__device__ __forceinline__ bool finite3(float x, float y, float z) {
-    return isfinite(x) && isfinite(y) && isfinite(z);
 }
 
 }  // namespace mdlj

@@ -80,7 +80,9 @@ hipError_t launch_scan(const SimArgs& a, hipStream_t st);
 hipError_t launch_scatter(const SimArgs& a, hipStream_t st);
 hipError_t launch_cell_order(const SimArgs& a, bool from_step, hipStream_t st);
 hipError_t launch_integrate(const SimArgs& a, hipStream_t st);
-hipError_t launch_forces(const SimArgs& a, bool kick, bool energy, bool write_force, bool from_step,
+// drift (with kick, without write_force): the next step's first half fused
+// into the epilogue, writing the staging arrays for the next rebuild.
+hipError_t launch_forces(const SimArgs& a, bool kick, bool energy, bool write_force, bool from_step, bool drift,
                          hipStream_t st);
 hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st);
 hipError_t launch_gather_user(const SimArgs& a, float4* pos_out, float4* vel_out, float4* force_out,
@@ -103,7 +105,7 @@ hipError_t launch_batch_load(const SimArgs& base, const Replica* reps, const int
 hipError_t launch_batch_integrate(const SimArgs& base, const Replica* reps, const int* atom_rep, hipStream_t st);
 hipError_t launch_batch_scan(const SimArgs& base, const Replica* reps, int count, hipStream_t st);
 hipError_t launch_batch_forces(const SimArgs& base, const Replica* reps, const int* cell_rep, int total_cells,
-                               int max_tile_cap, bool kick, bool energy, bool write_force, hipStream_t st);
+                               int max_tile_cap, bool kick, bool energy, bool write_force, bool drift, hipStream_t st);
 hipError_t launch_batch_energy_final(const SimArgs& base, const Replica* reps, int count, double* out, hipStream_t st);
 
 }  // namespace mdlj

@@ -134,12 +134,11 @@ def test_neighbor_sets_exact(case, orc):
         assert np.array_equal(np.sort(idx[i, :counts[i]]), idx_o[off[i]:off[i + 1]]), i
 
 
-@pytest.mark.parametrize("case", ["lj4k_jitter_shuffled", "sparse_gas_rho0.05", "dense_clump"])
-def test_cell_lists_are_a_valid_counting_sort(case):
-    pos4, box = CASES[case]()
-    _say(f"cell lists {case} n={len(pos4)}")
+def _check_cell_lists(pos4, box, steps=0, vel4=None):
     s = _system(len(pos4), box)
-    s.load(_dev(pos4), forces=False)
+    s.load(_dev(pos4), None if vel4 is None else _dev(vel4), forces=steps > 0)
+    if steps:
+        s.step(steps)
     start, order = s.cell_lists()
     pos, _ = s.state()
     assert s.check() == 0
@@ -154,9 +153,26 @@ def test_cell_lists_are_a_valid_counting_sort(case):
     cell_of_atom = ic[:, 0] + nc * (ic[:, 1] + nc * ic[:, 2])
     cell_of_slot = np.repeat(np.arange(nc ** 3), np.diff(start))
     np.testing.assert_array_equal(cell_of_atom[order], cell_of_slot)
-    for c in range(nc ** 3):  # stable order inside each cell: ascending user index
-        seg = order[start[c]:start[c + 1]]
-        assert np.all(np.diff(seg) > 0)
+    # stable order inside each cell: ascending user index
+    same = cell_of_slot[1:] == cell_of_slot[:-1]
+    assert np.all(np.diff(order)[same] > 0)
+
+
+@pytest.mark.parametrize("case", ["lj4k_jitter_shuffled", "sparse_gas_rho0.05", "dense_clump"])
+def test_cell_lists_are_a_valid_counting_sort(case):
+    pos4, box = CASES[case]()
+    _say(f"cell lists {case} n={len(pos4)}")
+    _check_cell_lists(pos4, box)
+
+
+@pytest.mark.parametrize("name", ["lj256k", "lj2m"])
+def test_cell_lists_full_size_after_steps(name):
+    """Grids of 26^3 and 53^3 cells (one and several scan tiles), rebuilt by
+    the fused drift of a 3-step run."""
+    w = ljsynth.WORKLOADS[name]
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05, shuffle=True)
+    _say(f"cell lists full size {name} n={w.n}, 3 steps")
+    _check_cell_lists(pos4, box, steps=3, vel4=vel4)
 
 
 def test_fcc_lattice_energy_pin():
@@ -236,17 +252,24 @@ def test_bitwise_deterministic():
 
 
 def test_step_chunks_equal_one_call():
+    """Inside one md_step call every force pass but the last also performs the
+    next step's half kick and drift; a call of one step runs the separate drift
+    kernel. Any split of the same run must give bitwise the same state."""
     w = ljsynth.WORKLOADS["lj4k"]
-    pos4, vel4, box = ljsynth.make_state(w)
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05, shuffle=True)
     _say("step chunks lj4k")
     res = []
-    for chunks in ([10], [3, 7]):
+    for chunks in ([10], [3, 7], [1] * 10):
         s = _system(w.n, box)
         s.load(_dev(pos4), _dev(vel4))
         for c in chunks:
             s.step(c)
-        res.append([t.cpu().numpy() for t in s.state()])
-    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+        pos, vel = s.state()
+        res.append([t.cpu().numpy() for t in (pos, vel, s.forces(), s.energy())])
+        assert s.check() == 0
+    for other in res[1:]:
+        for a, b in zip(res[0], other):
+            assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("name,rows", [("lj256k", 1024), ("lj2m", 512)])
