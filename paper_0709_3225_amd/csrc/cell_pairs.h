@@ -23,62 +23,72 @@ struct Neighbourhood {
     int home_first;  // its sorted slot
     int n_home;
     int nseg;
+    float origin[3];    // home-cell origin
     int seg_pos[27];    // neighbourhood index of the segment's first atom
     int seg_first[27];  // its sorted slot
     int seg_len[27];
     float sx[27], sy[27], sz[27];  // frame offset o - sh of the segment's cells
 };
 
-// Fill the neighbourhood table of home cell c (lanes 0..26 one cell each).
-__device__ __forceinline__ void load_neighbourhood(const SimArgs& a, int c, Neighbourhood& nb,
-                                                   float& ox, float& oy, float& oz) {
+// The same table while it is built, in registers: lane l < 27 first holds
+// neighbour cell l (HoodLoads: its CSR range, still in flight), then segment l
+// (HoodSegs). The uniform fields are the same in every lane.
+struct HoodLoads {
+    int first = 0, next = 0;  // start[cj], start[cj + 1]
+    float bx = 0.f, by = 0.f, bz = 0.f;
+    int cell = 0;  // the home cell
+    bool rows = false;
+};
+
+// Origin of cell c (local index) in the box.
+__device__ __forceinline__ void cell_origin(const SimArgs& a, int c, float& ox, float& oy, float& oz) {
+    const int nc = a.nc;
+    ox = (c % nc) * a.s;
+    oy = ((c / nc) % nc) * a.s;
+    oz = (c / (nc * nc)) * a.s;
+}
+
+// Uniform facts are spread over lanes (meta: lane 0 total, 1 home_pos,
+// 2 home_first, 3 n_home, 4 nseg; org: lanes 0..2 the home-cell origin) so
+// that a table held across the pair loops costs vector registers, not scalar
+// ones.
+struct HoodSegs {
+    int pos = 0, first = 0, len = 0;
+    float x = 0.f, y = 0.f, z = 0.f;
+    int meta = 0;
+    float org = 0.f;
+    __device__ __forceinline__ int total() const { return __builtin_amdgcn_readlane(meta, 0); }
+    __device__ __forceinline__ int home_pos() const { return __builtin_amdgcn_readlane(meta, 1); }
+    __device__ __forceinline__ int home_first() const { return __builtin_amdgcn_readlane(meta, 2); }
+    __device__ __forceinline__ int n_home() const { return __builtin_amdgcn_readlane(meta, 3); }
+    __device__ __forceinline__ int nseg() const { return __builtin_amdgcn_readlane(meta, 4); }
+    __device__ __forceinline__ float origin(int d) const {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(org), d));
+    }
+};
+
+// Issue the CSR loads of home cell c's 27 neighbours (lanes 0..26); nothing
+// waits for them here.
+__device__ __forceinline__ void hood_issue(const SimArgs& a, int c, HoodLoads& h) {
     const int lane = threadIdx.x;
     const int nc = a.nc;
     const int ix = c % nc, iy = (c / nc) % nc, iz = c / (nc * nc);
-    ox = ix * a.s;
-    oy = iy * a.s;
-    oz = iz * a.s;
-    int cnt = 0, first = 0;
-    float bx = ox, by = oy, bz = oz;
+    float ox, oy, oz;
+    cell_origin(a, c, ox, oy, oz);
+    h.cell = c;
+    h.rows = ix >= 1 && ix <= nc - 2;  // x-rows are contiguous and unshifted in x
+    h.bx = ox;
+    h.by = oy;
+    h.bz = oz;
     if (lane < 27) {
         int jx = ix + lane % 3 - 1, jy = iy + (lane / 3) % 3 - 1, jz = iz + lane / 9 - 1;
-        if (jx < 0) { jx += nc; bx = ox + a.box; } else if (jx >= nc) { jx -= nc; bx = ox - a.box; }
-        if (jy < 0) { jy += nc; by = oy + a.box; } else if (jy >= nc) { jy -= nc; by = oy - a.box; }
-        if (jz < 0) { jz += nc; bz = oz + a.box; } else if (jz >= nc) { jz -= nc; bz = oz - a.box; }
+        if (jx < 0) { jx += nc; h.bx = ox + a.box; } else if (jx >= nc) { jx -= nc; h.bx = ox - a.box; }
+        if (jy < 0) { jy += nc; h.by = oy + a.box; } else if (jy >= nc) { jy -= nc; h.by = oy - a.box; }
+        if (jz < 0) { jz += nc; h.bz = oz + a.box; } else if (jz >= nc) { jz -= nc; h.bz = oz - a.box; }
         const int cj = a.cbase + jx + nc * (jy + nc * jz);
-        first = a.start[cj];
-        cnt = a.start[cj + 1] - first;
+        h.first = a.start[cj];
+        h.next = a.start[cj + 1];
     }
-    const int incl = wave_incl_scan(cnt);
-    const int pos = incl - cnt;
-    const bool rows = ix >= 1 && ix <= nc - 2;  // uniform: x-rows are contiguous, unshifted in x
-    const int row_end = __shfl(incl, lane + 2 < kWave ? lane + 2 : lane);
-    if (rows) {
-        if (lane < 27 && lane % 3 == 0) {
-            const int r = lane / 3;
-            nb.seg_pos[r] = pos;
-            nb.seg_first[r] = first;
-            nb.seg_len[r] = row_end - pos;
-            nb.sx[r] = bx;
-            nb.sy[r] = by;
-            nb.sz[r] = bz;
-        }
-    } else if (lane < 27) {
-        nb.seg_pos[lane] = pos;
-        nb.seg_first[lane] = first;
-        nb.seg_len[lane] = cnt;
-        nb.sx[lane] = bx;
-        nb.sy[lane] = by;
-        nb.sz[lane] = bz;
-    }
-    if (lane == 13) {
-        nb.home_pos = pos;
-        nb.home_first = first;
-        nb.n_home = cnt;
-    }
-    if (lane == 26) nb.total = incl;
-    if (lane == 0) nb.nseg = rows ? 9 : 27;
-    __syncthreads();
 }
 
 __device__ __forceinline__ int lane_value(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
@@ -86,67 +96,190 @@ __device__ __forceinline__ float lane_value(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
-// Stage neighbourhood atoms [t0, t0 + tn) into the tile, frame-translated.
-// w carries the user index (ID_IN_W) or |x|^2 in the frame (for the screen).
-// With WITH_VEC the matching entries of a per-atom vector (sorted order) are
-// copied into vtile as well. A uniform cursor walks the segments in chunks of
-// at most one wavefront; the segment table sits in lanes 0..nseg-1 and is read
-// with readlane, and kBatch chunks have their loads in flight before the LDS
-// stores, so an interior cell's neighbourhood costs one global round trip.
-template <bool ID_IN_W, bool WITH_VEC = false>
+// Segments of a neighbourhood from its CSR ranges (waits for hood_issue's loads).
+__device__ __forceinline__ void hood_segments(const SimArgs& a, const HoodLoads& h, HoodSegs& g) {
+    const int lane = threadIdx.x;
+    const int cnt = lane < 27 ? h.next - h.first : 0;
+    const int incl = wave_incl_scan(cnt);
+    const int pos = incl - cnt;
+    int nseg;
+    if (h.rows) {
+        // segment r = cells 3r .. 3r + 2, gathered from lanes 3r and 3r + 2
+        const int src = lane < 9 ? 3 * lane : 0;
+        const int end = __shfl(incl, lane < 9 ? 3 * lane + 2 : 0);
+        g.pos = __shfl(pos, src);
+        g.first = __shfl(h.first, src);
+        g.len = end - g.pos;
+        g.x = __shfl(h.bx, src);
+        g.y = __shfl(h.by, src);
+        g.z = __shfl(h.bz, src);
+        nseg = 9;
+    } else {
+        g.pos = pos;
+        g.first = h.first;
+        g.len = cnt;
+        g.x = h.bx;
+        g.y = h.by;
+        g.z = h.bz;
+        nseg = 27;
+    }
+    const int total = __shfl(incl, 26), home_pos = __shfl(pos, 13), home_first = __shfl(h.first, 13),
+              n_home = __shfl(cnt, 13);
+    g.meta = lane == 0 ? total : lane == 1 ? home_pos : lane == 2 ? home_first : lane == 3 ? n_home : nseg;
+    float ox, oy, oz;
+    cell_origin(a, h.cell, ox, oy, oz);
+    g.org = lane == 0 ? ox : lane == 1 ? oy : oz;
+}
+
+// Write the table to LDS (the caller synchronises before it is read).
+__device__ __forceinline__ void hood_store(const HoodSegs& g, Neighbourhood& nb) {
+    const int lane = threadIdx.x;
+    if (lane < g.nseg()) {
+        nb.seg_pos[lane] = g.pos;
+        nb.seg_first[lane] = g.first;
+        nb.seg_len[lane] = g.len;
+        nb.sx[lane] = g.x;
+        nb.sy[lane] = g.y;
+        nb.sz[lane] = g.z;
+    }
+    if (lane == 0) nb.total = g.meta;
+    if (lane == 1) nb.home_pos = g.meta;
+    if (lane == 2) nb.home_first = g.meta;
+    if (lane == 3) nb.n_home = g.meta;
+    if (lane == 4) nb.nseg = g.meta;
+    if (lane < 3) nb.origin[lane] = g.org;
+}
+
+// The segment table of nb back in registers (lane l holds segment l).
+__device__ __forceinline__ HoodSegs hood_from_lds(const Neighbourhood& nb) {
+    const int lane = threadIdx.x;
+    HoodSegs g;
+    const int nseg = nb.nseg;
+    g.meta = lane == 0 ? nb.total : lane == 1 ? nb.home_pos : lane == 2 ? nb.home_first : lane == 3 ? nb.n_home : nseg;
+    g.org = nb.origin[lane < 3 ? lane : 0];
+    if (lane < nseg) {
+        g.pos = nb.seg_pos[lane];
+        g.first = nb.seg_first[lane];
+        g.len = nb.seg_len[lane];
+        g.x = nb.sx[lane];
+        g.y = nb.sy[lane];
+        g.z = nb.sz[lane];
+    }
+    return g;
+}
+
+// Fill the neighbourhood table of home cell c and synchronise.
+__device__ __forceinline__ void load_neighbourhood(const SimArgs& a, int c, Neighbourhood& nb,
+                                                   float& ox, float& oy, float& oz) {
+    HoodLoads h;
+    hood_issue(a, c, h);
+    HoodSegs g;
+    hood_segments(a, h, g);
+    hood_store(g, nb);
+    cell_origin(a, c, ox, oy, oz);
+    __syncthreads();
+}
+
+// Staging of neighbourhood atoms [t0, t1) into the tile, frame-translated: a
+// uniform cursor (segment sg, neighbourhood index g) walks the segments in
+// chunks of at most one wavefront; a batch of B chunks has its loads in flight
+// before its LDS stores. w carries the user index (ID_IN_W) or |x|^2 in the
+// frame (for the screen); with WITH_VEC the matching entries of a per-atom
+// vector (sorted order) go to vtile as well.
+struct StageCursor {
+    int sg, g;
+};
+
+__device__ __forceinline__ StageCursor stage_begin(const HoodSegs& h, int t0) {
+    StageCursor cur{0, t0};
+    const int nseg = h.nseg();
+    while (cur.sg < nseg && lane_value(h.pos, cur.sg) + lane_value(h.len, cur.sg) <= t0) ++cur.sg;
+    return cur;
+}
+
+__device__ __forceinline__ bool stage_more(const HoodSegs& h, const StageCursor& cur, int t1) {
+    return cur.g < t1 && cur.sg < h.nseg();
+}
+
+// One batch of chunks: per chunk the loaded atoms (one per lane). The chunk
+// boundaries are not stored: the commit replays the cursor from the position
+// the issue started at (a few scalar operations per chunk, and no scalar
+// registers held between issue and commit).
+template <int B, bool WITH_VEC>
+struct StageBatch {
+    float4 q[B], vq[B];
+};
+
+// Bounds of the chunk at the cursor: atoms [cur.g, ce) of segment cur.sg,
+// whose first atom has neighbourhood index p and sorted slot first; advances
+// the cursor past it.
+__device__ __forceinline__ void stage_chunk(const HoodSegs& h, StageCursor& cur, int t1, int& p, int& first,
+                                            int& base, int& cnt, int& seg) {
+    p = lane_value(h.pos, cur.sg);
+    const int end = p + lane_value(h.len, cur.sg);
+    const int ce = min(min(cur.g + kWave, end), t1);
+    first = lane_value(h.first, cur.sg);
+    base = cur.g;
+    cnt = ce - cur.g;
+    seg = cur.sg;
+    cur.g = ce;
+    if (cur.g >= end) ++cur.sg;
+}
+
+template <int B, bool WITH_VEC>
+__device__ __forceinline__ void stage_issue(const SimArgs& a, const HoodSegs& h, StageCursor& cur, int t1,
+                                            StageBatch<B, WITH_VEC>& b, const float4* vec) {
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+        int slot = 0;  // lanes without an atom load slot 0 (always valid) and store nothing
+        if (stage_more(h, cur, t1)) {
+            int p, first, base, cnt, seg;
+            stage_chunk(h, cur, t1, p, first, base, cnt, seg);
+            if (lane < cnt) slot = first + (base - p) + lane;
+        }
+        b.q[u] = a.pos0[slot];
+        if (WITH_VEC) b.vq[u] = vec[slot];
+    }
+}
+
+// cur: the cursor stage_issue started from; on return, past the batch.
+template <int B, bool ID_IN_W, bool WITH_VEC>
+__device__ __forceinline__ void stage_commit(const HoodSegs& h, const StageBatch<B, WITH_VEC>& b, StageCursor& cur,
+                                             int t0, int t1, float4* tile, float4* vtile) {
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+        if (stage_more(h, cur, t1)) {
+            int p, first, base, cnt, seg;
+            stage_chunk(h, cur, t1, p, first, base, cnt, seg);
+            if (lane < cnt) {
+                const int dst = base - t0 + lane;
+                const float x = b.q[u].x - lane_value(h.x, seg);
+                const float y = b.q[u].y - lane_value(h.y, seg);
+                const float z = b.q[u].z - lane_value(h.z, seg);
+                tile[dst] = make_float4(x, y, z, ID_IN_W ? b.q[u].w : x * x + y * y + z * z);
+                if (WITH_VEC) vtile[dst] = b.vq[u];
+            }
+        }
+    }
+}
+
+// Stage neighbourhood atoms [t0, t0 + tn) of the table in nb (an interior
+// cell's neighbourhood costs one global round trip).
+// B chunks in flight per batch (default: 9, or 5 with a vector).
+template <bool ID_IN_W, bool WITH_VEC = false, int B = (WITH_VEC ? 5 : 9)>
 __device__ __forceinline__ void stage_tile(const SimArgs& a, const Neighbourhood& nb, float4* tile,
                                            int t0, int tn, const float4* vec = nullptr,
                                            float4* vtile = nullptr) {
-    constexpr int kBatch = WITH_VEC ? 5 : 9;  // chunks in flight (register budget)
-    const int lane = threadIdx.x;
-    const int nseg = nb.nseg;
-    int s_pos = 0, s_first = 0, s_len = 0;
-    float s_x = 0.f, s_y = 0.f, s_z = 0.f;
-    if (lane < nseg) {
-        s_pos = nb.seg_pos[lane];
-        s_first = nb.seg_first[lane];
-        s_len = nb.seg_len[lane];
-        s_x = nb.sx[lane];
-        s_y = nb.sy[lane];
-        s_z = nb.sz[lane];
-    }
+    const HoodSegs h = hood_from_lds(nb);
     const int t1 = t0 + tn;
-    int sg = 0;  // uniform cursor: segment sg, neighbourhood index g
-    while (sg < nseg && lane_value(s_pos, sg) + lane_value(s_len, sg) <= t0) ++sg;
-    int g = t0;
-    while (g < t1 && sg < nseg) {
-        float4 q[kBatch], vq[kBatch];
-        int dst[kBatch], seg[kBatch];
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            dst[u] = -1;
-            seg[u] = 0;
-            int slot = 0;  // lanes without an atom load slot 0 (always valid) and store nothing
-            if (g < t1 && sg < nseg) {
-                const int p = lane_value(s_pos, sg), end = p + lane_value(s_len, sg);
-                const int ce = min(min(g + kWave, end), t1);
-                const int my = g + lane;
-                if (my < ce) {
-                    slot = lane_value(s_first, sg) + (my - p);
-                    dst[u] = my - t0;
-                }
-                seg[u] = sg;
-                g = ce;
-                if (g >= end) ++sg;
-            }
-            q[u] = a.pos0[slot];
-            if (WITH_VEC) vq[u] = vec[slot];
-        }
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-            if (dst[u] >= 0) {
-                const float x = q[u].x - lane_value(s_x, seg[u]);
-                const float y = q[u].y - lane_value(s_y, seg[u]);
-                const float z = q[u].z - lane_value(s_z, seg[u]);
-                tile[dst[u]] = make_float4(x, y, z, ID_IN_W ? q[u].w : x * x + y * y + z * z);
-                if (WITH_VEC) vtile[dst[u]] = vq[u];
-            }
-        }
+    StageCursor cur = stage_begin(h, t0);
+    while (stage_more(h, cur, t1)) {
+        StageBatch<B, WITH_VEC> b;
+        StageCursor issue = cur;
+        stage_issue(a, h, issue, t1, b, vec);
+        stage_commit<B, ID_IN_W, WITH_VEC>(h, b, cur, t0, t1, tile, vtile);
     }
 }
 

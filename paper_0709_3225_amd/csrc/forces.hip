@@ -124,7 +124,8 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                 w_loc = op.w_loc;
             }
         }
-        // sum the slice partials of each home atom in slice order
+        // sum the slice partials of each home atom in slice order (red aliases the
+        // tile: every lane has finished its walk at this barrier)
         __syncthreads();
         red[0 * kWave + lane] = fx;
         red[1 * kWave + lane] = fy;
@@ -206,8 +207,9 @@ __global__ void __launch_bounds__(kWave) k_forces(SimArgs a, bool from_step) {
     }
     extern __shared__ float4 tile[];  // a.tile_cap + kTilePad entries
     __shared__ Neighbourhood nb;
-    __shared__ float red[5 * kWave];
-    force_cell<KICK, ENERGY, WRITE, DRIFT>(a, xcd_block_order(blockIdx.x, a.ncells), tile, nb, red);
+    // the slice reduction reuses the tile (at least kTilePad = 80 entries, 320 floats)
+    force_cell<KICK, ENERGY, WRITE, DRIFT>(a, xcd_block_order(blockIdx.x, a.ncells), tile, nb,
+                                           reinterpret_cast<float*>(tile));
     if (WRITE && blockIdx.x == 0 && threadIdx.x == 0) a.hdr[HDR_STATE] = STATE_FORCES;
 }
 
@@ -219,7 +221,7 @@ __global__ void __launch_bounds__(kWave)
     if (base.hdr[HDR_ERROR] & DEV_ORDER) return;
     extern __shared__ float4 tile[];  // max tile_cap over replicas + kTilePad entries
     __shared__ Neighbourhood nb;
-    __shared__ float red[5 * kWave];
+    float* red = reinterpret_cast<float*>(tile);  // slice reduction, as in k_forces
     const int gc = xcd_block_order(blockIdx.x, total_cells);
     const SimArgs a = replica_view(base, reps[cell_rep[gc]]);
     force_cell<KICK, ENERGY, WRITE, DRIFT>(a, gc - a.cbase, tile, nb, red);

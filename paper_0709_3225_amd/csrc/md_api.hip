@@ -122,10 +122,12 @@ bool aligned16(const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 
 float screen_bound(double rc, double s) { return static_cast<float>(rc * rc + std::ldexp(12.0 * s * s, -17)); }
 
 // One LDS pass of the cell-pair kernels holds the mean 27-cell neighbourhood
-// plus 30% and a wavefront.
+// plus 10% and half a wavefront (a liquid's neighbourhood counts vary by a few
+// percent; a larger one takes a second pass). A small tile leaves room for
+// more wavefronts per CU, which hide the latency of staging.
 int tile_capacity(int n, int ncells) {
     const double hood = 27.0 * static_cast<double>(n) / ncells;
-    const int cap = static_cast<int>(std::ceil((1.3 * hood + 64.0) / 64.0)) * 64;
+    const int cap = static_cast<int>(std::ceil((1.1 * hood + 32.0) / 64.0)) * 64;
     return std::min(2048, std::max(128, cap));
 }
 
