@@ -1,19 +1,24 @@
-// Cell-list build by counting sort (section 3 cells of side >= r_c; section
-// 3.1 membership kept current as particles move), and the velocity-Verlet
-// drift that feeds it (section 2).
+// Cell-list build by counting sort into per-cell buckets (section 3 cells of
+// side >= r_c; section 3.1 membership kept current as particles move), and the
+// velocity-Verlet drift that feeds it (section 2).
 //
-// One build is four launches, all HBM/L2-bound streaming passes:
-//   load or drift : wrap + cell index + histogram rank (one atomic per run of
-//                   equal cells in a wavefront); inside a multi-step run the
-//                   force kernel's epilogue does this for every step after
-//                   the first, and the drift kernel only starts a run
-//   scan          : exclusive prefix of the histogram -> cell offsets;
-//                   clears the histogram for the next build
-//   scatter       : key[offset + rank] = staging slot
-//   cell order    : a 16-lane group per cell orders its members by user
-//                   index and moves them into the sorted arrays
-// The paper updated each cell with one serial thread per cell (section 3.1);
-// a counting sort has no serial part and no capacity per cell.
+// A build is three launches:
+//   bin        : wrap + cell index + histogram rank (one atomic per run of
+//                equal cells in a wavefront); the atom's staging slot goes to
+//                its cell's bucket (or the overflow list beyond the bucket
+//                capacity).
+//                Inside a multi-step run the force kernel's epilogue bins the
+//                drifted atoms, so this launch only starts a build or a run.
+//   block scan : one workgroup sums the histogram over blocks of 16 cells
+//                and scans the sums into the atoms before each block.
+//   cell order : the workgroup of a 16-cell block adds its cells' counts to
+//                the block's offset, writes the cell offsets, clears its
+//                cells' counts, orders each cell's members by user index and
+//                moves them into the sorted arrays.
+// The cell order clears its own cells' counts after the block scan has read
+// them, so the histogram is zero between builds. The paper updated each cell with one
+// serial thread per cell (section 3.1); here nothing runs serially per cell and
+// there is no capacity per cell (the overflow list takes the excess).
 #include "md_device.h"
 
 namespace mdlj {
@@ -22,20 +27,24 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Header and histograms cleared (the whole workspace of a batch).
 __global__ void __launch_bounds__(kBlock) k_build_init(SimArgs a) {
     const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int stride = gridDim.x * kBlock;
     if (t == 0) {
         a.hdr[HDR_ERROR] = 0;
         a.hdr[HDR_STATE] = STATE_BUILDING;
         a.hdr[HDR_N] = a.n;
         a.hdr[HDR_NC] = a.nc;
+        a.hdr[HDR_OVF] = 0;
+        a.hdr[HDR_OVF_READ] = 0;
     }
-    for (int c = t; c < a.ncells; c += gridDim.x * kBlock) a.count[c] = 0;
+    for (int c = t; c < (a.nblocks << kBlockShift); c += stride) a.counts[c] = 0;
 }
 
-// Load one user-order atom i into the staging arrays: wrap, cell index,
-// rank. Called by every lane of the wave (valid = false for lanes past the
-// end); cells are numbered globally (a.cbase + local index).
+// Load one user-order atom i into staging slot i: wrap, cell index, binning.
+// Called by every lane of the wave (valid = false for
+// lanes past the end); cells are numbered globally (a.cbase + local index).
 __device__ __forceinline__ void load_atom(const SimArgs& a, int i, bool valid, const float4* __restrict__ pos_in,
                                           const float4* __restrict__ vel_in) {
     const float invL = 1.0f / a.box;
@@ -54,35 +63,26 @@ __device__ __forceinline__ void load_atom(const SimArgs& a, int i, bool valid, c
         p.w = __int_as_float(i);
         v.w = 0.f;
         c = a.cbase + cell_index(p.x, p.y, p.z, a);
-    }
-    const int r = histogram_rank(a.count, c);
-    if (valid) {
         a.pos1[i] = p;
         a.vel1[i] = v;
-        a.cell[i] = c;
-        a.rank[i] = r;
     }
+    bin_atom(a, i, c);
 }
 
-// Velocity-Verlet first half for sorted slot i (half kick, drift, wrap),
-// then the histogram rank for the rebuild. Reads the sorted state, writes
-// staging. Called by every lane of the wave.
+// Velocity-Verlet first half for sorted slot i (half kick, drift, wrap), then
+// the binning for the rebuild. Reads the sorted state, writes staging slot i.
+// Called by every lane of the wave.
 __device__ __forceinline__ void integrate_atom(const SimArgs& a, int i, bool valid) {
     int c = -1;
-    float4 p = make_float4(0.f, 0.f, 0.f, 0.f), v = p;
     if (valid) {
-        p = a.pos0[i];
-        v = a.vel0[i];
+        float4 p = a.pos0[i];
+        float4 v = a.vel0[i];
         const float4 f = a.force[i];
         c = half_kick_drift(a, p, v, f.x, f.y, f.z);
-    }
-    const int r = histogram_rank(a.count, c);
-    if (valid) {
         a.pos1[i] = p;
         a.vel1[i] = v;
-        a.cell[i] = c;
-        a.rank[i] = r;
     }
+    bin_atom(a, i, c);
 }
 
 __global__ void __launch_bounds__(kBlock) k_load(SimArgs a, const float4* __restrict__ pos_in,
@@ -126,101 +126,59 @@ __global__ void __launch_bounds__(kBlock) k_batch_integrate(SimArgs base, const 
     integrate_atom(a, i, valid);
 }
 
-// Batch set-up: per-atom and per-cell replica tables, zero histogram, header.
-// One workgroup per replica.
+// Batch set-up: per-atom and per-cell replica tables and the batch marker in
+// the header (k_build_init has cleared the rest). One workgroup per replica.
 __global__ void __launch_bounds__(kBlock) k_batch_setup(SimArgs base, const Replica* __restrict__ reps,
                                                         int* __restrict__ atom_rep, int* __restrict__ cell_rep,
                                                         int count) {
     const int b = blockIdx.x;
     const Replica r = reps[b];
-    if (b == 0 && threadIdx.x == 0) {
-        base.hdr[HDR_ERROR] = 0;
-        base.hdr[HDR_STATE] = STATE_BUILDING;
-        base.hdr[HDR_N] = base.n;
-        base.hdr[HDR_NC] = -count;  // marks a batch workspace
-    }
+    if (b == 0 && threadIdx.x == 0) base.hdr[HDR_NC] = -count;  // marks a batch workspace
     for (int i = threadIdx.x; i < r.n; i += kBlock) atom_rep[r.abase + i] = b;
-    for (int c = threadIdx.x; c < r.ncells; c += kBlock) {
-        cell_rep[r.cbase + c] = b;
-        base.count[r.cbase + c] = 0;
-    }
+    for (int c = threadIdx.x; c < r.ncells; c += kBlock) cell_rep[r.cbase + c] = b;
 }
 
-// Batched scan: one workgroup per replica scans its own histogram into
-// start[cbase .. cbase + ncells) (global slots: abase + prefix) and clears it;
-// the last replica also writes the terminal entry.
-__global__ void __launch_bounds__(kBlock) k_batch_scan(SimArgs base, const Replica* __restrict__ reps, int count) {
-    if (base.hdr[HDR_ERROR] & DEV_ORDER) return;
-    __shared__ int wave_tot[kBlock / kWave];
-    const Replica r = reps[blockIdx.x];
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    int carry = r.abase;
-    for (int base_c = 0; base_c < r.ncells; base_c += kBlock) {
-        const int c = base_c + tid;
-        const int v = (c < r.ncells) ? base.count[r.cbase + c] : 0;
-        const int incl = wave_incl_scan(v);
-        if (lane == kWave - 1) wave_tot[wave] = incl;
-        __syncthreads();
-        int off = 0, tot = 0;
-        for (int w = 0; w < kBlock / kWave; ++w) {
-            const int t = wave_tot[w];
-            if (w < wave) off += t;
-            tot += t;
-        }
-        if (c < r.ncells) {
-            base.start[r.cbase + c] = carry + off + incl - v;
-            base.count[r.cbase + c] = 0;
-        }
-        carry += tot;
-        __syncthreads();
-    }
-    if (blockIdx.x == count - 1 && tid == 0) base.start[r.cbase + r.ncells] = carry;
-}
-
-// Exclusive prefix scan of the histogram into start[0..ncells], by one
-// workgroup of 1024 lanes. One workgroup runs on one CU, whose memory pipeline
-// serves a few cache lines per clock, so every global access here is a
-// coalesced int4 (consecutive lanes, consecutive 16 bytes) and the transpose
-// to "each lane owns 4 kScanVec consecutive cells" goes through LDS. Per tile of
-// 4096 kScanVec cells: coalesced loads into LDS, per-lane sums, a wavefront
-// scan and a scan of the 16 wave totals, exclusive offsets back into LDS,
-// coalesced stores of the offsets and of zeros into the histogram (cleared
-// for the next build). A carry links the tiles.
+// Block scan: bstart[b] = atoms in the cells of blocks 0 .. b - 1 (16 cells
+// a block), by one workgroup of 1024 lanes. One workgroup runs on one CU,
+// whose memory pipeline serves a few cache lines per clock, so a lane reads
+// kScanBlocks whole blocks as consecutive int4 (adjacent lanes read adjacent
+// 128-byte runs) and all of a tile's loads are issued before any arithmetic.
+// A lane's blocks then get a running prefix, a wavefront scan and a scan of
+// the 16 wave totals give the lane's offset, and tiles are linked by a carry.
+// Hands the overflow count to the cell order.
 constexpr int kScanBlock = 1024;
-constexpr int kScanVec = 3;                       // int4 per lane per tile
-constexpr int kScanTile = kScanBlock * 4 * kScanVec;  // 12288 cells, 48 KiB of LDS
-__global__ void __launch_bounds__(kScanBlock) k_scan(SimArgs a, bool from_step) {
-    __shared__ int4 buf[kScanTile / 4];
+constexpr int kScanBlocks = 2;                          // blocks per lane per tile
+constexpr int kScanTile = kScanBlock * kScanBlocks;      // 2048 blocks = 32768 cells
+constexpr int kBlockInts = 1 << kBlockShift;
+__global__ void __launch_bounds__(kScanBlock) k_block_scan(SimArgs a, bool from_step) {
     __shared__ int wave_tot[kScanBlock / kWave];
     const int err = a.hdr[HDR_ERROR];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    const int nc = a.ncells;
+    const int nb = a.nblocks;
     int carry = 0;
-    for (int base = 0; base < nc; base += kScanTile) {
-        int4 v[kScanVec];
+    for (int base = 0; base < nb; base += kScanTile) {
+        const int b0 = base + tid * kScanBlocks;
+        int4 v[kScanBlocks * kBlockInts / 4];
 #pragma unroll
-        for (int q = 0; q < kScanVec; ++q) {
-            const int c = base + 4 * (q * kScanBlock + tid);
-            if (c + 3 < nc) {
-                v[q] = *reinterpret_cast<const int4*>(a.count + c);
-            } else {
-                v[q].x = c < nc ? a.count[c] : 0;
-                v[q].y = c + 1 < nc ? a.count[c + 1] : 0;
-                v[q].z = c + 2 < nc ? a.count[c + 2] : 0;
-                v[q].w = 0;
-            }
+        for (int q = 0; q < kScanBlocks * kBlockInts / 4; ++q) {
+            // counts holds whole blocks (zero past the last cell)
+            v[q] = (b0 + q / (kBlockInts / 4) < nb)
+                       ? reinterpret_cast<const int4*>(a.counts)[b0 * (kBlockInts / 4) + q]
+                       : make_int4(0, 0, 0, 0);
         }
         if (from_step && (err & DEV_ORDER)) return;  // uniform over the workgroup
-#pragma unroll
-        for (int q = 0; q < kScanVec; ++q) buf[q * kScanBlock + tid] = v[q];
-        __syncthreads();
-        // this lane's cells: tile entries kScanVec * tid .. + kScanVec - 1
-        int4 w[kScanVec];
+        int bsum[kScanBlocks];
         int tsum = 0;
 #pragma unroll
-        for (int q = 0; q < kScanVec; ++q) {
-            w[q] = buf[kScanVec * tid + q];
-            tsum += w[q].x + w[q].y + w[q].z + w[q].w;
+        for (int j = 0; j < kScanBlocks; ++j) {
+            int t = 0;
+#pragma unroll
+            for (int q = 0; q < kBlockInts / 4; ++q) {
+                const int4 x = v[j * (kBlockInts / 4) + q];
+                t += x.x + x.y + x.z + x.w;
+            }
+            bsum[j] = t;
+            tsum += t;
         }
         const int incl = wave_incl_scan(tsum);
         if (lane == kWave - 1) wave_tot[wave] = incl;
@@ -234,63 +192,58 @@ __global__ void __launch_bounds__(kScanBlock) k_scan(SimArgs a, bool from_step) 
         }
         int run = carry + wave_off + incl - tsum;
 #pragma unroll
-        for (int q = 0; q < kScanVec; ++q) {
-            const int s0 = run, s1 = s0 + w[q].x, s2 = s1 + w[q].y, s3 = s2 + w[q].z;
-            run = s3 + w[q].w;
-            buf[kScanVec * tid + q] = make_int4(s0, s1, s2, s3);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < kScanVec; ++q) {
-            const int c = base + 4 * (q * kScanBlock + tid);
-            const int4 o = buf[q * kScanBlock + tid];
-            if (c + 3 < nc) {
-                *reinterpret_cast<int4*>(a.start + c) = o;
-                *reinterpret_cast<int4*>(a.count + c) = make_int4(0, 0, 0, 0);
-            } else {
-                if (c < nc) { a.start[c] = o.x; a.count[c] = 0; }
-                if (c + 1 < nc) { a.start[c + 1] = o.y; a.count[c + 1] = 0; }
-                if (c + 2 < nc) { a.start[c + 2] = o.z; a.count[c + 2] = 0; }
-            }
+        for (int j = 0; j < kScanBlocks; ++j) {
+            if (b0 + j < nb) a.bstart[b0 + j] = run;
+            run += bsum[j];
         }
         carry += tile_tot;
         __syncthreads();
     }
-    if (tid == 0) a.start[nc] = carry;
-}
-
-// The error word is read alongside the kernels' first loads (not before them),
-// so a pending order error costs no extra memory round trip; nothing is
-// written, and nothing is read through a loaded index, once it is seen.
-__global__ void __launch_bounds__(kBlock) k_scatter(SimArgs a, bool from_step) {
-    const int err = a.hdr[HDR_ERROR];
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    int c = 0, r = 0;
-    if (i < a.n) {
-        c = a.cell[i];
-        r = a.rank[i];
+    if (tid == 0) {
+        a.hdr[HDR_OVF_READ] = a.hdr[HDR_OVF];
+        a.hdr[HDR_OVF] = 0;
     }
-    if (from_step && (err & DEV_ORDER)) return;
-    if (i < a.n) a.key[a.start[c] + r] = i;
 }
 
-// In-cell order: the members of cell c (staging slots key[start .. start + n))
-// are ranked by user index and moved to pos0/vel0[start + rank], which makes
-// the sorted layout independent of the arrival order of the histogram
-// atomics. One 16-lane group per cell, 16 cells per workgroup; a lane holds
-// two members (sub and sub + 16) of each 32-member window. A member's rank
-// counts the smaller indices of its cell: each window's indices are put in
-// LDS and every lane reads them back four at a time (a broadcast within the
-// group). Loop bounds are the workgroup's largest cell, so the barriers are
-// uniform.
+// Cell order. Workgroup b owns cells c0 = 16 b .. c0 + 15 (one block of the
+// block histogram): the offset of cell c is bstart[b] plus the owned cells
+// before c. For a batch the cells of all replicas are one sequence, so the
+// offset of a replica's first cell is its first atom. The workgroup writes
+// its cells' offsets and clears their counts.
+// Members of a cell are bucket entries 0 .. min(n, cap) - 1 and the cell's
+// entries of the overflow list beyond that. They are ranked by user index and
+// moved to pos0/vel0[start + rank], which makes the sorted layout independent
+// of the arrival order of the binning atomics. One 16-lane group per cell; a
+// lane holds two members (sub and sub + 16) of each 32-member window, and a
+// member's rank counts the smaller indices of its cell, read four at a time
+// from the window's indices in LDS. Loop bounds are the workgroup's largest
+// cell, so the barriers are uniform.
 constexpr int kOrderBlock = 256;
 constexpr int kOrderGroup = 16;
 constexpr int kOrderWin = 2 * kOrderGroup;
 constexpr int kOrderCells = kOrderBlock / kOrderGroup;
 constexpr int kNoId = 0x7fffffff;  // larger than any user index
 
-__device__ __forceinline__ int staged_id(const SimArgs& a, int first, int m, int n) {
-    return m < n ? __float_as_int(a.pos1[a.key[first + m]].w) : kNoId;
+// Staging slot of member m of cell c (clamped to a valid slot, so that even
+// an inconsistent workspace is never read out of bounds).
+__device__ __forceinline__ int member_slot(const SimArgs& a, int c, int m, int novf) {
+    if (m < a.cap) {
+        const int k = a.bucket[static_cast<size_t>(c) * a.cap + m];
+        return static_cast<unsigned>(k) < static_cast<unsigned>(a.natoms) ? k : 0;
+    }
+    int want = m - a.cap;  // the want-th overflow entry of cell c (rare: a cell beyond its capacity)
+    for (int j = 0; j < novf; ++j) {
+        const int2 e = a.ovf[j];
+        if (e.x == c) {
+            if (want == 0) return static_cast<unsigned>(e.y) < static_cast<unsigned>(a.natoms) ? e.y : 0;
+            --want;
+        }
+    }
+    return 0;  // not reached while the histogram and the list agree
+}
+
+__device__ __forceinline__ int member_id(const SimArgs& a, int c, int m, int n, int novf) {
+    return m < n ? __float_as_int(a.pos1[member_slot(a, c, m, novf)].w) : kNoId;
 }
 
 __device__ __forceinline__ int count_below(int4 k, int id) {
@@ -298,37 +251,43 @@ __device__ __forceinline__ int count_below(int4 k, int id) {
 }
 
 __global__ void __launch_bounds__(kOrderBlock) k_cell_order(SimArgs a, bool from_step) {
+    static_assert(kOrderCells == (1 << kBlockShift), "a cell-order workgroup owns one histogram block");
     __shared__ int4 win[kOrderCells][kOrderWin / 4];
-    __shared__ int wave_max[kOrderBlock / kWave];
+    __shared__ int cnt_s[kOrderCells];
     const int err = a.hdr[HDR_ERROR];
-    const int cl = threadIdx.x / kOrderGroup;
-    const int c = blockIdx.x * kOrderCells + cl;
-    const int sub = threadIdx.x & (kOrderGroup - 1);
-    int first = 0, n = 0;
-    if (c < a.ncells) {
-        first = a.start[c];
-        n = a.start[c + 1] - first;
-    }
+    const int tid = threadIdx.x;
+    const int cl = tid / kOrderGroup, sub = tid & (kOrderGroup - 1);
+    const int c0 = blockIdx.x * kOrderCells, c = c0 + cl;
+    const int nct = a.ncells;
+    const int n = c < nct ? a.counts[c] : 0;
+    const int base = a.bstart[blockIdx.x];
+    const int novf = min(a.hdr[HDR_OVF_READ], a.natoms);
     if (from_step && (err & DEV_ORDER)) return;  // uniform over the workgroup
-    int nmax = max(n, __shfl_xor(n, 16));
-    nmax = max(nmax, __shfl_xor(nmax, 32));
-    if ((threadIdx.x & (kWave - 1)) == 0) wave_max[threadIdx.x / kWave] = nmax;
+    if (sub == 0) cnt_s[cl] = n;
     __syncthreads();
+    int first = base;
+    for (int j = 0; j < cl; ++j) first += cnt_s[j];
+    int nmax = 0;
 #pragma unroll
-    for (int w = 0; w < kOrderBlock / kWave; ++w) nmax = max(nmax, wave_max[w]);
+    for (int j = 0; j < kOrderCells; ++j) nmax = max(nmax, cnt_s[j]);
+    if (c < nct && sub == 0) {
+        a.start[c] = first;
+        if (c == nct - 1) a.start[nct] = first + n;
+        a.counts[c] = 0;  // the next build's histogram
+    }
     int* wids = reinterpret_cast<int*>(win[cl]);
     for (int m0 = 0; m0 < nmax; m0 += kOrderWin) {
         const int ma = m0 + sub, mb = ma + kOrderGroup;
         float4 pa = make_float4(0.f, 0.f, 0.f, 0.f), va = pa, pb = pa, vb = pa;
         int ida = kNoId, idb = kNoId;
         if (ma < n) {
-            const int src = a.key[first + ma];
+            const int src = member_slot(a, c, ma, novf);
             pa = a.pos1[src];
             va = a.vel1[src];
             ida = __float_as_int(pa.w);
         }
         if (mb < n) {
-            const int src = a.key[first + mb];
+            const int src = member_slot(a, c, mb, novf);
             pb = a.pos1[src];
             vb = a.vel1[src];
             idb = __float_as_int(pb.w);
@@ -337,8 +296,8 @@ __global__ void __launch_bounds__(kOrderBlock) k_cell_order(SimArgs a, bool from
         for (int k0 = 0; k0 < nmax; k0 += kOrderWin) {
             int ka = ida, kb = idb;
             if (k0 != m0) {
-                ka = staged_id(a, first, k0 + sub, n);
-                kb = staged_id(a, first, k0 + kOrderGroup + sub, n);
+                ka = member_id(a, c, k0 + sub, n, novf);
+                kb = member_id(a, c, k0 + kOrderGroup + sub, n, novf);
             }
             __syncthreads();  // the previous window has been read
             wids[sub] = ka;
@@ -351,16 +310,18 @@ __global__ void __launch_bounds__(kOrderBlock) k_cell_order(SimArgs a, bool from
                 rb += count_below(k4, idb);
             }
         }
-        if (ma < n) {
+        // (a consistent histogram keeps first + n within the atoms; the guard
+        // keeps an inconsistent one from writing past them)
+        if (ma < n && first + ra < a.natoms) {
             a.pos0[first + ra] = pa;
             a.vel0[first + ra] = va;
         }
-        if (mb < n) {
+        if (mb < n && first + rb < a.natoms) {
             a.pos0[first + rb] = pb;
             a.vel0[first + rb] = vb;
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0 && !from_step) a.hdr[HDR_STATE] = STATE_CELLS;
+    if (blockIdx.x == 0 && tid == 0 && !from_step) a.hdr[HDR_STATE] = STATE_CELLS;
 }
 
 __global__ void __launch_bounds__(kBlock) k_gather_user(SimArgs a, float4* pos_out, float4* vel_out,
@@ -397,12 +358,12 @@ __global__ void __launch_bounds__(kBlock) k_cell_lists(SimArgs a, int* cell_star
 
 inline int blocks_for(int n, int b) { return (n + b - 1) / b; }
 
+inline int clamp_blocks(int b) { return b < 1 ? 1 : (b > 4096 ? 4096 : b); }
+
 }  // namespace
 
 hipError_t launch_build_init(const SimArgs& a, hipStream_t st) {
-    int g = blocks_for(a.ncells, kBlock);
-    g = g < 1 ? 1 : (g > 4096 ? 4096 : g);
-    hipLaunchKernelGGL(k_build_init, dim3(g), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_build_init, dim3(clamp_blocks(blocks_for(a.ncells, kBlock))), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 
@@ -416,19 +377,13 @@ hipError_t launch_integrate(const SimArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_scan(const SimArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanBlock), 0, st, a, true);
-    return hipGetLastError();
-}
-
-hipError_t launch_scatter(const SimArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(a.n, kBlock)), dim3(kBlock), 0, st, a, true);
+hipError_t launch_block_scan(const SimArgs& a, bool from_step, hipStream_t st) {
+    hipLaunchKernelGGL(k_block_scan, dim3(1), dim3(kScanBlock), 0, st, a, from_step);
     return hipGetLastError();
 }
 
 hipError_t launch_cell_order(const SimArgs& a, bool from_step, hipStream_t st) {
-    hipLaunchKernelGGL(k_cell_order, dim3(blocks_for(a.ncells, kOrderCells)), dim3(kOrderBlock), 0, st, a,
-                       from_step);
+    hipLaunchKernelGGL(k_cell_order, dim3(a.nblocks), dim3(kOrderBlock), 0, st, a, from_step);
     return hipGetLastError();
 }
 
@@ -455,11 +410,6 @@ hipError_t launch_batch_load(const SimArgs& base, const Replica* reps, const int
 hipError_t launch_batch_integrate(const SimArgs& base, const Replica* reps, const int* atom_rep, hipStream_t st) {
     hipLaunchKernelGGL(k_batch_integrate, dim3(blocks_for(base.n, kBlock)), dim3(kBlock), 0, st, base, reps,
                        atom_rep);
-    return hipGetLastError();
-}
-
-hipError_t launch_batch_scan(const SimArgs& base, const Replica* reps, int count, hipStream_t st) {
-    hipLaunchKernelGGL(k_batch_scan, dim3(count), dim3(kBlock), 0, st, base, reps, count);
     return hipGetLastError();
 }
 

@@ -64,7 +64,7 @@ struct ForceOp {
 // a); one wavefront. Energy partials go to a.epart[3 (a.cbase + c) + 0..2].
 // KICK completes the step's velocity (v += dt/(2m) F). DRIFT (with KICK) goes
 // on into the next step's first half with the same force, as the drift kernel
-// would (half kick, drift, wrap, cell, histogram rank), and writes the staging
+// would (half kick, drift, wrap, cell, binning), and writes the staging
 // arrays for the next rebuild instead of vel0; force and vel0 are then left
 // stale, since the rebuild replaces the sorted state.
 template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT>
@@ -174,13 +174,11 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
             }
         }
         if (DRIFT) {
-            const int r = histogram_rank(a.count, c_next);  // all lanes
             if (c_next >= 0) {
                 a.pos1[k] = p_next;
                 a.vel1[k] = v_next;
-                a.cell[k] = c_next;
-                a.rank[k] = r;
             }
+            bin_atom(a, k, c_next);  // all lanes
         }
     }
     if (bad) atomicOr(&a.hdr[HDR_ERROR], DEV_NONFINITE);
@@ -371,7 +369,8 @@ hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st) {
 }
 
 hipError_t launch_batch_forces(const SimArgs& base, const Replica* reps, const int* cell_rep, int total_cells,
-                               int max_tile_cap, bool kick, bool energy, bool write_force, bool drift, hipStream_t st) {
+                               int max_tile_cap, bool kick, bool energy, bool write_force, bool drift,
+                               hipStream_t st) {
     const dim3 g(total_cells), b(kWave);
     const size_t lds = sizeof(float4) * static_cast<size_t>(max_tile_cap + kTilePad);
 #define MD_FORCES(K, E, W, D) \

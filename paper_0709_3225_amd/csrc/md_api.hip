@@ -72,6 +72,28 @@ int cells_per_dim(const md_params* p) {
     return nc;
 }
 
+// Bucket entries per cell: twice the mean occupancy plus 16, in multiples of
+// 16. A liquid's cells rarely hold more than 1.5 times the mean; atoms beyond
+// the capacity go to the overflow list, which is correct at any occupancy and
+// slow only for cells that use it.
+int bucket_capacity(double mean_occupancy) {
+    const int cap = static_cast<int>(std::ceil((2.0 * mean_occupancy + 16.0) / 16.0)) * 16;
+    return std::min(1024, std::max(32, cap));
+}
+
+// Histograms, buckets, overflow list and CSR offsets of a build over n atoms
+// in ncells cells.
+template <class Take>
+void take_build_arrays(Layout& L, size_t n, size_t ncells, int cap, Take& take) {
+    L.nblocks = static_cast<int>((ncells + (size_t{1} << kBlockShift) - 1) >> kBlockShift);
+    L.cap = cap;
+    L.counts = take(4 * (static_cast<size_t>(L.nblocks) << kBlockShift));  // whole blocks, padding stays zero
+    L.bstart = take(4 * static_cast<size_t>(L.nblocks) + 16);
+    L.bucket = take(4 * ncells * static_cast<size_t>(cap));
+    L.ovf = take(8 * n);
+    L.start = take(4 * (ncells + 1) + 16);
+}
+
 md_status make_layout(const md_params* p, Layout& L) {
     md_status s = validate(p);
     if (s != MD_OK) return s;
@@ -96,11 +118,8 @@ md_status make_layout(const md_params* p, Layout& L) {
     L.pos1 = take(16 * n);
     L.vel1 = take(16 * n);
     L.force = take(16 * n);
-    L.cell = take(4 * n);
-    L.rank = take(4 * n);
-    L.key = take(4 * n);
-    L.count = take(4 * static_cast<size_t>(L.ncells) + 16);
-    L.start = take(4 * (static_cast<size_t>(L.ncells) + 1) + 16);
+    take_build_arrays(L, n, static_cast<size_t>(L.ncells), bucket_capacity(static_cast<double>(p->n) / L.ncells),
+                      take);
     L.epart = take(sizeof(double) * 3 * static_cast<size_t>(L.nforce_blocks));
     L.total = off;
     return MD_OK;
@@ -140,11 +159,14 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     a.pos1 = reinterpret_cast<float4*>(b + L.pos1);
     a.vel1 = reinterpret_cast<float4*>(b + L.vel1);
     a.force = reinterpret_cast<float4*>(b + L.force);
-    a.cell = reinterpret_cast<int*>(b + L.cell);
-    a.rank = reinterpret_cast<int*>(b + L.rank);
-    a.key = reinterpret_cast<int*>(b + L.key);
-    a.count = reinterpret_cast<int*>(b + L.count);
+    a.counts = reinterpret_cast<int*>(b + L.counts);
+    a.bstart = reinterpret_cast<int*>(b + L.bstart);
+    a.bucket = reinterpret_cast<int*>(b + L.bucket);
+    a.ovf = reinterpret_cast<int2*>(b + L.ovf);
     a.start = reinterpret_cast<int*>(b + L.start);
+    a.nblocks = L.nblocks;
+    a.cap = L.cap;
+    a.natoms = L.n;
     a.epart = reinterpret_cast<double*>(b + L.epart);
     a.n = L.n;
     a.nc = L.nc;
@@ -179,18 +201,14 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
         if (e_ != hipSuccess) return hip_fail(e_, where); \
     } while (0)
 
-md_status rebuild_from_staging(const SimArgs& a, bool from_step, hipStream_t st) {
-    MD_TRY_HIP(launch_scan(a, st), "scan");
-    MD_TRY_HIP(launch_scatter(a, st), "scatter");
-    MD_TRY_HIP(launch_cell_order(a, from_step, st), "cell order");
-    return MD_OK;
-}
+
 
 // ---- batches of independent replicas -------------------------------------
 
 struct BatchPlan {
     Layout L;                    // shared arrays; n = total atoms, ncells = total cells
     int count = 0, max_tile = 0;
+    double max_mean = 0.0;  // largest mean cell occupancy of any replica
     size_t reps = 0, atom_rep = 0, cell_rep = 0;
     std::vector<Replica> table;  // host copy of the replica table
 };
@@ -229,6 +247,7 @@ md_status batch_plan(const md_params* p, const md_replica* reps, int32_t count, 
         r.inv_s = Lb.inv_s;
         r.screen2 = screen_bound(static_cast<double>(cutoff(&q)), Lb.s);
         B.max_tile = std::max(B.max_tile, r.tile_cap);
+        B.max_mean = std::max(B.max_mean, static_cast<double>(q.n) / Lb.ncells);
         ntot += q.n;
         ctot += Lb.ncells;
         if (ntot > kMaxAtoms) return fail(MD_ERR_ARG, "batch holds more than 2^27 atoms");
@@ -255,11 +274,7 @@ md_status batch_plan(const md_params* p, const md_replica* reps, int32_t count, 
     L.pos1 = take(16 * n);
     L.vel1 = take(16 * n);
     L.force = take(16 * n);
-    L.cell = take(4 * n);
-    L.rank = take(4 * n);
-    L.key = take(4 * n);
-    L.count = take(4 * c + 16);
-    L.start = take(4 * (c + 1) + 16);
+    take_build_arrays(L, n, c, bucket_capacity(B.max_mean), take);
     L.epart = take(sizeof(double) * 3 * c);
     L.total = off;
     return MD_OK;
@@ -300,8 +315,7 @@ md_status batch_steps(const BatchPlan& B, const BatchArgs& ba, int32_t nsteps, i
         const bool energy = thermo && thermo_every > 0 && (k % thermo_every) == 0;
         const bool last = k == nsteps;
         if (k == 1) MD_TRY_HIP(launch_batch_integrate(ba.base, ba.reps, ba.atom_rep, st), "batch integrate");
-        MD_TRY_HIP(launch_batch_scan(ba.base, ba.reps, B.count, st), "batch scan");
-        MD_TRY_HIP(launch_scatter(ba.base, st), "batch scatter");
+        MD_TRY_HIP(launch_block_scan(ba.base, true, st), "batch block scan");
         MD_TRY_HIP(launch_cell_order(ba.base, true, st), "batch cell order");
         MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, true, energy, last,
                                        !last, st),
@@ -348,7 +362,9 @@ md_status md_build_cells(const md_params* p, void* ws, size_t ws_bytes, const fl
     MD_TRY_HIP(launch_build_init(a, stream), "build init");
     MD_TRY_HIP(launch_load(a, reinterpret_cast<const float4*>(pos4), reinterpret_cast<const float4*>(vel4), stream),
                "load");
-    return rebuild_from_staging(a, false, stream);
+    MD_TRY_HIP(launch_block_scan(a, false, stream), "block scan");
+    MD_TRY_HIP(launch_cell_order(a, false, stream), "cell order");
+    return MD_OK;
 }
 
 md_status md_forces(const md_params* p, void* ws, size_t ws_bytes, float* force4, hipStream_t stream) {
@@ -374,12 +390,14 @@ md_status md_step(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps,
     if (thermo_every > 0 && !thermo) return fail(MD_ERR_ARG, "thermo_every > 0 needs a thermo buffer");
     const SimArgs a = make_args(p, L, ws);
     // The force pass of every step but the last also performs the next step's
-    // half kick and drift, so the drift kernel runs only on the first step.
+    // half kick, drift and binning, so the drift kernel runs only on the first
+    // step; a rebuild is then the block scan and the cell order.
     for (int32_t k = 1; k <= nsteps; ++k) {
         const bool energy = thermo && thermo_every > 0 && (k % thermo_every) == 0;
         const bool last = k == nsteps;
         if (k == 1) MD_TRY_HIP(launch_integrate(a, stream), "integrate");
-        if ((s = rebuild_from_staging(a, true, stream)) != MD_OK) return s;
+        MD_TRY_HIP(launch_block_scan(a, true, stream), "block scan");
+        MD_TRY_HIP(launch_cell_order(a, true, stream), "cell order");
         MD_TRY_HIP(launch_forces(a, true, energy, last, true, !last, stream), "forces");
         if (energy)
             MD_TRY_HIP(launch_energy_final(a, thermo + 3 * static_cast<size_t>(k / thermo_every - 1), stream),
@@ -505,12 +523,12 @@ md_status md_batch_build(const md_params* p, const md_replica* reps, int32_t cou
                               hipMemcpyHostToDevice, stream),
                "replica table upload");
     MD_TRY_HIP(hipStreamSynchronize(stream), "replica table upload");
+    MD_TRY_HIP(launch_build_init(ba.base, stream), "batch init");
     MD_TRY_HIP(launch_batch_setup(ba.base, ba.reps, ba.atom_rep, ba.cell_rep, B.count, stream), "batch setup");
     MD_TRY_HIP(launch_batch_load(ba.base, ba.reps, ba.atom_rep, reinterpret_cast<const float4*>(pos4),
                                  reinterpret_cast<const float4*>(vel4), stream),
                "batch load");
-    MD_TRY_HIP(launch_batch_scan(ba.base, ba.reps, B.count, stream), "batch scan");
-    MD_TRY_HIP(launch_scatter(ba.base, stream), "batch scatter");
+    MD_TRY_HIP(launch_block_scan(ba.base, false, stream), "batch block scan");
     MD_TRY_HIP(launch_cell_order(ba.base, false, stream), "batch cell order");
     return MD_OK;
 }

@@ -61,8 +61,9 @@ __device__ __forceinline__ int half_kick_drift(const SimArgs& a, float4& p, floa
 // Arrival rank of each lane's atom in cell c (c < 0: no atom). Lanes holding
 // the same cell in a contiguous run share one atomicAdd of the run length on
 // the histogram; input that is already cell-sorted (every step after the
-// first) turns most per-atom atomics into one per run. Must be called by all
-// 64 lanes of the wave.
+// first) turns most per-atom atomics into one per run. Atomics on one address
+// serialise (about 0.15 us each here), so nothing coarser than a cell is
+// counted atomically. Must be called by all 64 lanes of the wave.
 __device__ __forceinline__ int histogram_rank(int* count, int c) {
     const int lane = __lane_id();
     const int prev = __shfl_up(c, 1);
@@ -76,6 +77,27 @@ __device__ __forceinline__ int histogram_rank(int* count, int c) {
     if (head && c >= 0) base = atomicAdd(&count[c], next_head - lane);
     base = __shfl(base, my_head);
     return base + (lane - my_head);
+}
+
+// Bin staging slot k into cell c (global index; c < 0: this lane has no
+// atom): rank in the cell, then the slot goes to the cell's bucket, or to the
+// overflow list once the bucket is full. Must be called by all 64 lanes.
+__device__ __forceinline__ void bin_atom(const SimArgs& a, int k, int c) {
+    const int r = histogram_rank(a.counts, c);
+    if (c < 0) return;
+    if (r < a.cap) {
+        a.bucket[static_cast<size_t>(c) * a.cap + r] = k;
+    } else {
+        const int j = atomicAdd(&a.hdr[HDR_OVF], 1);
+        if (j < a.natoms) a.ovf[j] = make_int2(c, k);
+        else atomicOr(&a.hdr[HDR_ERROR], DEV_ORDER);  // histogram not cleared: a call sequence was cut short
+    }
+}
+
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {

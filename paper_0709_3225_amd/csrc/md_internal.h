@@ -12,11 +12,17 @@ namespace mdlj {
 // HDR_N and HDR_NC record the particle count and cell grid the workspace was
 // built for; kernels refuse a workspace whose record differs from their
 // arguments (its array offsets would not match).
-enum : int { HDR_ERROR = 0, HDR_STATE = 1, HDR_N = 2, HDR_NC = 3, HDR_WORDS = 64 };
+// HDR_OVF counts the overflow-list entries being binned; the block scan moves
+// it to HDR_OVF_READ (read by the cell order) and clears it.
+enum : int { HDR_ERROR = 0, HDR_STATE = 1, HDR_N = 2, HDR_NC = 3, HDR_OVF = 4, HDR_OVF_READ = 5, HDR_WORDS = 64 };
 
 // Workspace states. Distinctive values so that an uninitialised workspace is
 // never mistaken for a built one.
 enum : int { STATE_BUILDING = 0x4D440000, STATE_CELLS = 0x4D440001, STATE_FORCES = 0x4D440002 };
+
+// The cell order runs one workgroup per block of 2^kBlockShift consecutive
+// cells; the block scan gives each block its first atom.
+constexpr int kBlockShift = 4;
 
 // Device error bits (same values as the public MD_DEV_* macros).
 enum : int { DEV_NONFINITE = 1, DEV_ORDER = 2, DEV_NB_OVERFLOW = 4 };
@@ -29,12 +35,16 @@ struct SimArgs {
     float4* pos1;    // unsorted staging (after load or drift), w = user index bits
     float4* vel1;
     float4* force;   // cell-sorted forces
-    int* cell;       // cell of each staging slot
-    int* rank;       // arrival rank of each staging slot within its cell
-    int* key;        // sorted slot -> staging slot (before the in-cell order)
-    int* count;      // per-cell histogram (kept zero between builds)
+    // Cell build: per-cell histogram, zero between builds; a binned atom's
+    // staging slot goes to its cell's bucket of cap entries, or to the
+    // overflow list past the capacity.
+    int* counts;     // ncells (+ 16 zero padding)
+    int* bstart;     // nblocks = ceil(ncells / 16): atoms before each block of 16 cells
+    int* bucket;     // ncells x cap staging slots
+    int2* ovf;       // (cell, staging slot) pairs, one per atom at most
     int* start;      // per-cell CSR offsets, ncells + 1 entries
     double* epart;   // per-block energy partials, 3 doubles per force block
+    int nblocks, cap, natoms;  // natoms: staging slots (all atoms of the workspace)
 
     int n;
     int nc;          // cells per dimension
@@ -70,18 +80,16 @@ struct Replica {
 struct Layout {
     int n, nc, ncells, nforce_blocks;
     float s, inv_s;
-    size_t hdr, pos0, vel0, pos1, vel1, force, cell, rank, key, count, start, epart, total;
+    int nblocks, cap;
+    size_t hdr, pos0, vel0, pos1, vel1, force, counts, bstart, bucket, ovf, start, epart, total;
 };
 
 // Kernel launchers (each returns hipGetLastError() after its launch).
 hipError_t launch_build_init(const SimArgs& a, hipStream_t st);
 hipError_t launch_load(const SimArgs& a, const float4* pos_in, const float4* vel_in, hipStream_t st);
-hipError_t launch_scan(const SimArgs& a, hipStream_t st);
-hipError_t launch_scatter(const SimArgs& a, hipStream_t st);
+hipError_t launch_block_scan(const SimArgs& a, bool from_step, hipStream_t st);
 hipError_t launch_cell_order(const SimArgs& a, bool from_step, hipStream_t st);
 hipError_t launch_integrate(const SimArgs& a, hipStream_t st);
-// drift (with kick, without write_force): the next step's first half fused
-// into the epilogue, writing the staging arrays for the next rebuild.
 hipError_t launch_forces(const SimArgs& a, bool kick, bool energy, bool write_force, bool from_step, bool drift,
                          hipStream_t st);
 hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st);
@@ -103,9 +111,9 @@ hipError_t launch_batch_setup(const SimArgs& base, const Replica* reps, int* ato
 hipError_t launch_batch_load(const SimArgs& base, const Replica* reps, const int* atom_rep, const float4* pos_in,
                              const float4* vel_in, hipStream_t st);
 hipError_t launch_batch_integrate(const SimArgs& base, const Replica* reps, const int* atom_rep, hipStream_t st);
-hipError_t launch_batch_scan(const SimArgs& base, const Replica* reps, int count, hipStream_t st);
 hipError_t launch_batch_forces(const SimArgs& base, const Replica* reps, const int* cell_rep, int total_cells,
-                               int max_tile_cap, bool kick, bool energy, bool write_force, bool drift, hipStream_t st);
+                               int max_tile_cap, bool kick, bool energy, bool write_force, bool drift,
+                               hipStream_t st);
 hipError_t launch_batch_energy_final(const SimArgs& base, const Replica* reps, int count, double* out, hipStream_t st);
 
 }  // namespace mdlj
