@@ -4,9 +4,9 @@
 //
 // A build is three launches:
 //   bin        : wrap + cell index + histogram rank (one atomic per run of
-//                equal cells in a wavefront); the atom's staging slot goes to
-//                its cell's bucket (or the overflow list beyond the bucket
-//                capacity).
+//                equal cells in a wavefront); the atom's position and
+//                velocity go to its cell's bucket (or the overflow list
+//                beyond the bucket capacity).
 //                Inside a multi-step run the force kernel's epilogue bins the
 //                drifted atoms, so this launch only starts a build or a run.
 //   block scan : one workgroup sums the histogram over blocks of 16 cells
@@ -37,12 +37,20 @@ __global__ void __launch_bounds__(kBlock) k_build_init(SimArgs a) {
         a.hdr[HDR_N] = a.n;
         a.hdr[HDR_NC] = a.nc;
         a.hdr[HDR_OVF] = 0;
-        a.hdr[HDR_OVF_READ] = 0;
+        a.hdr[HDR_OVF + 1] = 0;
     }
     for (int c = t; c < (a.nblocks << kBlockShift); c += stride) a.counts[c] = 0;
+    for (int b = t; b < 2 * a.nbstride; b += stride) a.bcounts[b] = 0;
 }
 
-// Load one user-order atom i into staging slot i: wrap, cell index, binning.
+// Clear the counters of parity par (overflow count, block histogram).
+__global__ void __launch_bounds__(kBlock) k_zero_blocks(SimArgs a, int par) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t == 0) a.hdr[HDR_OVF + par] = 0;
+    for (int b = t; b < a.nbstride; b += gridDim.x * kBlock) a.bcounts[par * a.nbstride + b] = 0;
+}
+
+// Load one user-order atom i: wrap, cell index, binning.
 // Called by every lane of the wave (valid = false for
 // lanes past the end); cells are numbered globally (a.cbase + local index).
 __device__ __forceinline__ void load_atom(const SimArgs& a, int i, bool valid, const float4* __restrict__ pos_in,
@@ -63,26 +71,22 @@ __device__ __forceinline__ void load_atom(const SimArgs& a, int i, bool valid, c
         p.w = __int_as_float(i);
         v.w = 0.f;
         c = a.cbase + cell_index(p.x, p.y, p.z, a);
-        a.pos1[i] = p;
-        a.vel1[i] = v;
     }
-    bin_atom(a, i, c);
+    bin_atom(a, p, v, c);
 }
 
 // Velocity-Verlet first half for sorted slot i (half kick, drift, wrap), then
-// the binning for the rebuild. Reads the sorted state, writes staging slot i.
-// Called by every lane of the wave.
+// the binning for the rebuild. Called by every lane of the wave.
 __device__ __forceinline__ void integrate_atom(const SimArgs& a, int i, bool valid) {
     int c = -1;
+    float4 p = make_float4(0.f, 0.f, 0.f, 0.f), v = p;
     if (valid) {
-        float4 p = a.pos0[i];
-        float4 v = a.vel0[i];
+        p = a.pos0[i];
+        v = a.vel0[i];
         const float4 f = a.force[i];
         c = half_kick_drift(a, p, v, f.x, f.y, f.z);
-        a.pos1[i] = p;
-        a.vel1[i] = v;
     }
-    bin_atom(a, i, c);
+    bin_atom(a, p, v, c);
 }
 
 __global__ void __launch_bounds__(kBlock) k_load(SimArgs a, const float4* __restrict__ pos_in,
@@ -145,7 +149,6 @@ __global__ void __launch_bounds__(kBlock) k_batch_setup(SimArgs base, const Repl
 // 128-byte runs) and all of a tile's loads are issued before any arithmetic.
 // A lane's blocks then get a running prefix, a wavefront scan and a scan of
 // the 16 wave totals give the lane's offset, and tiles are linked by a carry.
-// Hands the overflow count to the cell order.
 constexpr int kScanBlock = 1024;
 constexpr int kScanBlocks = 2;                          // blocks per lane per tile
 constexpr int kScanTile = kScanBlock * kScanBlocks;      // 2048 blocks = 32768 cells
@@ -199,10 +202,6 @@ __global__ void __launch_bounds__(kScanBlock) k_block_scan(SimArgs a, bool from_
         carry += tile_tot;
         __syncthreads();
     }
-    if (tid == 0) {
-        a.hdr[HDR_OVF_READ] = a.hdr[HDR_OVF];
-        a.hdr[HDR_OVF] = 0;
-    }
 }
 
 // Cell order. Workgroup b owns cells c0 = 16 b .. c0 + 15 (one block of the
@@ -224,26 +223,36 @@ constexpr int kOrderWin = 2 * kOrderGroup;
 constexpr int kOrderCells = kOrderBlock / kOrderGroup;
 constexpr int kNoId = 0x7fffffff;  // larger than any user index
 
-// Staging slot of member m of cell c (clamped to a valid slot, so that even
-// an inconsistent workspace is never read out of bounds).
-__device__ __forceinline__ int member_slot(const SimArgs& a, int c, int m, int novf) {
-    if (m < a.cap) {
-        const int k = a.bucket[static_cast<size_t>(c) * a.cap + m];
-        return static_cast<unsigned>(k) < static_cast<unsigned>(a.natoms) ? k : 0;
-    }
-    int want = m - a.cap;  // the want-th overflow entry of cell c (rare: a cell beyond its capacity)
+// Member m of cell c: bucket entry m, or past the capacity the cell's
+// (m - cap)-th entry of the overflow list (rare: a cell beyond its
+// capacity). Returns the overflow index, or -1 for a bucket entry.
+__device__ __forceinline__ int overflow_entry(const SimArgs& a, int c, int m, int novf) {
+    int want = m - a.cap;
     for (int j = 0; j < novf; ++j) {
-        const int2 e = a.ovf[j];
-        if (e.x == c) {
-            if (want == 0) return static_cast<unsigned>(e.y) < static_cast<unsigned>(a.natoms) ? e.y : 0;
+        if (a.ovf_cell[j] == c) {
+            if (want == 0) return j;
             --want;
         }
     }
     return 0;  // not reached while the histogram and the list agree
 }
 
+__device__ __forceinline__ void load_member(const SimArgs& a, int c, int m, int novf, float4& p, float4& v) {
+    if (m < a.cap) {
+        const size_t e = static_cast<size_t>(c) * a.cap + m;
+        p = a.bpos[e];
+        v = a.bvel[e];
+    } else {
+        const int j = overflow_entry(a, c, m, novf);
+        p = a.pos1[j];
+        v = a.vel1[j];
+    }
+}
+
 __device__ __forceinline__ int member_id(const SimArgs& a, int c, int m, int n, int novf) {
-    return m < n ? __float_as_int(a.pos1[member_slot(a, c, m, novf)].w) : kNoId;
+    if (m >= n) return kNoId;
+    const float4 p = m < a.cap ? a.bpos[static_cast<size_t>(c) * a.cap + m] : a.pos1[overflow_entry(a, c, m, novf)];
+    return __float_as_int(p.w);
 }
 
 __device__ __forceinline__ int count_below(int4 k, int id) {
@@ -254,18 +263,38 @@ __global__ void __launch_bounds__(kOrderBlock) k_cell_order(SimArgs a, bool from
     static_assert(kOrderCells == (1 << kBlockShift), "a cell-order workgroup owns one histogram block");
     __shared__ int4 win[kOrderCells][kOrderWin / 4];
     __shared__ int cnt_s[kOrderCells];
+    __shared__ int part_s[kOrderBlock / kWave];
     const int err = a.hdr[HDR_ERROR];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int cl = tid / kOrderGroup, sub = tid & (kOrderGroup - 1);
     const int c0 = blockIdx.x * kOrderCells, c = c0 + cl;
     const int nct = a.ncells;
+    // Everything the first window needs is requested at once: the first 32
+    // bucket entries of the cell (the capacity is at least 32; entries past
+    // the count are never used), its count, and the block offset (or the
+    // block counts before this block).
+    float4 pa0 = make_float4(0.f, 0.f, 0.f, 0.f), va0 = pa0, pb0 = pa0, vb0 = pa0;
+    if (c < nct) {
+        const size_t e = static_cast<size_t>(c) * a.cap + sub;
+        pa0 = a.bpos[e];
+        va0 = a.bvel[e];
+        pb0 = a.bpos[e + kOrderGroup];
+        vb0 = a.bvel[e + kOrderGroup];
+    }
     const int n = c < nct ? a.counts[c] : 0;
-    const int base = a.bstart[blockIdx.x];
-    const int novf = min(a.hdr[HDR_OVF_READ], a.natoms);
+    int part = 0;
+    if (a.direct) {
+        const int* bc = a.bcounts + a.par * a.nbstride;
+        for (int j = tid; j < static_cast<int>(blockIdx.x); j += kOrderBlock) part += bc[j];
+    }
+    const int bs = a.direct ? 0 : a.bstart[blockIdx.x];
+    const int novf = min(a.hdr[HDR_OVF + a.par], a.natoms);
     if (from_step && (err & DEV_ORDER)) return;  // uniform over the workgroup
+    part = wave_sum_int(part);
+    if (lane == 0) part_s[wave] = part;
     if (sub == 0) cnt_s[cl] = n;
     __syncthreads();
-    int first = base;
+    int first = a.direct ? part_s[0] + part_s[1] + part_s[2] + part_s[3] : bs;
     for (int j = 0; j < cl; ++j) first += cnt_s[j];
     int nmax = 0;
 #pragma unroll
@@ -275,23 +304,19 @@ __global__ void __launch_bounds__(kOrderBlock) k_cell_order(SimArgs a, bool from
         if (c == nct - 1) a.start[nct] = first + n;
         a.counts[c] = 0;  // the next build's histogram
     }
+    // the other parity's counters, for the next build
+    if (a.direct && tid == 0) a.bcounts[(1 - a.par) * a.nbstride + blockIdx.x] = 0;
+    if (blockIdx.x == 0 && tid == 0) a.hdr[HDR_OVF + 1 - a.par] = 0;
     int* wids = reinterpret_cast<int*>(win[cl]);
     for (int m0 = 0; m0 < nmax; m0 += kOrderWin) {
         const int ma = m0 + sub, mb = ma + kOrderGroup;
-        float4 pa = make_float4(0.f, 0.f, 0.f, 0.f), va = pa, pb = pa, vb = pa;
-        int ida = kNoId, idb = kNoId;
-        if (ma < n) {
-            const int src = member_slot(a, c, ma, novf);
-            pa = a.pos1[src];
-            va = a.vel1[src];
-            ida = __float_as_int(pa.w);
+        float4 pa = pa0, va = va0, pb = pb0, vb = vb0;
+        if (m0 > 0) {
+            if (ma < n) load_member(a, c, ma, novf, pa, va);
+            if (mb < n) load_member(a, c, mb, novf, pb, vb);
         }
-        if (mb < n) {
-            const int src = member_slot(a, c, mb, novf);
-            pb = a.pos1[src];
-            vb = a.vel1[src];
-            idb = __float_as_int(pb.w);
-        }
+        const int ida = ma < n ? __float_as_int(pa.w) : kNoId;
+        const int idb = mb < n ? __float_as_int(pb.w) : kNoId;
         int ra = 0, rb = 0;
         for (int k0 = 0; k0 < nmax; k0 += kOrderWin) {
             int ka = ida, kb = idb;
@@ -360,6 +385,12 @@ inline int blocks_for(int n, int b) { return (n + b - 1) / b; }
 
 inline int clamp_blocks(int b) { return b < 1 ? 1 : (b > 4096 ? 4096 : b); }
 
+inline SimArgs with_par(const SimArgs& a, int par) {
+    SimArgs b = a;
+    b.par = par;
+    return b;
+}
+
 }  // namespace
 
 hipError_t launch_build_init(const SimArgs& a, hipStream_t st) {
@@ -368,12 +399,12 @@ hipError_t launch_build_init(const SimArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_load(const SimArgs& a, const float4* pos_in, const float4* vel_in, hipStream_t st) {
-    hipLaunchKernelGGL(k_load, dim3(blocks_for(a.n, kBlock)), dim3(kBlock), 0, st, a, pos_in, vel_in);
+    hipLaunchKernelGGL(k_load, dim3(blocks_for(a.n, kBlock)), dim3(kBlock), 0, st, with_par(a, 0), pos_in, vel_in);
     return hipGetLastError();
 }
 
 hipError_t launch_integrate(const SimArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_integrate, dim3(blocks_for(a.n, kBlock)), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(k_integrate, dim3(blocks_for(a.n, kBlock)), dim3(kBlock), 0, st, with_par(a, 0));
     return hipGetLastError();
 }
 
@@ -382,8 +413,14 @@ hipError_t launch_block_scan(const SimArgs& a, bool from_step, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_cell_order(const SimArgs& a, bool from_step, hipStream_t st) {
-    hipLaunchKernelGGL(k_cell_order, dim3(a.nblocks), dim3(kOrderBlock), 0, st, a, from_step);
+hipError_t launch_cell_order(const SimArgs& a, int par, bool from_step, hipStream_t st) {
+    hipLaunchKernelGGL(k_cell_order, dim3(a.nblocks), dim3(kOrderBlock), 0, st, with_par(a, par), from_step);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_blocks(const SimArgs& a, int par, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_blocks, dim3(clamp_blocks(blocks_for(a.nbstride, kBlock))), dim3(kBlock), 0, st, a,
+                       par);
     return hipGetLastError();
 }
 
@@ -402,14 +439,14 @@ hipError_t launch_batch_setup(const SimArgs& base, const Replica* reps, int* ato
 
 hipError_t launch_batch_load(const SimArgs& base, const Replica* reps, const int* atom_rep, const float4* pos_in,
                              const float4* vel_in, hipStream_t st) {
-    hipLaunchKernelGGL(k_batch_load, dim3(blocks_for(base.n, kBlock)), dim3(kBlock), 0, st, base, reps, atom_rep,
-                       pos_in, vel_in);
+    hipLaunchKernelGGL(k_batch_load, dim3(blocks_for(base.n, kBlock)), dim3(kBlock), 0, st, with_par(base, 0), reps,
+                       atom_rep, pos_in, vel_in);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_integrate(const SimArgs& base, const Replica* reps, const int* atom_rep, hipStream_t st) {
-    hipLaunchKernelGGL(k_batch_integrate, dim3(blocks_for(base.n, kBlock)), dim3(kBlock), 0, st, base, reps,
-                       atom_rep);
+    hipLaunchKernelGGL(k_batch_integrate, dim3(blocks_for(base.n, kBlock)), dim3(kBlock), 0, st, with_par(base, 0),
+                       reps, atom_rep);
     return hipGetLastError();
 }
 

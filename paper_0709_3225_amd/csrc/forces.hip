@@ -64,9 +64,9 @@ struct ForceOp {
 // a); one wavefront. Energy partials go to a.epart[3 (a.cbase + c) + 0..2].
 // KICK completes the step's velocity (v += dt/(2m) F). DRIFT (with KICK) goes
 // on into the next step's first half with the same force, as the drift kernel
-// would (half kick, drift, wrap, cell, binning), and writes the staging
-// arrays for the next rebuild instead of vel0; force and vel0 are then left
-// stale, since the rebuild replaces the sorted state.
+// would (half kick, drift, wrap, cell, binning into the next rebuild's
+// buckets) instead of writing vel0; force and vel0 are then left stale, since
+// the rebuild replaces the sorted state.
 template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT>
 __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile, Neighbourhood& nb, float* red) {
     const int lane = threadIdx.x;
@@ -173,13 +173,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                 }
             }
         }
-        if (DRIFT) {
-            if (c_next >= 0) {
-                a.pos1[k] = p_next;
-                a.vel1[k] = v_next;
-            }
-            bin_atom(a, k, c_next);  // all lanes
-        }
+        if (DRIFT) bin_atom(a, p_next, v_next, c_next);  // all lanes
     }
     if (bad) atomicOr(&a.hdr[HDR_ERROR], DEV_NONFINITE);
     if (ENERGY) {
@@ -341,8 +335,10 @@ __global__ void __launch_bounds__(kWave) k_neighbors(SimArgs a, int* counts, int
 
 }  // namespace
 
-hipError_t launch_forces(const SimArgs& a, bool kick, bool energy, bool write_force, bool from_step, bool drift,
-                         hipStream_t st) {
+hipError_t launch_forces(const SimArgs& a_in, bool kick, bool energy, bool write_force, bool from_step, bool drift,
+                         int par, hipStream_t st) {
+    SimArgs a = a_in;
+    a.par = par;
     const dim3 g(a.ncells), b(kWave);
     const size_t lds = sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
 #define MD_FORCES(K, E, W, D) hipLaunchKernelGGL((k_forces<K, E, W, D>), g, b, lds, st, a, from_step)
@@ -368,9 +364,11 @@ hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch_forces(const SimArgs& base, const Replica* reps, const int* cell_rep, int total_cells,
-                               int max_tile_cap, bool kick, bool energy, bool write_force, bool drift,
+hipError_t launch_batch_forces(const SimArgs& base_in, const Replica* reps, const int* cell_rep, int total_cells,
+                               int max_tile_cap, bool kick, bool energy, bool write_force, bool drift, int par,
                                hipStream_t st) {
+    SimArgs base = base_in;
+    base.par = par;
     const dim3 g(total_cells), b(kWave);
     const size_t lds = sizeof(float4) * static_cast<size_t>(max_tile_cap + kTilePad);
 #define MD_FORCES(K, E, W, D) \

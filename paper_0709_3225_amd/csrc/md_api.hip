@@ -81,6 +81,8 @@ int bucket_capacity(double mean_occupancy) {
     return std::min(1024, std::max(32, cap));
 }
 
+size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
+
 // Histograms, buckets, overflow list and CSR offsets of a build over n atoms
 // in ncells cells.
 template <class Take>
@@ -89,8 +91,11 @@ void take_build_arrays(Layout& L, size_t n, size_t ncells, int cap, Take& take) 
     L.cap = cap;
     L.counts = take(4 * (static_cast<size_t>(L.nblocks) << kBlockShift));  // whole blocks, padding stays zero
     L.bstart = take(4 * static_cast<size_t>(L.nblocks) + 16);
-    L.bucket = take(4 * ncells * static_cast<size_t>(cap));
-    L.ovf = take(8 * n);
+    L.nbstride = static_cast<int>(round_up(static_cast<size_t>(L.nblocks), 64));
+    L.bcounts = take(4 * 2 * static_cast<size_t>(L.nbstride));
+    L.bpos = take(16 * ncells * static_cast<size_t>(cap));
+    L.bvel = take(16 * ncells * static_cast<size_t>(cap));
+    L.ovf_cell = take(4 * n);
     L.start = take(4 * (ncells + 1) + 16);
 }
 
@@ -161,12 +166,17 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     a.force = reinterpret_cast<float4*>(b + L.force);
     a.counts = reinterpret_cast<int*>(b + L.counts);
     a.bstart = reinterpret_cast<int*>(b + L.bstart);
-    a.bucket = reinterpret_cast<int*>(b + L.bucket);
-    a.ovf = reinterpret_cast<int2*>(b + L.ovf);
+    a.bpos = reinterpret_cast<float4*>(b + L.bpos);
+    a.bvel = reinterpret_cast<float4*>(b + L.bvel);
+    a.ovf_cell = reinterpret_cast<int*>(b + L.ovf_cell);
     a.start = reinterpret_cast<int*>(b + L.start);
     a.nblocks = L.nblocks;
     a.cap = L.cap;
     a.natoms = L.n;
+    a.bcounts = reinterpret_cast<int*>(b + L.bcounts);
+    a.nbstride = L.nbstride;
+    a.par = 0;
+    a.direct = L.nblocks <= kDirectBlocks ? 1 : 0;
     a.epart = reinterpret_cast<double*>(b + L.epart);
     a.n = L.n;
     a.nc = L.nc;
@@ -202,6 +212,13 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     } while (0)
 
 
+
+// Cell offsets and sorted arrays from the binned atoms (block histogram par).
+md_status rebuild(const SimArgs& a, int par, bool from_step, hipStream_t st) {
+    if (!a.direct) MD_TRY_HIP(launch_block_scan(a, from_step, st), "block scan");
+    MD_TRY_HIP(launch_cell_order(a, par, from_step, st), "cell order");
+    return MD_OK;
+}
 
 // ---- batches of independent replicas -------------------------------------
 
@@ -315,16 +332,17 @@ md_status batch_steps(const BatchPlan& B, const BatchArgs& ba, int32_t nsteps, i
         const bool energy = thermo && thermo_every > 0 && (k % thermo_every) == 0;
         const bool last = k == nsteps;
         if (k == 1) MD_TRY_HIP(launch_batch_integrate(ba.base, ba.reps, ba.atom_rep, st), "batch integrate");
-        MD_TRY_HIP(launch_block_scan(ba.base, true, st), "batch block scan");
-        MD_TRY_HIP(launch_cell_order(ba.base, true, st), "batch cell order");
+        md_status s = rebuild(ba.base, (k - 1) & 1, true, st);
+        if (s != MD_OK) return s;
         MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, true, energy, last,
-                                       !last, st),
+                                       !last, k & 1, st),
                    "batch forces");
         if (energy)
             MD_TRY_HIP(launch_batch_energy_final(ba.base, ba.reps, B.count,
                                                  thermo + 3 * static_cast<size_t>(B.count) * (k / thermo_every - 1), st),
                        "batch energy");
     }
+    if (nsteps > 0) MD_TRY_HIP(launch_zero_blocks(ba.base, (nsteps - 1) & 1, st), "batch counter clear");
     return MD_OK;
 }
 
@@ -362,8 +380,8 @@ md_status md_build_cells(const md_params* p, void* ws, size_t ws_bytes, const fl
     MD_TRY_HIP(launch_build_init(a, stream), "build init");
     MD_TRY_HIP(launch_load(a, reinterpret_cast<const float4*>(pos4), reinterpret_cast<const float4*>(vel4), stream),
                "load");
-    MD_TRY_HIP(launch_block_scan(a, false, stream), "block scan");
-    MD_TRY_HIP(launch_cell_order(a, false, stream), "cell order");
+    if ((s = rebuild(a, 0, false, stream)) != MD_OK) return s;
+    MD_TRY_HIP(launch_zero_blocks(a, 0, stream), "counter clear");
     return MD_OK;
 }
 
@@ -374,7 +392,7 @@ md_status md_forces(const md_params* p, void* ws, size_t ws_bytes, float* force4
     if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
     if (force4 && !aligned16(force4)) return fail(MD_ERR_ARG, "force array must be 16-byte aligned");
     const SimArgs a = make_args(p, L, ws);
-    MD_TRY_HIP(launch_forces(a, false, false, true, false, false, stream), "forces");
+    MD_TRY_HIP(launch_forces(a, false, false, true, false, false, 0, stream), "forces");
     if (force4) MD_TRY_HIP(launch_gather_user(a, nullptr, nullptr, reinterpret_cast<float4*>(force4), stream), "gather");
     return MD_OK;
 }
@@ -391,18 +409,20 @@ md_status md_step(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps,
     const SimArgs a = make_args(p, L, ws);
     // The force pass of every step but the last also performs the next step's
     // half kick, drift and binning, so the drift kernel runs only on the first
-    // step; a rebuild is then the block scan and the cell order.
+    // step; a rebuild is then the block scan (large grids) and the cell order.
+    // Step k's atoms are binned with parity (k - 1) mod 2; the counters of
+    // both parities are zero again on return.
     for (int32_t k = 1; k <= nsteps; ++k) {
         const bool energy = thermo && thermo_every > 0 && (k % thermo_every) == 0;
         const bool last = k == nsteps;
         if (k == 1) MD_TRY_HIP(launch_integrate(a, stream), "integrate");
-        MD_TRY_HIP(launch_block_scan(a, true, stream), "block scan");
-        MD_TRY_HIP(launch_cell_order(a, true, stream), "cell order");
-        MD_TRY_HIP(launch_forces(a, true, energy, last, true, !last, stream), "forces");
+        if ((s = rebuild(a, (k - 1) & 1, true, stream)) != MD_OK) return s;
+        MD_TRY_HIP(launch_forces(a, true, energy, last, true, !last, k & 1, stream), "forces");
         if (energy)
             MD_TRY_HIP(launch_energy_final(a, thermo + 3 * static_cast<size_t>(k / thermo_every - 1), stream),
                        "energy");
     }
+    if (nsteps > 0) MD_TRY_HIP(launch_zero_blocks(a, (nsteps - 1) & 1, stream), "counter clear");
     return MD_OK;
 }
 
@@ -413,7 +433,7 @@ md_status md_energy_virial(const md_params* p, void* ws, size_t ws_bytes, double
     if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
     if (!out3) return fail(MD_ERR_ARG, "output is NULL");
     const SimArgs a = make_args(p, L, ws);
-    MD_TRY_HIP(launch_forces(a, false, true, false, false, false, stream), "energy pass");
+    MD_TRY_HIP(launch_forces(a, false, true, false, false, false, 0, stream), "energy pass");
     MD_TRY_HIP(launch_energy_final(a, out3, stream), "energy");
     return MD_OK;
 }
@@ -528,8 +548,8 @@ md_status md_batch_build(const md_params* p, const md_replica* reps, int32_t cou
     MD_TRY_HIP(launch_batch_load(ba.base, ba.reps, ba.atom_rep, reinterpret_cast<const float4*>(pos4),
                                  reinterpret_cast<const float4*>(vel4), stream),
                "batch load");
-    MD_TRY_HIP(launch_block_scan(ba.base, false, stream), "batch block scan");
-    MD_TRY_HIP(launch_cell_order(ba.base, false, stream), "batch cell order");
+    if ((s = rebuild(ba.base, 0, false, stream)) != MD_OK) return s;
+    MD_TRY_HIP(launch_zero_blocks(ba.base, 0, stream), "batch counter clear");
     return MD_OK;
 }
 
@@ -540,7 +560,7 @@ md_status md_batch_forces(const md_params* p, const md_replica* reps, int32_t co
     if (s != MD_OK) return s;
     if (force4 && !aligned16(force4)) return fail(MD_ERR_ARG, "force array must be 16-byte aligned");
     const BatchArgs ba = batch_args(p, B, ws);
-    MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, false, false, true, false, stream),
+    MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, false, false, true, false, 0, stream),
                "batch forces");
     if (force4) MD_TRY_HIP(launch_gather_user(ba.base, nullptr, nullptr, reinterpret_cast<float4*>(force4), stream), "gather");
     return MD_OK;
@@ -564,7 +584,7 @@ md_status md_batch_energy_virial(const md_params* p, const md_replica* reps, int
     if (s != MD_OK) return s;
     if (!out) return fail(MD_ERR_ARG, "output is NULL");
     const BatchArgs ba = batch_args(p, B, ws);
-    MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, false, true, false, false, stream),
+    MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, false, true, false, false, 0, stream),
                "batch energy pass");
     MD_TRY_HIP(launch_batch_energy_final(ba.base, ba.reps, B.count, out, stream), "batch energy");
     return MD_OK;

@@ -61,10 +61,11 @@ __device__ __forceinline__ int half_kick_drift(const SimArgs& a, float4& p, floa
 // Arrival rank of each lane's atom in cell c (c < 0: no atom). Lanes holding
 // the same cell in a contiguous run share one atomicAdd of the run length on
 // the histogram; input that is already cell-sorted (every step after the
-// first) turns most per-atom atomics into one per run. Atomics on one address
-// serialise (about 0.15 us each here), so nothing coarser than a cell is
+// first) turns most per-atom atomics into one per run. bcount (nullable)
+// receives the run length per block of 16 cells too. Atomics on one address
+// serialise (about 0.15 us each here), so nothing coarser than 16 cells is
 // counted atomically. Must be called by all 64 lanes of the wave.
-__device__ __forceinline__ int histogram_rank(int* count, int c) {
+__device__ __forceinline__ int histogram_rank(int* count, int* bcount, int c) {
     const int lane = __lane_id();
     const int prev = __shfl_up(c, 1);
     const bool head = (lane == 0) || (prev != c);
@@ -74,23 +75,34 @@ __device__ __forceinline__ int histogram_rank(int* count, int c) {
     const int next_head = above ? (__ffsll(static_cast<unsigned long long>(above)) - 1) : kWave;
     const int my_head = 63 - __clzll(static_cast<long long>(heads & upto));
     int base = 0;
-    if (head && c >= 0) base = atomicAdd(&count[c], next_head - lane);
+    if (head && c >= 0) {
+        base = atomicAdd(&count[c], next_head - lane);
+        if (bcount) atomicAdd(&bcount[c >> kBlockShift], next_head - lane);
+    }
     base = __shfl(base, my_head);
     return base + (lane - my_head);
 }
 
-// Bin staging slot k into cell c (global index; c < 0: this lane has no
-// atom): rank in the cell, then the slot goes to the cell's bucket, or to the
-// overflow list once the bucket is full. Must be called by all 64 lanes.
-__device__ __forceinline__ void bin_atom(const SimArgs& a, int k, int c) {
-    const int r = histogram_rank(a.counts, c);
+// Bin an atom (position p with its user index in w, velocity v) into cell c
+// (global index; c < 0: this lane has no atom): rank in the cell, then the
+// atom goes to the cell's bucket, or to the overflow list once the bucket is
+// full. Must be called by all 64 lanes of the wave.
+__device__ __forceinline__ void bin_atom(const SimArgs& a, float4 p, float4 v, int c) {
+    const int r = histogram_rank(a.counts, a.direct ? a.bcounts + a.par * a.nbstride : nullptr, c);
     if (c < 0) return;
     if (r < a.cap) {
-        a.bucket[static_cast<size_t>(c) * a.cap + r] = k;
+        const size_t e = static_cast<size_t>(c) * a.cap + r;
+        a.bpos[e] = p;
+        a.bvel[e] = v;
     } else {
-        const int j = atomicAdd(&a.hdr[HDR_OVF], 1);
-        if (j < a.natoms) a.ovf[j] = make_int2(c, k);
-        else atomicOr(&a.hdr[HDR_ERROR], DEV_ORDER);  // histogram not cleared: a call sequence was cut short
+        const int j = atomicAdd(&a.hdr[HDR_OVF + a.par], 1);
+        if (j < a.natoms) {
+            a.ovf_cell[j] = c;
+            a.pos1[j] = p;
+            a.vel1[j] = v;
+        } else {
+            atomicOr(&a.hdr[HDR_ERROR], DEV_ORDER);  // histogram not cleared: a call sequence was cut short
+        }
     }
 }
 

@@ -12,17 +12,19 @@ namespace mdlj {
 // HDR_N and HDR_NC record the particle count and cell grid the workspace was
 // built for; kernels refuse a workspace whose record differs from their
 // arguments (its array offsets would not match).
-// HDR_OVF counts the overflow-list entries being binned; the block scan moves
-// it to HDR_OVF_READ (read by the cell order) and clears it.
-enum : int { HDR_ERROR = 0, HDR_STATE = 1, HDR_N = 2, HDR_NC = 3, HDR_OVF = 4, HDR_OVF_READ = 5, HDR_WORDS = 64 };
+// HDR_OVF + p counts the overflow-list entries of a build binned with parity
+// p (p = 0, 1; the same alternation as the block histograms).
+enum : int { HDR_ERROR = 0, HDR_STATE = 1, HDR_N = 2, HDR_NC = 3, HDR_OVF = 4, HDR_WORDS = 64 };
 
 // Workspace states. Distinctive values so that an uninitialised workspace is
 // never mistaken for a built one.
 enum : int { STATE_BUILDING = 0x4D440000, STATE_CELLS = 0x4D440001, STATE_FORCES = 0x4D440002 };
 
 // The cell order runs one workgroup per block of 2^kBlockShift consecutive
-// cells; the block scan gives each block its first atom.
+// cells; the block scan gives each block its first atom, or on grids of up to
+// kDirectBlocks blocks each workgroup sums the block counts before its own.
 constexpr int kBlockShift = 4;
+constexpr int kDirectBlocks = 2048;
 
 // Device error bits (same values as the public MD_DEV_* macros).
 enum : int { DEV_NONFINITE = 1, DEV_ORDER = 2, DEV_NB_OVERFLOW = 4 };
@@ -32,19 +34,27 @@ struct SimArgs {
     int* hdr;
     float4* pos0;    // cell-sorted positions, w = user index bits
     float4* vel0;    // cell-sorted velocities
-    float4* pos1;    // unsorted staging (after load or drift), w = user index bits
-    float4* vel1;
+    float4* pos1;    // overflow storage of the cell build (entry j of the list), and
+    float4* vel1;    // scratch for the adjoint between builds
     float4* force;   // cell-sorted forces
     // Cell build: per-cell histogram, zero between builds; a binned atom's
-    // staging slot goes to its cell's bucket of cap entries, or to the
-    // overflow list past the capacity.
+    // position and velocity go to its cell's bucket of cap entries, or to the
+    // overflow list (pos1, vel1 and the cell) past the capacity.
     int* counts;     // ncells (+ 16 zero padding)
     int* bstart;     // nblocks = ceil(ncells / 16): atoms before each block of 16 cells
-    int* bucket;     // ncells x cap staging slots
-    int2* ovf;       // (cell, staging slot) pairs, one per atom at most
+    // Builds alternate between two parities (par: the one being filled or
+    // read; the other's counters are zero): the overflow count, and on grids
+    // of at most kDirectBlocks blocks (direct != 0) a per-block atom count,
+    // two histograms nbstride entries apart, which lets the cell order sum the
+    // blocks before its own instead of reading bstart.
+    int* bcounts;
+    int nbstride, par, direct;
+    float4* bpos;    // ncells x cap bucket entries (w = user index bits)
+    float4* bvel;
+    int* ovf_cell;   // cell of overflow entry j, one entry per atom at most
     int* start;      // per-cell CSR offsets, ncells + 1 entries
     double* epart;   // per-block energy partials, 3 doubles per force block
-    int nblocks, cap, natoms;  // natoms: staging slots (all atoms of the workspace)
+    int nblocks, cap, natoms;  // natoms: all atoms of the workspace
 
     int n;
     int nc;          // cells per dimension
@@ -81,17 +91,22 @@ struct Layout {
     int n, nc, ncells, nforce_blocks;
     float s, inv_s;
     int nblocks, cap;
-    size_t hdr, pos0, vel0, pos1, vel1, force, counts, bstart, bucket, ovf, start, epart, total;
+    int nbstride;
+    size_t hdr, pos0, vel0, pos1, vel1, force, counts, bstart, bcounts, bpos, bvel, ovf_cell, start, epart, total;
 };
 
 // Kernel launchers (each returns hipGetLastError() after its launch).
 hipError_t launch_build_init(const SimArgs& a, hipStream_t st);
 hipError_t launch_load(const SimArgs& a, const float4* pos_in, const float4* vel_in, hipStream_t st);
+// par: the block histogram a cell order reads (ignored unless a.direct); the
+// binning launches (load, drift) fill histogram 0, the force pass's drift the
+// one given to launch_forces.
 hipError_t launch_block_scan(const SimArgs& a, bool from_step, hipStream_t st);
-hipError_t launch_cell_order(const SimArgs& a, bool from_step, hipStream_t st);
+hipError_t launch_cell_order(const SimArgs& a, int par, bool from_step, hipStream_t st);
+hipError_t launch_zero_blocks(const SimArgs& a, int par, hipStream_t st);
 hipError_t launch_integrate(const SimArgs& a, hipStream_t st);
 hipError_t launch_forces(const SimArgs& a, bool kick, bool energy, bool write_force, bool from_step, bool drift,
-                         hipStream_t st);
+                         int par, hipStream_t st);
 hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st);
 hipError_t launch_gather_user(const SimArgs& a, float4* pos_out, float4* vel_out, float4* force_out,
                               hipStream_t st);
@@ -112,7 +127,7 @@ hipError_t launch_batch_load(const SimArgs& base, const Replica* reps, const int
                              const float4* vel_in, hipStream_t st);
 hipError_t launch_batch_integrate(const SimArgs& base, const Replica* reps, const int* atom_rep, hipStream_t st);
 hipError_t launch_batch_forces(const SimArgs& base, const Replica* reps, const int* cell_rep, int total_cells,
-                               int max_tile_cap, bool kick, bool energy, bool write_force, bool drift,
+                               int max_tile_cap, bool kick, bool energy, bool write_force, bool drift, int par,
                                hipStream_t st);
 hipError_t launch_batch_energy_final(const SimArgs& base, const Replica* reps, int count, double* out, hipStream_t st);
 
