@@ -175,6 +175,52 @@ def test_cell_lists_full_size_after_steps(name):
     _check_cell_lists(pos4, box, steps=3, vel4=vel4)
 
 
+def _gas_with_cluster(box, n_gas, seed):
+    """Ideal gas at low density plus a 10^3 simple-cubic cluster of spacing
+    0.75 sigma in one corner: the cluster's cells hold about 40 atoms, past the
+    bucket capacity of a dilute grid (32), so binning uses the overflow list.
+    Gas atoms closer than 1 sigma to the cluster or to each other are dropped."""
+    rng = np.random.default_rng(seed)
+    g = 0.1 + 0.75 * np.arange(10)  # four planes inside the first cell on each axis
+    cl = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    pts = [p for p in cl]
+    gas = rng.uniform(0, box, (n_gas, 3))
+    for q in gas:
+        d = np.asarray(pts) - q
+        d -= box * np.round(d / box)
+        if (np.einsum("ij,ij->i", d, d) >= 1.0).all():
+            pts.append(q)
+    pos4 = np.zeros((len(pts), 4), np.float32)
+    pos4[:, :3] = np.asarray(pts)
+    vel4 = np.zeros_like(pos4)
+    vel4[:, :3] = rng.normal(0, 0.5, (len(pts), 3))
+    return pos4, vel4, np.float32(box)
+
+
+@pytest.mark.parametrize("box,n_gas", [(16.0, 100), (85.0, 3000)], ids=["direct_offsets", "block_scan"])
+def test_bucket_overflow_build_and_steps(box, n_gas, orc):
+    """Cells beyond the bucket capacity, on a grid whose cell order sums block
+    counts itself (16 sigma, 6^3 cells) and on one that needs the block scan
+    (85 sigma, 33^3 cells > 2048 blocks of 16): build, forces against the
+    oracle, three fused steps, cell-list invariants and forces again."""
+    pos4, vel4, box = _gas_with_cluster(box, n_gas, 31)
+    _say(f"bucket overflow box={box} n={len(pos4)}")
+    s = _system(len(pos4), box)
+    s.load(_dev(pos4), _dev(vel4))
+    f = s.forces().cpu().numpy()[:, :3]
+    assert s.check() == 0
+    fo, _, _ = orc.forces(orc.params(box), pos4)
+    assert rel_l2(f, fo) <= FORCE_TOL
+    s.step(3)
+    pos, _ = s.state()
+    f = s.forces().cpu().numpy()[:, :3]
+    assert s.check() == 0
+    p3 = pos.cpu().numpy()
+    fo, _, _ = orc.forces(orc.params(box), p3)
+    assert rel_l2(f, fo) <= FORCE_TOL
+    _check_cell_lists(p3, box)
+
+
 def test_fcc_lattice_energy_pin():
     """Perfect FCC at rho = 0.8442: U/N = -5.693278, W/N = -20.16527 from the
     textbook shells, with no oracle in the loop."""
