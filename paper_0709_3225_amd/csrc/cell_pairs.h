@@ -265,6 +265,58 @@ __device__ __forceinline__ void stage_commit(const HoodSegs& h, const StageBatch
     }
 }
 
+// Staging of a whole neighbourhood in one pass (total <= tile capacity), with
+// few instructions per segment: every lane of a wavefront loads and stores
+// entry pos + lane of each segment whether or not the segment has that many
+// atoms. Segments are written in order and tile [0, total) without gaps, so
+// the surplus entries of segment k (indices pos_k + len_k .. pos_k + 63) are
+// overwritten by a later segment, or fall into the padding after total,
+// which the caller fills afterwards; loads past the arrays' end are clamped.
+// Atoms 64 and up of a longer segment follow, masked, after every segment's
+// first 64: no surplus store reaches that far (pos_j + 63 < pos_k + 64 for
+// j < k). The tile needs room for total + 63 entries.
+template <bool ID_IN_W>
+__device__ __forceinline__ void stage_whole(const SimArgs& a, const HoodSegs& h, float4* tile) {
+    const int lane = threadIdx.x;
+    const int nseg = h.nseg();  // 9 or 27
+    const int last = a.natoms - 1;
+    // 32-bit byte offsets from the array base (scalar base + vector offset loads)
+    const char* pbase = reinterpret_cast<const char*>(a.pos0);
+    for (int k0 = 0; k0 < nseg; k0 += 9) {
+        float4 q[9];
+#pragma unroll
+        for (int u = 0; u < 9; ++u) {
+            const uint32_t off = static_cast<uint32_t>(min(lane_value(h.first, k0 + u) + lane, last)) << 4;
+            q[u] = *reinterpret_cast<const float4*>(pbase + off);
+        }
+#pragma unroll
+        for (int u = 0; u < 9; ++u) {
+            const int k = k0 + u;
+            const float x = q[u].x - lane_value(h.x, k);
+            const float y = q[u].y - lane_value(h.y, k);
+            const float z = q[u].z - lane_value(h.z, k);
+            tile[lane_value(h.pos, k) + lane] = make_float4(x, y, z, ID_IN_W ? q[u].w : x * x + y * y + z * z);
+            // store as each load arrives: nine results held for one burst of
+            // stores would cost 36 more registers
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    uint64_t longs = __ballot(lane < nseg && h.len > kWave);
+    while (longs) {
+        const int k = __ffsll(static_cast<unsigned long long>(longs)) - 1;
+        longs &= longs - 1;
+        const int len = lane_value(h.len, k), first = lane_value(h.first, k), pos = lane_value(h.pos, k);
+        const float sx = lane_value(h.x, k), sy = lane_value(h.y, k), sz = lane_value(h.z, k);
+        for (int off = kWave + lane; off - lane < len; off += kWave) {
+            if (off < len) {
+                const float4 q = a.pos0[first + off];
+                const float x = q.x - sx, y = q.y - sy, z = q.z - sz;
+                tile[pos + off] = make_float4(x, y, z, ID_IN_W ? q.w : x * x + y * y + z * z);
+            }
+        }
+    }
+}
+
 // Stage neighbourhood atoms [t0, t0 + tn) of the table in nb (an interior
 // cell's neighbourhood costs one global round trip).
 // B chunks in flight per batch (default: 9, or 5 with a vector).
@@ -273,6 +325,10 @@ __device__ __forceinline__ void stage_tile(const SimArgs& a, const Neighbourhood
                                            int t0, int tn, const float4* vec = nullptr,
                                            float4* vtile = nullptr) {
     const HoodSegs h = hood_from_lds(nb);
+    if (!WITH_VEC && t0 == 0 && tn == h.total()) {
+        stage_whole<ID_IN_W>(a, h, tile);
+        return;
+    }
     const int t1 = t0 + tn;
     StageCursor cur = stage_begin(h, t0);
     while (stage_more(h, cur, t1)) {
@@ -343,10 +399,13 @@ __device__ __forceinline__ void screen_span(const float4* tile, int first, int n
 // lanes that have spent their bits. The words rotate through four registers
 // (never indexed, which would put them in scratch memory); an exhausted word
 // is replaced by the next one without a branch.
-template <class Op>
+// BLOCKED: the words come from screen_mfma (bit 4b + i of a word is candidate
+// 16 b + i of the lane's span, whose first candidate is its slice's), so a bit
+// index k maps to byte offset 256 (k >> 2) + 16 (k & 3) and a word spans 2 KiB.
+template <class Op, bool BLOCKED = false>
 __device__ __forceinline__ void walk_bits(int ns, uint32_t m, uint32_t n1, uint32_t n2, uint32_t n3, Op& op) {
-    const uint32_t cstep = static_cast<uint32_t>(ns) * sizeof(float4);  // bytes between candidates
-    const uint32_t wstep = 32u * cstep;                                  // bytes between words
+    const uint32_t cstep = static_cast<uint32_t>(ns) * sizeof(float4);   // bytes between candidates
+    const uint32_t wstep = BLOCKED ? 8u * 16u * sizeof(float4) : 32u * cstep;  // bytes between words
     uint32_t wb = 0;                                                     // byte offset of the word's candidate 0
     uint32_t left = __builtin_popcount(m) + __builtin_popcount(n1) + __builtin_popcount(n2) +
                     __builtin_popcount(n3);
@@ -364,7 +423,8 @@ __device__ __forceinline__ void walk_bits(int ns, uint32_t m, uint32_t n1, uint3
         left -= live ? 1u : 0u;
         // a spent lane keeps rotating (wb grows past its span): it reads its
         // span's first candidate instead, which is always staged
-        op(live ? wb + k * cstep : 0u, live);
+        const uint32_t koff = BLOCKED ? ((k >> 2) << 8) | ((k & 3u) << 4) : k * cstep;
+        op(live ? wb + koff : 0u, live);
     } while (__any(left != 0u));
 }
 
@@ -377,6 +437,66 @@ __device__ __forceinline__ void clear_self(int self_t, int first, int ns, int gr
     if (g >= groups) return;
     const uint32_t bit = 0x80000000u >> (g & 31);
     const int w = g >> 5;
+    wd[0] &= (w == 0) ? ~bit : ~0u;
+    wd[1] &= (w == 1) ? ~bit : ~0u;
+    wd[2] &= (w == 2) ? ~bit : ~0u;
+    wd[3] &= (w == 3) ? ~bit : ~0u;
+}
+
+// ---- screen on the matrix cores ------------------------------------------
+// For a home cell of 11..16 atoms the screen runs as 16 x 16 x 4 FP32
+// matrix products: D = A B + C with A the 16 candidates of a block (rows:
+// x, y, z, |x|^2 in the home frame), B the 16 home atoms (columns:
+// -2 x_i, -2 y_i, -2 z_i, 1) and C = -(bound - |x_i|^2) per column, so that
+// D[j][i] = |x_j|^2 - 2 x_i.x_j - (bound - |x_i|^2) = r^2 - bound, negative
+// iff accepted. Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
+// receives D[4 (l / 16) + q][l % 16], q = 0..3: lane (home atom l % 16,
+// slice l / 16) gets the verdicts on candidates 16 b + 4 (l / 16) + q of
+// every block b, four sign bits per block, one v_alignbit each (about one
+// VALU instruction per candidate instead of five). Unused home columns carry
+// C = +inf and B = (0, 0, 0, 1): their D is +inf. Padding entries (w = +inf)
+// are never accepted either.
+constexpr int kMfmaMinHome = 11;  // below this the VALU screen's extra slices win
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+// Screen one span of nblk <= 32 blocks starting at candidate first (a
+// multiple of 16): word w, bit 31 - (4 (b - 8 w) + q) holds the verdict on
+// block b, row q of this lane. bval: this lane's B element; cneg: C.
+__device__ __forceinline__ void screen_mfma(const float4* tile, int first, int nblk, float bval, float cneg,
+                                            uint32_t (&wd)[kWords]) {
+    const int lane = threadIdx.x;
+    const float* base = reinterpret_cast<const float*>(tile + first) + (lane & 15) * 4 + (lane >> 4);
+    const mfma_f4 c = {cneg, cneg, cneg, cneg};
+#pragma unroll
+    for (int w = 0; w < kWords; ++w) {
+        uint32_t bits = 0;
+        const int nb = min(8, nblk - 8 * w);  // uniform
+        if (nb > 0) {
+            for (int b0 = 0; b0 < nb; b0 += 4) {
+                float av[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) av[u] = base[(8 * w + b0 + u) * 64];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const mfma_f4 d = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bval, c, 0, 0, 0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) bits = __builtin_amdgcn_alignbit(bits, __float_as_uint(d[q]), 31);
+                }
+            }
+            const int done = (nb + 3) / 4 * 4;  // blocks shifted in (the last group may run past nb)
+            if (done < 8) bits <<= (32 - 4 * done);
+        }
+        wd[w] = bits;
+    }
+}
+
+// Clear the home atom's own bit (span index self_t = tile index - first) in
+// the blocked layout, if it lies in this lane's slice s.
+__device__ __forceinline__ void clear_self_blocked(int self_t, int s, int nblk, uint32_t (&wd)[kWords]) {
+    if (self_t < 0 || self_t >= 16 * nblk || ((self_t & 15) >> 2) != s) return;
+    const int b = self_t >> 4;
+    const uint32_t bit = 0x80000000u >> (4 * (b & 7) + (self_t & 3));
+    const int w = b >> 3;
     wd[0] &= (w == 0) ? ~bit : ~0u;
     wd[1] &= (w == 1) ? ~bit : ~0u;
     wd[2] &= (w == 2) ? ~bit : ~0u;

@@ -80,18 +80,29 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
     bool bad = false;
     for (int h0 = 0; h0 < n_home; h0 += kWave) {
         const int nh = min(kWave, n_home - h0);
-        const int ns = min(kMaxSlices, kWave / nh);
-        const int h = lane % nh, s = lane / nh;
-        const bool act = s < ns;
+        // 11..16 home atoms: matrix-core screen, lane = (atom lane % 16, slice
+        // lane / 16); otherwise the VALU screen with ns interleaved slices
+        const bool mf = nh >= kMfmaMinHome && nh <= 16;  // uniform
+        const int ns = mf ? 4 : min(kMaxSlices, kWave / nh);
+        const int hstride = mf ? 16 : nh;  // lanes of one home atom: h, h + hstride, ...
+        const int h = lane % hstride, s = lane / hstride;
+        const bool act = mf ? h < nh : s < ns;
+        // the lane that finishes home atom h; in the matrix-core layout lanes
+        // nh..15 have s == 0 but no atom
+        const bool lead = act && s == 0;
         float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
         if (act) pi = a.pos0[home_first + h0 + h];
         float4 vel = make_float4(0.f, 0.f, 0.f, 0.f);  // fetched now, used by the epilogue
-        if ((KICK || ENERGY) && s == 0) vel = a.vel0[home_first + h0 + h];
+        if ((KICK || ENERGY) && lead) vel = a.vel0[home_first + h0 + h];
         const float xi = pi.x - ox, yi = pi.y - oy, zi = pi.z - oz;
         const float ai = fmaf(zi, zi, fmaf(yi, yi, xi * xi));
         // idle lanes get a bound no candidate can meet (q.w - thr_i = +inf)
         const float thr_i = act ? a.screen2 - ai : -__builtin_huge_valf();
         const float mx = -2.0f * xi, my = -2.0f * yi, mz = -2.0f * zi;
+        // matrix-core operands: this lane's element of B (component s of
+        // (-2 x_i, -2 y_i, -2 z_i, 1)) and of C (-bound + |x_i|^2; +inf idle)
+        const float bval = s == 3 ? 1.0f : (act ? (s == 0 ? mx : (s == 1 ? my : mz)) : 0.0f);
+        const float cneg = -thr_i;
         float fx = 0.f, fy = 0.f, fz = 0.f, u_loc = 0.f, w_loc = 0.f;
         for (int t0 = 0; t0 < total; t0 += a.tile_cap) {
             const int tn = min(a.tile_cap, total - t0);
@@ -99,8 +110,26 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
             stage_tile<false>(a, nb, tile, t0, tn);
             for (int t = lane; t < kTilePad; t += kWave) tile[tn + t] = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
             __syncthreads();
-            const int groups_all = (tn + ns - 1) / ns;  // candidates of the largest slice
             const int self_t = nb.home_pos + h0 + h - t0;  // the home atom's own tile index (may be outside)
+            if (mf) {
+                const int nblk_all = (tn + 15) / 16;
+                for (int b0 = 0; b0 < nblk_all; b0 += 8 * kWords) {
+                    const int nblk = min(8 * kWords, nblk_all - b0);
+                    uint32_t wd[kWords];
+                    screen_mfma(tile, 16 * b0, nblk, bval, cneg, wd);
+                    if (act) clear_self_blocked(self_t - 16 * b0, s, nblk, wd);
+                    ForceOp<ENERGY> op{a, reinterpret_cast<const char*>(tile + 16 * b0 + 4 * s), xi, yi, zi, fx, fy,
+                                       fz, u_loc, w_loc};
+                    walk_bits<ForceOp<ENERGY>, true>(ns, wd[0], wd[1], wd[2], wd[3], op);
+                    fx = op.fx;
+                    fy = op.fy;
+                    fz = op.fz;
+                    u_loc = op.u_loc;
+                    w_loc = op.w_loc;
+                }
+                continue;
+            }
+            const int groups_all = (tn + ns - 1) / ns;  // candidates of the largest slice
             for (int g0 = 0; g0 < groups_all; g0 += kGroups) {
                 const int groups = min(kGroups, groups_all - g0);
                 const int first = g0 * ns + (act ? s : 0);
@@ -138,10 +167,10 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         const int k = home_first + h0 + h;
         int c_next = -1;  // DRIFT: the home atom's next cell, -1 on lanes without one
         float4 p_next = pi, v_next = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (s == 0) {
+        if (lead) {
             float gx = 0.f, gy = 0.f, gz = 0.f, gu = 0.f, gw = 0.f;
             for (int q = 0; q < ns; ++q) {
-                const int l = h + q * nh;
+                const int l = h + q * hstride;
                 gx += red[0 * kWave + l];
                 gy += red[1 * kWave + l];
                 gz += red[2 * kWave + l];
@@ -292,7 +321,7 @@ __global__ void __launch_bounds__(kWave) k_neighbors(SimArgs a, int* counts, int
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&a.hdr[HDR_ERROR], DEV_ORDER);
         return;
     }
-    __shared__ float4 tile[kTile];
+    __shared__ float4 tile[kTile + kWave];  // a one-pass staging writes up to 63 entries past the atoms
     __shared__ Neighbourhood nb;
     const int lane = threadIdx.x;
     const int c = blockIdx.x;
