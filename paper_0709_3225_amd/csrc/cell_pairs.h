@@ -40,12 +40,15 @@ struct HoodLoads {
     bool rows = false;
 };
 
-// Origin of cell c (local index) in the box.
+// Origin of cell c (local index) in the box. The frame offsets o +- L are
+// formed from this rounded product; contraction is off wherever they are
+// computed, since fma(i, s, -L) is not the exact o - L the frame relies on.
 __device__ __forceinline__ void cell_origin(const SimArgs& a, int c, float& ox, float& oy, float& oz) {
+#pragma clang fp contract(off)
     const int nc = a.nc;
-    ox = (c % nc) * a.s;
-    oy = ((c / nc) % nc) * a.s;
-    oz = (c / (nc * nc)) * a.s;
+    ox = static_cast<float>(c % nc) * a.s;
+    oy = static_cast<float>((c / nc) % nc) * a.s;
+    oz = static_cast<float>(c / (nc * nc)) * a.s;
 }
 
 // Uniform facts are spread over lanes (meta: lane 0 total, 1 home_pos,
@@ -70,6 +73,7 @@ struct HoodSegs {
 // Issue the CSR loads of home cell c's 27 neighbours (lanes 0..26); nothing
 // waits for them here.
 __device__ __forceinline__ void hood_issue(const SimArgs& a, int c, HoodLoads& h) {
+#pragma clang fp contract(off)
     const int lane = threadIdx.x;
     const int nc = a.nc;
     const int ix = c % nc, iy = (c / nc) % nc, iz = c / (nc * nc);
@@ -312,6 +316,105 @@ __device__ __forceinline__ void stage_whole(const SimArgs& a, const HoodSegs& h,
                 const float4 q = a.pos0[first + off];
                 const float x = q.x - sx, y = q.y - sy, z = q.z - sz;
                 tile[pos + off] = make_float4(x, y, z, ID_IN_W ? q.w : x * x + y * y + z * z);
+            }
+        }
+    }
+}
+
+// Neighbourhood of a home cell away from the x faces (1 <= ix <= nc - 2), held
+// in scalar registers: its nine x-rows (dy, dz) of three cells each are
+// contiguous in the sorted arrays and need no image shift in x, so the row
+// bounds come from nine uniform loads of four CSR offsets each and the
+// staging below needs no per-segment table lookups.
+struct RowHood {
+    int first[9];  // sorted slot of each row's first atom
+    int pos[10];   // neighbourhood index of each row's first atom; pos[9] = total
+    int home_first, n_home, home_pos;
+    float ox, oy, oz;  // home-cell origin
+    float fy[3], fz[3];  // frame offsets o - sh of the rows with dy, dz = -1, 0, 1
+};
+
+// Fill r for home cell c (local index, uniform); false for a cell on an x
+// face. Lane k < 9 loads the CSR offsets of row k's cells ix - 1 .. ix + 2
+// (one 16-byte load, one round trip for the table); the values then move to
+// scalar registers.
+typedef int Int4u __attribute__((ext_vector_type(4), aligned(4)));
+
+__device__ __forceinline__ bool row_hood(const SimArgs& a, int c, RowHood& r) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x;
+    const int nc = a.nc;
+    const int ix = __builtin_amdgcn_readfirstlane(c % nc);
+    const int iy = __builtin_amdgcn_readfirstlane((c / nc) % nc);
+    const int iz = __builtin_amdgcn_readfirstlane(c / (nc * nc));
+    if (ix < 1 || ix > nc - 2) return false;
+    r.ox = static_cast<float>(ix) * a.s;
+    r.oy = static_cast<float>(iy) * a.s;
+    r.oz = static_cast<float>(iz) * a.s;
+    r.fy[0] = iy == 0 ? r.oy + a.box : r.oy;
+    r.fy[1] = r.oy;
+    r.fy[2] = iy == nc - 1 ? r.oy - a.box : r.oy;
+    r.fz[0] = iz == 0 ? r.oz + a.box : r.oz;
+    r.fz[1] = r.oz;
+    r.fz[2] = iz == nc - 1 ? r.oz - a.box : r.oz;
+    Int4u row = {0, 0, 0, 0};
+    if (lane < 9) {
+        int jy = iy + lane % 3 - 1, jz = iz + lane / 3 - 1;
+        jy = jy < 0 ? jy + nc : (jy >= nc ? jy - nc : jy);
+        jz = jz < 0 ? jz + nc : (jz >= nc ? jz - nc : jz);
+        row = *reinterpret_cast<const Int4u*>(a.start + a.cbase + (ix - 1) + nc * (jy + nc * jz));
+    }
+    int s0[9], s3[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        s0[k] = __builtin_amdgcn_readlane(row.x, k);
+        s3[k] = __builtin_amdgcn_readlane(row.w, k);
+    }
+    const int s1 = __builtin_amdgcn_readlane(row.y, 4), s2 = __builtin_amdgcn_readlane(row.z, 4);
+    int p = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        r.first[k] = s0[k];
+        r.pos[k] = p;
+        if (k == 4) r.home_pos = p + (s1 - s0[k]);
+        p += s3[k] - s0[k];
+    }
+    r.home_first = s1;
+    r.n_home = s2 - s1;
+    r.pos[9] = p;
+    return true;
+}
+
+// Staging of a RowHood neighbourhood in one pass (total <= tile capacity), by
+// the same unmasked scheme as stage_whole (rows tile [0, total) in order).
+__device__ __forceinline__ void stage_rows(const SimArgs& a, const RowHood& r, float4* tile) {
+    const int lane = threadIdx.x;
+    const int last = a.natoms - 1;
+    const char* pbase = reinterpret_cast<const char*>(a.pos0);
+    float4 q[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const uint32_t off = static_cast<uint32_t>(min(r.first[k] + lane, last)) << 4;
+        q[k] = *reinterpret_cast<const float4*>(pbase + off);
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const float x = q[k].x - r.ox;
+        const float y = q[k].y - r.fy[k % 3];
+        const float z = q[k].z - r.fz[k / 3];
+        tile[r.pos[k] + lane] = make_float4(x, y, z, x * x + y * y + z * z);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int len = r.pos[k + 1] - r.pos[k];
+        if (len > kWave) {  // uniform; rare
+            for (int off = kWave + lane; off - lane < len; off += kWave) {
+                if (off < len) {
+                    const float4 v = a.pos0[r.first[k] + off];
+                    const float x = v.x - r.ox, y = v.y - r.fy[k % 3], z = v.z - r.fz[k / 3];
+                    tile[r.pos[k] + off] = make_float4(x, y, z, x * x + y * y + z * z);
+                }
             }
         }
     }

@@ -71,10 +71,28 @@ template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT>
 __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile, Neighbourhood& nb, float* red) {
     const int lane = threadIdx.x;
     float ox, oy, oz;
-    load_neighbourhood(a, c, nb, ox, oy, oz);
-    const int total = nb.total;
-    const int home_first = nb.home_first;
-    const int n_home = nb.n_home;
+    // a cell away from the x faces whose neighbourhood and home atoms fit one
+    // pass is staged here, from a table in scalar registers; others take the
+    // LDS table and stage in the pass loop below
+    RowHood rh;
+    const bool rows = row_hood(a, c, rh) && rh.pos[9] <= a.tile_cap && rh.n_home <= kWave;
+    int total, home_first, n_home, home_pos;
+    if (rows) {
+        ox = rh.ox;
+        oy = rh.oy;
+        oz = rh.oz;
+        total = rh.pos[9];
+        home_first = rh.home_first;
+        n_home = rh.n_home;
+        home_pos = rh.home_pos;
+        stage_rows(a, rh, tile);
+    } else {
+        load_neighbourhood(a, c, nb, ox, oy, oz);
+        total = nb.total;
+        home_first = nb.home_first;
+        n_home = nb.n_home;
+        home_pos = nb.home_pos;
+    }
 
     double u_acc = 0.0, w_acc = 0.0, k_acc = 0.0;
     bool bad = false;
@@ -106,11 +124,13 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         float fx = 0.f, fy = 0.f, fz = 0.f, u_loc = 0.f, w_loc = 0.f;
         for (int t0 = 0; t0 < total; t0 += a.tile_cap) {
             const int tn = min(a.tile_cap, total - t0);
-            __syncthreads();
-            stage_tile<false>(a, nb, tile, t0, tn);
+            if (!rows) {
+                __syncthreads();
+                stage_tile<false>(a, nb, tile, t0, tn);
+            }
             for (int t = lane; t < kTilePad; t += kWave) tile[tn + t] = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
             __syncthreads();
-            const int self_t = nb.home_pos + h0 + h - t0;  // the home atom's own tile index (may be outside)
+            const int self_t = home_pos + h0 + h - t0;  // the home atom's own tile index (may be outside)
             if (mf) {
                 const int nblk_all = (tn + 15) / 16;
                 for (int b0 = 0; b0 < nblk_all; b0 += 8 * kWords) {
