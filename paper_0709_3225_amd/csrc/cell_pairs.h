@@ -526,7 +526,8 @@ __device__ __forceinline__ void walk_bits(int ns, uint32_t m, uint32_t n1, uint3
         left -= live ? 1u : 0u;
         // a spent lane keeps rotating (wb grows past its span): it reads its
         // span's first candidate instead, which is always staged
-        const uint32_t koff = BLOCKED ? ((k >> 2) << 8) | ((k & 3u) << 4) : k * cstep;
+        // blocked: 256 (k >> 2) + 16 (k & 3) = 16 k + 192 (k >> 2)
+        const uint32_t koff = BLOCKED ? (k << 4) + 192u * (k >> 2) : k * cstep;
         op(live ? wb + koff : 0u, live);
     } while (__any(left != 0u));
 }

@@ -284,8 +284,18 @@ __global__ void __launch_bounds__(kOrderBlock) k_cell_order(SimArgs a, bool from
     const int n = c < nct ? a.counts[c] : 0;
     int part = 0;
     if (a.direct) {
+        // all loads in flight at once (a loop bounded by blockIdx.x waited for
+        // each before the next)
+        static_assert(kDirectBlocks % kOrderBlock == 0, "direct block sums take whole rounds");
         const int* bc = a.bcounts + a.par * a.nbstride;
-        for (int j = tid; j < static_cast<int>(blockIdx.x); j += kOrderBlock) part += bc[j];
+        int v[kDirectBlocks / kOrderBlock];
+#pragma unroll
+        for (int u = 0; u < kDirectBlocks / kOrderBlock; ++u) {
+            const int j = tid + u * kOrderBlock;
+            v[u] = j < static_cast<int>(blockIdx.x) ? bc[j] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kDirectBlocks / kOrderBlock; ++u) part += v[u];
     }
     const int bs = a.direct ? 0 : a.bstart[blockIdx.x];
     const int novf = min(a.hdr[HDR_OVF + a.par], a.natoms);

@@ -31,16 +31,16 @@ __device__ __forceinline__ void pair_force(const SimArgs& a, const float4 q, flo
     const bool ok = live && (r2 < a.rc2);
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float ir2 = rinv * rinv;
-    const float s2 = a.sig2 * ir2;
-    const float s6 = s2 * s2 * s2;
-    float fr = fmaf(a.eps24 * ir2, s6 * fmaf(2.0f, s6, -1.0f), -a.fc * rinv);
+    const float ir6 = ir2 * ir2 * ir2;
+    // f(r) / r = 24 eps (2 sigma^12 r^-14 - sigma^6 r^-8) - f_LJ(r_c) / r
+    float fr = fmaf(ir2 * ir6, fmaf(a.c12, ir6, -a.c6), -a.fc * rinv);
     fr = ok ? fr : 0.0f;
     fx = fmaf(fr, dx, fx);
     fy = fmaf(fr, dy, fy);
     fz = fmaf(fr, dz, fz);
     if (ENERGY) {
         const float r = r2 * rinv;
-        const float u = a.eps4 * s6 * (s6 - 1.0f) - a.uc + (r - a.rc) * a.fc;
+        const float u = ir6 * fmaf(a.e12, ir6, -a.e6) - a.uc + (r - a.rc) * a.fc;
         u_loc += ok ? u : 0.0f;
         w_loc += fr * r2;
     }

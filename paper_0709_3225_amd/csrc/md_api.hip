@@ -195,6 +195,11 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     a.sig2 = static_cast<float>(sig * sig);
     a.eps24 = static_cast<float>(24.0 * eps);
     a.eps4 = static_cast<float>(4.0 * eps);
+    const double sig6 = std::pow(sig, 6.0);
+    a.c12 = static_cast<float>(48.0 * eps * sig6 * sig6);
+    a.c6 = static_cast<float>(24.0 * eps * sig6);
+    a.e12 = static_cast<float>(4.0 * eps * sig6 * sig6);
+    a.e6 = static_cast<float>(4.0 * eps * sig6);
     a.fc = p->shift_mode == 0 ? static_cast<float>(flj_rc) : 0.f;
     a.uc = static_cast<float>(ulj_rc);
     a.screen2 = screen_bound(rc, L.s);

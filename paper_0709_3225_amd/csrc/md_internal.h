@@ -69,6 +69,8 @@ struct SimArgs {
     float sig2;      // sigma^2
     float eps24;     // 24 epsilon
     float eps4;      // 4 epsilon
+    float c12, c6;   // 48 eps sigma^12, 24 eps sigma^6: f_LJ(r) / r = r^-8 (c12 r^-6 - c6)
+    float e12, e6;   // 4 eps sigma^12, 4 eps sigma^6: u_LJ(r) = r^-6 (e12 r^-6 - e6)
     float fc;        // f_LJ(r_c) for the force shift, 0 for energy shift
     float uc;        // u_LJ(r_c)
     float screen2;   // conservative bound on r^2 for the dot-product screen
