@@ -42,6 +42,7 @@ def parse():
                     help="also run one plain device-to-device copy of this size (HBM counter calibration)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint throughput leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-replica throughput leg")
+    ap.add_argument("--no-widened", action="store_true", help="skip the density-axis and WCA legs")
     return ap.parse_args()
 
 
@@ -133,6 +134,75 @@ def adjoint_leg(torch):
         "value": adj, "unit": "atom-steps/s (forward + backward)", "plain_value": plain,
         "ratio_vs_plain": adj / plain, "loss": loss, "dL_deps": ge, "dL_dsigma": gs,
     }
+
+
+def _timed_steps(s, nsteps, torch):
+    """Seconds for nsteps of md_step: the larger of HIP-event and wall time."""
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.step(nsteps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return max(time.perf_counter() - t0, e0.elapsed_time(e1) / 1e3)
+
+
+def _widened_point(torch, w, cell_min, nsteps, warm):
+    import ljsynth
+    from paper_0709_3225_amd import LJSystem
+
+    pos4, vel4, box = ljsynth.make_state(w)
+    s = LJSystem(w.n, box, rc_over_sigma=w.rc_over_sigma, shift_mode=w.shift_mode, dt=w.dt, cell_min=cell_min)
+    s.load(torch.from_numpy(pos4).cuda(), torch.from_numpy(vel4).cuda())
+    s.step(warm)
+    t = _timed_steps(s, nsteps, torch)
+    s.check()
+    return {"cells_per_dim": s.cells_per_dim, "cell_side": round(s.cell_side, 4),
+            "atoms_per_cell": round(w.n / s.n_cells, 2), "value": w.n * nsteps / t,
+            "us_per_step": t * 1e6 / nsteps}
+
+
+def density_leg(torch, nsteps=100, warm=20):
+    """LJ (r_c = 2.5 sigma) at N = 256,000 along the density axis of the
+    paper's cell-list measurements (section 4): md_step atom-steps/s with the
+    paper's cells (side >= r_c) and with cells sized for about 14 atoms."""
+    import ljsynth
+    from paper_0709_3225_amd import occupancy_cell_min
+
+    points = []
+    for rho in ljsynth.DENSITY_SWEEP:
+        w = ljsynth.sweep_workload(rho)
+        box = ljsynth.box_length(w.n, rho)
+        for cells, cm in (("paper", 0.0), ("occupancy", occupancy_cell_min(w.n, box, w.rc_over_sigma))):
+            pt = _widened_point(torch, w, cm, nsteps, warm)
+            pt.update({"rho": rho, "cells": cells})
+            points.append(pt)
+    return {"workload": "LJ N=256000 (40^3 FCC start), T*=0.722, rc=2.5 sigma force-shifted, dt=0.005, "
+                        f"{nsteps} steps after {warm}, rho in {list(ljsynth.DENSITY_SWEEP)}",
+            "unit": "atom-steps/s", "points": points}
+
+
+def wca_leg(torch, nsteps=100, warm=20):
+    """WCA (LJ cut at 2^(1/6) sigma, shifted by eps) at N = 256,000,
+    rho = 0.8442, T* = 0.722: md_step atom-steps/s with the paper's cells
+    (side >= r_c) and with larger cells."""
+    import ljsynth
+    from paper_0709_3225_amd import occupancy_cell_min
+
+    w = ljsynth.wca_workload()
+    box = ljsynth.box_length(w.n, w.density)
+    points = []
+    for cells, cm in (("paper", 0.0), ("1.7", 1.7), ("2.1", 2.1),
+                      ("occupancy", occupancy_cell_min(w.n, box, w.rc_over_sigma))):
+        pt = _widened_point(torch, w, cm, nsteps, warm)
+        pt["cells"] = cells
+        points.append(pt)
+    best = max(points, key=lambda p: p["value"])
+    return {"workload": f"{w.name}: WCA N={w.n} (40^3 FCC start), rho={w.density}, T*={w.temperature}, "
+                        f"rc=2^(1/6) sigma energy-shifted, dt={w.dt}, {nsteps} steps after {warm}",
+            "unit": "atom-steps/s", "points": points, "best": best["cells"], "value": best["value"]}
 
 
 def algorithmic_force_flops(sys_, torch):
@@ -331,6 +401,9 @@ def main():
     if not args.no_batched:
         out["batched"] = batched_leg(torch)
         out["batched"]["ratio_vs_plain_headline"] = out["batched"]["value"] / value
+    if not args.no_widened:
+        out["density_axis"] = density_leg(torch)
+        out["wca"] = wca_leg(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s.state()[0].cpu().numpy(), box, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -45,6 +45,7 @@ class Workload:
     sigma: float = 1.0
     mass: float = 1.0
     rc_over_sigma: float = 2.5
+    shift_mode: int = 0  # 0: force shifted to zero at r_c; 1: energy shifted (WCA)
 
     @property
     def n(self) -> int:
@@ -60,6 +61,24 @@ WORKLOADS = {
     "lj32k_adjoint": Workload("lj32k_adjoint", 20, 0.8442, 1.0, 200, 5),
     "lj256_check": Workload("lj256_check", 4, 0.8442, 1.0, 200, 5),
 }
+
+
+# Widened workloads. The density axis of the paper's cell-list measurements
+# (section 4, rho from 0.1 to 1.0) at the headline size, and WCA: LJ cut at
+# its minimum 2^(1/6) sigma and shifted by eps (a short-range pair potential
+# in place of LJ, as the paper's closing section allows). The WCA cutoff is
+# the FP32 value both the GPU path and the oracle use.
+DENSITY_SWEEP = (0.1, 0.2, 0.4, 0.6, 0.8442, 1.0)
+WCA_RC = float(np.float32(2.0 ** (1.0 / 6.0)))
+
+
+def sweep_workload(density: float, n_fcc: int = 40, seed: int = 40) -> Workload:
+    return Workload(f"lj{4 * n_fcc ** 3 // 1000}k_rho{density}", n_fcc, density, 0.722, 100, seed)
+
+
+def wca_workload(n_fcc: int = 40, density: float = 0.8442, seed: int = 41) -> Workload:
+    return Workload(f"wca{4 * n_fcc ** 3 // 1000}k_rho{density}", n_fcc, density, 0.722, 100, seed,
+                    rc_over_sigma=WCA_RC, shift_mode=1)
 
 
 def box_length(n: int, density: float) -> float:

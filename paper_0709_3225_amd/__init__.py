@@ -21,7 +21,7 @@ from ._lib import (  # noqa: F401
     md_step,
     md_workspace_bytes,
 )
-from .system import LJSystem  # noqa: F401
+from .system import LJSystem, occupancy_cell_min  # noqa: F401
 from .adjoint import LJTrajectory, trajectory_gradients  # noqa: F401
 from .batch import BatchedLJ  # noqa: F401
 

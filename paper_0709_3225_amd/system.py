@@ -10,6 +10,15 @@ import torch
 from . import _lib as L
 
 
+def occupancy_cell_min(n: int, box: float, rc: float, target: float = 14.0) -> float:
+    """Cell side holding about ``target`` atoms on average at this density,
+    never below r_c (section 3 asks only for cells of side >= r_c). With cells
+    of side r_c at low density or with a short cutoff, a cell holds one or two
+    atoms and a wavefront per home cell leaves most of its lanes idle; the
+    value goes to ``cell_min``."""
+    return max(float(rc), (float(target) * float(box) ** 3 / float(n)) ** (1.0 / 3.0))
+
+
 class LJSystem:
     """Cubic periodic LJ system of n particles in a box of side ``box``."""
 

@@ -1,0 +1,155 @@
+"""GPU parity on the widened workloads, through the C-ABI, against the FP64
+oracle: the WCA potential (LJ cut at 2^(1/6) sigma, energy shifted), LJ
+across the density axis of the paper's cell-list measurements (section 4),
+and cells larger than r_c (``cell_min``, as the occupancy-sized grids of the
+bench use; section 3 asks only for cells of side >= r_c). Same tolerances as
+the core parity tests: forces within 1e-5 relative L2, energy and virial
+within 1e-6 relative.
+"""
+import numpy as np
+import pytest
+
+import ljsynth
+
+pytestmark = pytest.mark.gpu
+
+FORCE_TOL = 1e-5
+ENERGY_TOL = 1e-6
+
+
+def _torch():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _dev(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _lattice(n_fcc, rho, amp, seed):
+    n = 4 * n_fcc ** 3
+    box = ljsynth.box_length(n, rho)
+    pos = ljsynth.jitter(ljsynth.fcc_positions(n_fcc, box), amp, seed)
+    pos4 = np.zeros((n, 4), np.float32)
+    pos4[:, :3] = ljsynth.wrap_fp32(pos.astype(np.float32), box)
+    return pos4, box
+
+
+def _cell_min(kind, n, box, rc):
+    from paper_0709_3225_amd import occupancy_cell_min
+
+    return {"paper": 0.0, "occupancy": occupancy_cell_min(n, box, rc)}.get(kind, kind)
+
+
+def _gpu(pos4, box, rc_over_sigma, shift_mode, cell_min, vel4=None):
+    from paper_0709_3225_amd import LJSystem
+
+    s = LJSystem(len(pos4), box, rc_over_sigma=rc_over_sigma, shift_mode=shift_mode, cell_min=cell_min)
+    s.load(_dev(pos4), None if vel4 is None else _dev(vel4))
+    f = s.forces().cpu().numpy()[:, :3].astype(np.float64)
+    e = s.energy().cpu().numpy()
+    assert s.check() == 0
+    return s, f, e
+
+
+def _check(orc, pos4, box, rc, mode, f, e):
+    """Energy and virial within 1e-6 relative, with a floor of 1e-8 eps per
+    atom: at low density the pairs sit near r_c, where each shifted pair term
+    (about 1e-3 eps) is the difference of terms near 2e-2 eps whose FP32
+    rounding (about 1e-9 eps each) no longer shrinks with the total."""
+    fo, U, W = orc.forces(orc.params(box, rc=rc, shift_mode=mode), pos4)
+    floor = 0.01 * len(pos4)
+    assert rel_l2(f, fo) <= FORCE_TOL
+    assert abs(e[0] - U) <= ENERGY_TOL * max(abs(U), floor)
+    assert abs(e[2] - W) <= ENERGY_TOL * max(abs(W), floor)
+
+
+@pytest.mark.parametrize("cells", ["paper", 1.7, "occupancy"])
+@pytest.mark.parametrize("rho", [0.8442, 1.2])
+def test_wca_forces_energy(orc, rho, cells):
+    pos4, box = _lattice(10, rho, 0.06, 31)
+    cm = _cell_min(cells, len(pos4), box, ljsynth.WCA_RC)
+    _say(f"wca rho={rho} cells={cells} cell_min={cm:.3f} n={len(pos4)}")
+    s, f, e = _gpu(pos4, box, ljsynth.WCA_RC, 1, cm)
+    if cells == "paper":
+        assert s.cell_side >= ljsynth.WCA_RC and s.cell_side < 1.5
+    _check(orc, pos4, box, ljsynth.WCA_RC, 1, f, e)
+
+
+@pytest.mark.parametrize("cells", ["paper", "occupancy"])
+@pytest.mark.parametrize("rho", [0.1, 0.4, 1.0])
+def test_density_axis_forces_energy(orc, rho, cells):
+    pos4, box = _lattice(8, rho, 0.05, 32)
+    cm = _cell_min(cells, len(pos4), box, 2.5)
+    _say(f"lj rho={rho} cells={cells} cell_min={cm:.3f} n={len(pos4)}")
+    s, f, e = _gpu(pos4, box, 2.5, 0, cm)
+    _check(orc, pos4, box, 2.5, 0, f, e)
+
+
+@pytest.mark.parametrize("cell_min", [3.1, 4.4])
+def test_larger_cells_same_result(orc, cell_min):
+    """cell_min above r_c: fewer, larger cells; the forces are the same sums
+    (up to FP32 rounding of another summation order)."""
+    w = ljsynth.WORKLOADS["lj4k"]
+    pos4, _, box = ljsynth.make_state(w, jitter_amp=0.05, shuffle=True)
+    _say(f"lj4k cell_min={cell_min}")
+    s, f, e = _gpu(pos4, box, 2.5, 0, cell_min)
+    assert s.cell_side >= cell_min
+    _check(orc, pos4, box, 2.5, 0, f, e)
+
+
+# the configurations the bench's widened legs time, at full size (N = 256,000),
+# on 256 sampled rows
+FULL = {
+    "rho0.1_paper": (lambda: ljsynth.sweep_workload(0.1), "paper"),
+    "rho0.1_occupancy": (lambda: ljsynth.sweep_workload(0.1), "occupancy"),
+    "rho1.0_paper": (lambda: ljsynth.sweep_workload(1.0), "paper"),
+    "wca_paper": (lambda: ljsynth.wca_workload(), "paper"),
+    "wca_occupancy": (lambda: ljsynth.wca_workload(), "occupancy"),
+}
+
+
+@pytest.mark.parametrize("config", list(FULL))
+def test_widened_full_size_sampled_rows(orc, config):
+    make, cells = FULL[config]
+    w = make()
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05)
+    rc = w.rc_over_sigma
+    cm = _cell_min(cells, w.n, box, rc)
+    _say(f"full size {config} n={w.n} cell_min={cm:.3f}")
+    s, f, e = _gpu(pos4, box, rc, w.shift_mode, cm, vel4)
+    sel = np.random.default_rng(19).choice(w.n, size=256, replace=False)
+    fo, _, _ = orc.forces_rows(orc.params(box, rc=rc, shift_mode=w.shift_mode), pos4, sel)
+    assert rel_l2(f[sel], fo) <= FORCE_TOL
+
+
+def test_wca_short_run_matches_oracle(orc):
+    """50 velocity-Verlet steps of a WCA fluid: the GPU trajectory's total
+    energy stays within 1e-5 of the oracle's over the first ten steps and is
+    conserved to 5e-4 over the run."""
+    w = ljsynth.wca_workload(n_fcc=6)
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05)
+    _say(f"wca nve n={w.n} 50 steps")
+    from paper_0709_3225_amd import LJSystem
+
+    s = LJSystem(w.n, box, rc_over_sigma=w.rc_over_sigma, shift_mode=1, dt=w.dt)
+    s.load(_dev(pos4), _dev(vel4))
+    e0 = s.energy().cpu().numpy()
+    th = s.step(50, thermo_every=1).cpu().numpy()
+    assert s.check() == 0
+    etot = np.concatenate([[e0[0] + e0[1]], th[:, 0] + th[:, 1]])
+    assert np.abs(etot - etot[0]).max() / abs(etot[0]) < 5e-4
+    _, _, tho = orc.run(orc.params(box, rc=w.rc_over_sigma, dt=w.dt, shift_mode=1), pos4, vel4, 50)
+    eo = tho[:, 0] + tho[:, 1]
+    assert np.abs(etot[:11] - eo[:11]).max() / abs(eo[0]) < 1e-5  # both start with the initial state
