@@ -42,7 +42,7 @@ def parse():
                     help="also run one plain device-to-device copy of this size (HBM counter calibration)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint throughput leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-replica throughput leg")
-    ap.add_argument("--no-widened", action="store_true", help="skip the density-axis and WCA legs")
+    ap.add_argument("--no-widened", action="store_true", help="skip the density-axis, WCA and skin legs")
     return ap.parse_args()
 
 
@@ -136,14 +136,18 @@ def adjoint_leg(torch):
     }
 
 
-def _timed_steps(s, nsteps, torch):
-    """Seconds for nsteps of md_step: the larger of HIP-event and wall time."""
+def _timed_steps(s, nsteps, torch, every=0):
+    """Seconds for nsteps of md_step (or md_step_every with rebuilds every
+    `every` steps): the larger of HIP-event and wall time."""
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    s.step(nsteps)
+    if every:
+        s.step_every(nsteps, every)
+    else:
+        s.step(nsteps)
     e1.record(stream)
     torch.cuda.synchronize()
     return max(time.perf_counter() - t0, e0.elapsed_time(e1) / 1e3)
@@ -203,6 +207,33 @@ def wca_leg(torch, nsteps=100, warm=20):
     return {"workload": f"{w.name}: WCA N={w.n} (40^3 FCC start), rho={w.density}, T*={w.temperature}, "
                         f"rc=2^(1/6) sigma energy-shifted, dt={w.dt}, {nsteps} steps after {warm}",
             "unit": "atom-steps/s", "points": points, "best": best["cells"], "value": best["value"]}
+
+
+def skin_leg(torch, nsteps=100, warm=20):
+    """The headline workload with the cell lists rebuilt only every few steps
+    (md_step_every; section 3.1): the skin is the grid's margin over r_c
+    (cell_min picks the grid). A point is valid when no atom left its cell by
+    half the skin (no MD_DEV_SKIN)."""
+    import ljsynth
+    from paper_0709_3225_amd import LJSystem
+
+    w = ljsynth.WORKLOADS["lj256k"]
+    pos4, vel4, box = ljsynth.make_state(w)
+    points = []
+    for cm, every in ((0.0, 1), (0.0, 2), (0.0, 3), (0.0, 4), (0.0, 6), (2.7, 4), (2.7, 8), (2.9, 10)):
+        s = LJSystem(w.n, box, dt=w.dt, cell_min=cm)
+        s.load(torch.from_numpy(pos4).cuda(), torch.from_numpy(vel4).cuda())
+        s.step(warm)
+        t = _timed_steps(s, nsteps, torch, every)
+        flags = s.check(raise_on_error=False)
+        points.append({"cells_per_dim": s.cells_per_dim, "skin": round(s.cell_side - w.rc_over_sigma, 4),
+                       "rebuild_every": every, "value": w.n * nsteps / t, "us_per_step": t * 1e6 / nsteps,
+                       "valid": flags == 0})
+    best = max((p for p in points if p["valid"]), key=lambda p: p["value"])
+    return {"workload": f"{w.name}: LJ N={w.n}, rho={w.density}, T*={w.temperature}, {nsteps} steps after {warm}, "
+                        "cell lists rebuilt every k steps",
+            "unit": "atom-steps/s", "points": points, "best": {k: best[k] for k in ("skin", "rebuild_every")},
+            "value": best["value"]}
 
 
 def algorithmic_force_flops(sys_, torch):
@@ -404,6 +435,7 @@ def main():
     if not args.no_widened:
         out["density_axis"] = density_leg(torch)
         out["wca"] = wca_leg(torch)
+        out["skin"] = skin_leg(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s.state()[0].cpu().numpy(), box, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -55,6 +55,9 @@ typedef enum md_status {
 #define MD_DEV_ORDER 2     /* md_forces before md_build_cells, or md_step
                               before md_forces: the call did nothing */
 #define MD_DEV_NB_OVERFLOW 4 /* md_neighbors: a row exceeded max_per_atom */
+#define MD_DEV_SKIN 8      /* md_step_every: between rebuilds an atom left its
+                              cell by more than half the skin; that run may
+                              have missed pairs near r_c */
 
 /* Physical and numerical parameters, reduced LJ units. */
 typedef struct md_params {
@@ -127,6 +130,24 @@ md_status md_forces(const md_params* p, void* ws, size_t ws_bytes, float* force4
  */
 md_status md_step(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps,
                   int32_t thermo_every, double* thermo_dev, hipStream_t stream);
+
+/*
+ * md_step with the cell lists rebuilt only every rebuild_every steps
+ * (section 3.1: cells larger than r_c by a skin, updated every few steps;
+ * the Verlet displacement rule of section 3 bounds how far an atom may move
+ * before the update). The skin is the grid's own margin, cell side - r_c:
+ * choose it with md_params.cell_min = r_c + skin. Cells are rebuilt before
+ * the forces of steps 1, 1 + e, 1 + 2e, ... (e = rebuild_every) and of the
+ * last step; in between, positions are not wrapped and each atom keeps its
+ * cell. If an atom leaves its cell's box by more than skin / 2 the device
+ * sets MD_DEV_SKIN (the run may then have missed pairs; use a larger skin or
+ * a smaller rebuild_every). rebuild_every = 1 is md_step exactly (bitwise).
+ * On return the state is rebuilt and wrapped as after md_step; thermo_every
+ * and thermo_dev as for md_step. rebuild_every < 1 gives MD_ERR_ARG.
+ */
+md_status md_step_every(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps,
+                        int32_t rebuild_every, int32_t thermo_every, double* thermo_dev,
+                        hipStream_t stream);
 
 /*
  * Potential energy U, kinetic energy K = m/2 sum v^2 and virial

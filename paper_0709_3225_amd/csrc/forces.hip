@@ -67,7 +67,12 @@ struct ForceOp {
 // would (half kick, drift, wrap, cell, binning into the next rebuild's
 // buckets) instead of writing vel0; force and vel0 are then left stale, since
 // the rebuild replaces the sorted state.
-template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT>
+// SKIN (with DRIFT): a step between rebuilds. The drift writes the unwrapped
+// next position and velocity to pos2/vel2 (same sorted slot) instead of
+// binning, and raises DEV_SKIN if the atom has left its cell's box by more
+// than skin_half (cells of side r_c + skin then still hold every partner
+// within r_c in the 27-cell neighbourhood, section 3.1).
+template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT, bool SKIN = false>
 __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile, Neighbourhood& nb, float* red) {
     const int lane = threadIdx.x;
     float ox, oy, oz;
@@ -95,7 +100,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
     }
 
     double u_acc = 0.0, w_acc = 0.0, k_acc = 0.0;
-    bool bad = false;
+    bool bad = false, skin_out = false;
     for (int h0 = 0; h0 < n_home; h0 += kWave) {
         const int nh = min(kWave, n_home - h0);
         // 11..16 home atoms: matrix-core screen, lane = (atom lane % 16, slice
@@ -218,13 +223,24 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                 }
                 if (DRIFT) {
                     v_next = v;
-                    c_next = half_kick_drift(a, p_next, v_next, gx, gy, gz);
+                    if (SKIN) {
+                        half_kick_drift_unwrapped(a, p_next, v_next, gx, gy, gz);
+                        a.pos2[k] = p_next;
+                        a.vel2[k] = v_next;
+                        const float ex = fmaxf(fmaxf(ox - p_next.x, p_next.x - (ox + a.s)), 0.f);
+                        const float ey = fmaxf(fmaxf(oy - p_next.y, p_next.y - (oy + a.s)), 0.f);
+                        const float ez = fmaxf(fmaxf(oz - p_next.z, p_next.z - (oz + a.s)), 0.f);
+                        if (ex * ex + ey * ey + ez * ez > a.skin_half * a.skin_half) skin_out = true;
+                    } else {
+                        c_next = half_kick_drift(a, p_next, v_next, gx, gy, gz);
+                    }
                 }
             }
         }
-        if (DRIFT) bin_atom(a, p_next, v_next, c_next);  // all lanes
+        if (DRIFT && !SKIN) bin_atom(a, p_next, v_next, c_next);  // all lanes
     }
     if (bad) atomicOr(&a.hdr[HDR_ERROR], DEV_NONFINITE);
+    if (SKIN && skin_out) atomicOr(&a.hdr[HDR_ERROR], DEV_SKIN);
     if (ENERGY) {
         u_acc = wave_sum(u_acc);
         w_acc = wave_sum(w_acc);
@@ -252,6 +268,17 @@ __global__ void __launch_bounds__(kWave) k_forces(SimArgs a, bool from_step) {
     force_cell<KICK, ENERGY, WRITE, DRIFT>(a, xcd_block_order(blockIdx.x, a.ncells), tile, nb,
                                            reinterpret_cast<float*>(tile));
     if (WRITE && blockIdx.x == 0 && threadIdx.x == 0) a.hdr[HDR_STATE] = STATE_FORCES;
+}
+
+// A step between rebuilds (md_step_every): forces, kick, and the next step's
+// half kick and drift into pos2/vel2.
+template <bool ENERGY>
+__global__ void __launch_bounds__(kWave) k_forces_skin(SimArgs a) {
+    if (a.hdr[HDR_ERROR] & DEV_ORDER) return;
+    extern __shared__ float4 tile[];
+    __shared__ Neighbourhood nb;
+    force_cell<true, ENERGY, false, true, true>(a, xcd_block_order(blockIdx.x, a.ncells), tile, nb,
+                                                reinterpret_cast<float*>(tile));
 }
 
 // Batched forces: one workgroup per cell of any replica (global cell index,
@@ -405,6 +432,14 @@ hipError_t launch_forces(const SimArgs& a_in, bool kick, bool energy, bool write
         return hipErrorInvalidValue;
     }
 #undef MD_FORCES
+    return hipGetLastError();
+}
+
+hipError_t launch_forces_skin(const SimArgs& a, bool energy, hipStream_t st) {
+    const dim3 g(a.ncells), b(kWave);
+    const size_t lds = sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
+    if (energy) hipLaunchKernelGGL(k_forces_skin<true>, g, b, lds, st, a);
+    else hipLaunchKernelGGL(k_forces_skin<false>, g, b, lds, st, a);
     return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "md.h"
@@ -123,6 +124,8 @@ md_status make_layout(const md_params* p, Layout& L) {
     L.pos1 = take(16 * n);
     L.vel1 = take(16 * n);
     L.force = take(16 * n);
+    L.pos2 = take(16 * n);
+    L.vel2 = take(16 * n);
     take_build_arrays(L, n, static_cast<size_t>(L.ncells), bucket_capacity(static_cast<double>(p->n) / L.ncells),
                       take);
     L.epart = take(sizeof(double) * 3 * static_cast<size_t>(L.nforce_blocks));
@@ -164,6 +167,8 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     a.pos1 = reinterpret_cast<float4*>(b + L.pos1);
     a.vel1 = reinterpret_cast<float4*>(b + L.vel1);
     a.force = reinterpret_cast<float4*>(b + L.force);
+    a.pos2 = L.pos2 ? reinterpret_cast<float4*>(b + L.pos2) : nullptr;
+    a.vel2 = L.vel2 ? reinterpret_cast<float4*>(b + L.vel2) : nullptr;
     a.counts = reinterpret_cast<int*>(b + L.counts);
     a.bstart = reinterpret_cast<int*>(b + L.bstart);
     a.bpos = reinterpret_cast<float4*>(b + L.bpos);
@@ -203,6 +208,9 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     a.fc = p->shift_mode == 0 ? static_cast<float>(flj_rc) : 0.f;
     a.uc = static_cast<float>(ulj_rc);
     a.screen2 = screen_bound(rc, L.s);
+    // half the margin of the cell side over r_c, less a relative 2^-20 for the
+    // FP32 comparison
+    a.skin_half = static_cast<float>(std::max(0.0, 0.5 * (static_cast<double>(L.s) - rc) * (1.0 - std::ldexp(1.0, -20))));
     a.tile_cap = tile_capacity(p->n, L.ncells);
     a.dt = p->dt;
     a.hdt_m = static_cast<float>(0.5 * p->dt / p->mass);
@@ -428,6 +436,54 @@ md_status md_step(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps,
                        "energy");
     }
     if (nsteps > 0) MD_TRY_HIP(launch_zero_blocks(a, (nsteps - 1) & 1, stream), "counter clear");
+    return MD_OK;
+}
+
+md_status md_step_every(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps, int32_t rebuild_every,
+                        int32_t thermo_every, double* thermo, hipStream_t stream) {
+    Layout L{};
+    md_status s = make_layout(p, L);
+    if (s != MD_OK) return s;
+    if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
+    if (nsteps < 0) return fail(MD_ERR_ARG, "nsteps must be >= 0");
+    if (rebuild_every < 1) return fail(MD_ERR_ARG, "rebuild_every must be >= 1");
+    if (thermo_every < 0) return fail(MD_ERR_ARG, "thermo_every must be >= 0");
+    if (thermo_every > 0 && !thermo) return fail(MD_ERR_ARG, "thermo_every > 0 needs a thermo buffer");
+    const SimArgs a = make_args(p, L, ws);
+    SimArgs alt = a;  // reads the alternate sorted buffers, drifts into the canonical ones
+    std::swap(alt.pos0, alt.pos2);
+    std::swap(alt.vel0, alt.vel2);
+    // Cells are rebuilt before the forces of steps 1, 1 + e, 1 + 2e, ... and of
+    // the last step (so the call ends on a rebuilt, wrapped state with forces
+    // in the canonical order, as md_step does). The step before a rebuild bins
+    // in its force epilogue exactly as md_step; the other steps drift into the
+    // alternate buffers (unwrapped) and the live pair flips. Build b bins with
+    // parity b mod 2, as consecutive steps do in md_step.
+    int b = 0;
+    bool live_alt = false;
+    for (int32_t k = 1; k <= nsteps; ++k) {
+        const bool energy = thermo && thermo_every > 0 && (k % thermo_every) == 0;
+        const bool last = k == nsteps;
+        const bool rebuild_now = k == 1 || last || (k - 1) % rebuild_every == 0;
+        const bool rebuild_next = !last && (k + 1 == nsteps || k % rebuild_every == 0);
+        if (k == 1) MD_TRY_HIP(launch_integrate(a, stream), "integrate");
+        if (rebuild_now) {
+            if (k > 1) ++b;
+            if ((s = rebuild(a, b & 1, true, stream)) != MD_OK) return s;
+            live_alt = false;
+        }
+        const SimArgs& cur = live_alt ? alt : a;
+        if (last || rebuild_next) {
+            MD_TRY_HIP(launch_forces(cur, true, energy, last, true, !last, (b + 1) & 1, stream), "forces");
+        } else {
+            MD_TRY_HIP(launch_forces_skin(cur, energy, stream), "forces");
+            live_alt = !live_alt;
+        }
+        if (energy)
+            MD_TRY_HIP(launch_energy_final(a, thermo + 3 * static_cast<size_t>(k / thermo_every - 1), stream),
+                       "energy");
+    }
+    if (nsteps > 0) MD_TRY_HIP(launch_zero_blocks(a, b & 1, stream), "counter clear");
     return MD_OK;
 }
 

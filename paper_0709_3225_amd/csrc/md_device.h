@@ -35,13 +35,12 @@ __device__ __forceinline__ bool finite3(float x, float y, float z) {
 }
 
 // First half of a velocity-Verlet step for one atom (section 2): v += dt/(2m) f,
-// r += dt v, wrap into the box. A non-finite position raises DEV_NONFINITE and
+// r += dt v (the unwrapped form stops here), wrap into the box. A non-finite position raises DEV_NONFINITE and
 // is parked at the origin. Returns the atom's new cell (global index). The
 // drift kernel and the fused force epilogue both use this, so the two paths
 // round identically.
-__device__ __forceinline__ int half_kick_drift(const SimArgs& a, float4& p, float4& v, float fx, float fy,
-                                               float fz) {
-    const float invL = 1.0f / a.box;
+__device__ __forceinline__ void half_kick_drift_unwrapped(const SimArgs& a, float4& p, float4& v, float fx,
+                                                          float fy, float fz) {
     v.x += a.hdt_m * fx;
     v.y += a.hdt_m * fy;
     v.z += a.hdt_m * fz;
@@ -52,6 +51,12 @@ __device__ __forceinline__ int half_kick_drift(const SimArgs& a, float4& p, floa
         atomicOr(&a.hdr[HDR_ERROR], DEV_NONFINITE);
         p.x = p.y = p.z = 0.f;
     }
+}
+
+__device__ __forceinline__ int half_kick_drift(const SimArgs& a, float4& p, float4& v, float fx, float fy,
+                                               float fz) {
+    const float invL = 1.0f / a.box;
+    half_kick_drift_unwrapped(a, p, v, fx, fy, fz);
     p.x = wrap_coord(p.x, a.box, invL);
     p.y = wrap_coord(p.y, a.box, invL);
     p.z = wrap_coord(p.z, a.box, invL);

@@ -27,7 +27,7 @@ constexpr int kBlockShift = 4;
 constexpr int kDirectBlocks = 2048;
 
 // Device error bits (same values as the public MD_DEV_* macros).
-enum : int { DEV_NONFINITE = 1, DEV_ORDER = 2, DEV_NB_OVERFLOW = 4 };
+enum : int { DEV_NONFINITE = 1, DEV_ORDER = 2, DEV_NB_OVERFLOW = 4, DEV_SKIN = 8 };
 
 // Everything a kernel needs, passed by value.
 struct SimArgs {
@@ -37,6 +37,12 @@ struct SimArgs {
     float4* pos1;    // overflow storage of the cell build (entry j of the list), and
     float4* vel1;    // scratch for the adjoint between builds
     float4* force;   // cell-sorted forces
+    // Steps between rebuilds (md_step_every): the drift of the force epilogue
+    // writes the next positions and velocities here, in the same sorted slots;
+    // the host swaps this pair with pos0/vel0 from step to step.
+    float4* pos2;
+    float4* vel2;
+    float skin_half;  // an atom may leave its cell's box by this much before a rebuild is due
     // Cell build: per-cell histogram, zero between builds; a binned atom's
     // position and velocity go to its cell's bucket of cap entries, or to the
     // overflow list (pos1, vel1 and the cell) past the capacity.
@@ -94,7 +100,7 @@ struct Layout {
     float s, inv_s;
     int nblocks, cap;
     int nbstride;
-    size_t hdr, pos0, vel0, pos1, vel1, force, counts, bstart, bcounts, bpos, bvel, ovf_cell, start, epart, total;
+    size_t hdr, pos0, vel0, pos1, vel1, force, pos2, vel2, counts, bstart, bcounts, bpos, bvel, ovf_cell, start, epart, total;
 };
 
 // Kernel launchers (each returns hipGetLastError() after its launch).
@@ -109,6 +115,8 @@ hipError_t launch_zero_blocks(const SimArgs& a, int par, hipStream_t st);
 hipError_t launch_integrate(const SimArgs& a, hipStream_t st);
 hipError_t launch_forces(const SimArgs& a, bool kick, bool energy, bool write_force, bool from_step, bool drift,
                          int par, hipStream_t st);
+// A step between rebuilds: forces, kick, next drift into pos2/vel2 (md_step_every).
+hipError_t launch_forces_skin(const SimArgs& a, bool energy, hipStream_t st);
 hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st);
 hipError_t launch_gather_user(const SimArgs& a, float4* pos_out, float4* vel_out, float4* force_out,
                               hipStream_t st);

@@ -153,3 +153,69 @@ def test_wca_short_run_matches_oracle(orc):
     _, _, tho = orc.run(orc.params(box, rc=w.rc_over_sigma, dt=w.dt, shift_mode=1), pos4, vel4, 50)
     eo = tho[:, 0] + tho[:, 1]
     assert np.abs(etot[:11] - eo[:11]).max() / abs(eo[0]) < 1e-5  # both start with the initial state
+
+
+# ---- cell lists rebuilt every few steps (md_step_every; skin = cell side - r_c)
+
+def _run_pair(w, cell_min, nsteps, every):
+    from paper_0709_3225_amd import LJSystem
+
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05)
+    out = []
+    for mode in ("step", "every"):
+        s = LJSystem(w.n, box, dt=w.dt, cell_min=cell_min)
+        s.load(_dev(pos4), _dev(vel4))
+        th = s.step(nsteps, thermo_every=1) if mode == "step" else s.step_every(nsteps, every, thermo_every=1)
+        flags = s.check(raise_on_error=False)
+        p, v = s.state()
+        out.append((s, th.cpu().numpy(), p.cpu().numpy(), v.cpu().numpy(), s.forces().cpu().numpy(), flags))
+    return pos4, vel4, box, out
+
+
+def test_step_every_one_is_md_step_bitwise():
+    w = ljsynth.WORKLOADS["lj4k"]
+    _say("md_step_every(e=1) vs md_step, lj4k, 20 steps")
+    _, _, _, ((_, ta, pa, va, fa, ga), (_, tb, pb, vb, fb, gb)) = _run_pair(w, 0.0, 20, 1)
+    assert ga == 0 and gb == 0
+    assert np.array_equal(ta, tb) and np.array_equal(pa, pb) and np.array_equal(va, vb)
+    assert np.array_equal(fa, fb)
+
+
+@pytest.mark.parametrize("every", [3, 8])
+def test_step_every_tracks_md_step_and_oracle(orc, every):
+    """With a skin of 0.86 sigma (cell_min 2.9 on lj4k: 5 cells of 3.36) and a
+    rebuild every 3 or 8 steps, 40 steps: no atom leaves its cell by half the
+    skin; energies match the oracle's integrator and md_step on the same grid;
+    the final state (rebuilt and wrapped) has oracle forces."""
+    w = ljsynth.WORKLOADS["lj4k"]
+    _say(f"md_step_every e={every} vs md_step and oracle, lj4k, 40 steps, cell_min 2.9")
+    pos4, vel4, box, ((s, ta, pa, va, fa, ga), (_, tb, pb, vb, fb, gb)) = _run_pair(w, 2.9, 40, every)
+    assert s.cell_side - 2.5 > 0.8
+    assert ga == 0 and gb == 0
+    _, _, tho = orc.run(orc.params(box, dt=w.dt), pos4, vel4, 40)
+    eo = tho[1:, 0] + tho[1:, 1]
+    eb = tb[:, 0] + tb[:, 1]
+    assert np.abs(eb[:10] - eo[:10]).max() / abs(eo[0]) < 1e-5
+    assert np.abs(eb - (ta[:, 0] + ta[:, 1])).max() / abs(eo[0]) < 1e-5
+    d = pb[:, :3] - pa[:, :3]
+    d -= box * np.round(d / box)
+    assert np.abs(d).max() < 1e-3
+    assert (pb[:, :3] >= 0).all() and (pb[:, :3] < box).all()
+    fo, U, W = orc.forces(orc.params(box), pb)
+    assert rel_l2(fb[:, :3].astype(np.float64), fo) <= FORCE_TOL
+
+
+def test_step_every_flags_a_thin_skin():
+    """Cells of side 2.8 (skin 0.3) and no rebuild within 40 steps of a T* = 1
+    fluid (fast atoms move about 0.3 sigma): some atom leaves its cell by more
+    than 0.15 and the run reports MD_DEV_SKIN (and nothing else)."""
+    w = ljsynth.WORKLOADS["lj4k"]
+    _say("md_step_every thin skin, lj4k, 40 steps, no intermediate rebuild")
+    from paper_0709_3225_amd import LJSystem
+
+    pos4, vel4, box = ljsynth.make_state(w)
+    s = LJSystem(w.n, box, dt=w.dt)
+    assert 0.2 < s.cell_side - 2.5 < 0.4
+    s.load(_dev(pos4), _dev(vel4))
+    s.step_every(40, 1000)
+    assert s.check(raise_on_error=False) == 8  # MD_DEV_SKIN
