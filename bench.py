@@ -236,6 +236,44 @@ def skin_leg(torch, nsteps=100, warm=20):
             "value": best["value"]}
 
 
+def pair_list_leg(torch, nsteps=100, warm=20):
+    """The headline workload with pair lists (md_step_list): the force pass
+    after each cell rebuild records every lane's candidates within the cell
+    side, the passes in between walk them; the skin is the grid's margin over
+    r_c. A point is valid when no atom moved by half the skin since the lists
+    were recorded (no MD_DEV_SKIN)."""
+    import ljsynth
+    from paper_0709_3225_amd import LJSystem
+
+    w = ljsynth.WORKLOADS["lj256k"]
+    pos4, vel4, box = ljsynth.make_state(w)
+    points = []
+    for cm, every in ((0.0, 2), (0.0, 3), (0.0, 4), (2.7, 6), (2.7, 10), (2.9, 10), (2.9, 15)):
+        s = LJSystem(w.n, box, dt=w.dt, cell_min=cm)
+        s.load(torch.from_numpy(pos4).cuda(), torch.from_numpy(vel4).cuda())
+        s.step(warm)
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        s.step_list(nsteps, every)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = max(time.perf_counter() - t0, e0.elapsed_time(e1) / 1e3)
+        flags = s.check(raise_on_error=False)
+        points.append({"cells_per_dim": s.cells_per_dim, "skin": round(s.cell_side - w.rc_over_sigma, 4),
+                       "rebuild_every": every, "value": w.n * nsteps / t, "us_per_step": t * 1e6 / nsteps,
+                       "valid": flags == 0})
+    valid = [p for p in points if p["valid"]]
+    best = max(valid, key=lambda p: p["value"]) if valid else None
+    return {"workload": f"{w.name}: LJ N={w.n}, rho={w.density}, T*={w.temperature}, {nsteps} steps after {warm}, "
+                        "pair lists recorded at each cell rebuild (every k steps)",
+            "unit": "atom-steps/s", "points": points,
+            "best": {k: best[k] for k in ("skin", "rebuild_every")} if best else None,
+            "value": best["value"] if best else None}
+
+
 def algorithmic_force_flops(sys_, torch):
     """8 flops per candidate pair the 27-cell method tests plus 17 more per
     accepted ordered pair, counted on the current state."""
@@ -436,6 +474,7 @@ def main():
         out["density_axis"] = density_leg(torch)
         out["wca"] = wca_leg(torch)
         out["skin"] = skin_leg(torch)
+        out["pair_list"] = pair_list_leg(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s.state()[0].cpu().numpy(), box, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -150,6 +150,25 @@ md_status md_step_every(const md_params* p, void* ws, size_t ws_bytes, int32_t n
                         hipStream_t stream);
 
 /*
+ * md_step_every with pair lists (section 3: a Verlet list of partners within
+ * a radius larger than r_c, rebuilt when a particle has moved more than half
+ * the difference). Right after each cell rebuild the force pass screens the
+ * 27-cell neighbourhood against the cell side instead of r_c and keeps, for
+ * every lane of every home cell, its accept words (a bitmask over the staged
+ * candidates); until the next rebuild the force pass walks the kept words
+ * instead of screening. They hold the same candidates in the same order as
+ * the screen plus some beyond r_c that add exact zeros, so the trajectory is
+ * bitwise that of md_step_every with the same arguments. MD_DEV_SKIN is set
+ * if an atom moves more than (cell side - r_c) / 2 from where it was when the
+ * words were kept. Cells that need more than one LDS pass, or more than four
+ * 128-candidate spans per lane, screen as usual. Arguments and return values
+ * as for md_step_every.
+ */
+md_status md_step_list(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps,
+                       int32_t rebuild_every, int32_t thermo_every, double* thermo_dev,
+                       hipStream_t stream);
+
+/*
  * Potential energy U, kinetic energy K = m/2 sum v^2 and virial
  * W = sum over pairs r phi(r) (positive = repulsive) of the current state,
  * written as out3_dev[0..2] (device doubles). Pair and per-atom terms are

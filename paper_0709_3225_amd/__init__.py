@@ -20,6 +20,7 @@ from ._lib import (  # noqa: F401
     md_neighbors,
     md_step,
     md_step_every,
+    md_step_list,
     md_workspace_bytes,
 )
 from .system import LJSystem, occupancy_cell_min  # noqa: F401

@@ -32,6 +32,7 @@ SYMBOLS = (
     "md_forces",
     "md_step",
     "md_step_every",
+    "md_step_list",
     "md_energy_virial",
     "md_get_state",
     "md_neighbors",
@@ -115,6 +116,7 @@ def lib():
         L.md_forces.argtypes = [P, vp, sz, vp, vp]
         L.md_step.argtypes = [P, vp, sz, i32, i32, vp, vp]
         L.md_step_every.argtypes = [P, vp, sz, i32, i32, i32, vp, vp]
+        L.md_step_list.argtypes = [P, vp, sz, i32, i32, i32, vp, vp]
         L.md_energy_virial.argtypes = [P, vp, sz, vp, vp]
         L.md_get_state.argtypes = [P, vp, sz, vp, vp, vp]
         L.md_neighbors.argtypes = [P, vp, sz, vp, vp, i32, vp]
@@ -134,7 +136,7 @@ def lib():
         L.md_batch_graph_create.argtypes = [P, R, i32, vp, sz, i32, i32, vp, vp, ctypes.POINTER(vp)]
         L.md_graph_launch.argtypes = [vp, vp]
         L.md_graph_destroy.argtypes = [vp]
-        for name in ("md_cell_grid", "md_build_cells", "md_forces", "md_step", "md_step_every", "md_energy_virial",
+        for name in ("md_cell_grid", "md_build_cells", "md_forces", "md_step", "md_step_every", "md_step_list", "md_energy_virial",
                      "md_get_state", "md_neighbors", "md_cell_lists", "md_check", "md_adjoint_kick",
                      "md_adjoint_drift", "md_loss_grad", "md_batch_build", "md_batch_forces", "md_batch_step",
                      "md_batch_energy_virial", "md_batch_get_state", "md_batch_graph_create", "md_graph_launch",
@@ -249,6 +251,21 @@ def md_step_every(p: MDParams, ws, nsteps: int, rebuild_every: int, thermo_every
         tp = _ptr(thermo, "thermo", torch.float64)
     _check(lib().md_step_every(ctypes.byref(p), wp, wn, int(nsteps), int(rebuild_every), int(thermo_every), tp,
                                _stream(stream)))
+
+
+def md_step_list(p: MDParams, ws, nsteps: int, rebuild_every: int, thermo_every: int = 0, thermo=None,
+                 stream=None):
+    import torch
+
+    wp, wn = _ws(ws)
+    tp = None
+    if thermo is not None:
+        rows = nsteps // thermo_every if thermo_every > 0 else 0
+        if thermo.numel() < 3 * rows:
+            raise ValueError(f"thermo needs {3 * rows} doubles")
+        tp = _ptr(thermo, "thermo", torch.float64)
+    _check(lib().md_step_list(ctypes.byref(p), wp, wn, int(nsteps), int(rebuild_every), int(thermo_every), tp,
+                              _stream(stream)))
 
 
 def md_energy_virial(p: MDParams, ws, out3, stream=None):

@@ -22,9 +22,9 @@ namespace mdlj {
 namespace {
 
 template <bool ENERGY>
-__device__ __forceinline__ void pair_force(const SimArgs& a, const float4 q, float xi, float yi, float zi,
-                                           bool live, float& fx, float& fy, float& fz, float& u_loc,
-                                           float& w_loc) {
+__device__ __forceinline__ float pair_force(const SimArgs& a, const float4 q, float xi, float yi, float zi,
+                                            bool live, float& fx, float& fy, float& fz, float& u_loc,
+                                            float& w_loc) {
     const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
     // the atom itself never reaches this point (its screen bit is cleared)
@@ -44,6 +44,7 @@ __device__ __forceinline__ void pair_force(const SimArgs& a, const float4 q, flo
         u_loc += ok ? u : 0.0f;
         w_loc += fr * r2;
     }
+    return r2;
 }
 
 // Pair operation of the force walk: the accepted candidate at a byte offset
@@ -60,6 +61,22 @@ struct ForceOp {
     }
 };
 
+// Kept accept words (pair lists as bitmasks): span j of a lane is one 16-byte
+// record; spans past kListSpans are only counted (the cell then screens).
+__device__ __forceinline__ void keep_words(uint4* rows, int& n, const uint32_t (&wd)[kWords]) {
+    if (n < kListSpans) rows[n] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+    ++n;
+}
+
+// Span j's kept words; span 0 was requested before the staging (w0).
+__device__ __forceinline__ void kept_words(const uint4* rows, const uint4& w0, int j, uint32_t (&wd)[kWords]) {
+    const uint4 v = j == 0 ? w0 : rows[j];
+    wd[0] = v.x;
+    wd[1] = v.y;
+    wd[2] = v.z;
+    wd[3] = v.w;
+}
+
 // Forces on the atoms of home cell c (local index of the system described by
 // a); one wavefront. Energy partials go to a.epart[3 (a.cbase + c) + 0..2].
 // KICK completes the step's velocity (v += dt/(2m) F). DRIFT (with KICK) goes
@@ -71,8 +88,16 @@ struct ForceOp {
 // next position and velocity to pos2/vel2 (same sorted slot) instead of
 // binning, and raises DEV_SKIN if the atom has left its cell's box by more
 // than skin_half (cells of side r_c + skin then still hold every partner
-// within r_c in the 27-cell neighbourhood, section 3.1).
-template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT, bool SKIN = false>
+// within r_c in the 27-cell neighbourhood, section 3.1) or, with pair lists,
+// has moved more than disp_half since they were recorded (section 3).
+// LIST 1: the screen takes the list radius (the cell side) as its bound and
+// each lane's accept words are kept (one 16-byte record per span), and the
+// home positions go to posref. LIST 2: a lane walks its kept words instead of
+// screening: the same candidates in the same order plus some beyond r_c,
+// which add exact zeros, so the sums are bitwise those of the screen. A cell
+// with more than kListSpans spans per lane, or more than one pass, screens as
+// usual.
+template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT, bool SKIN = false, int LIST = 0>
 __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile, Neighbourhood& nb, float* red) {
     const int lane = threadIdx.x;
     float ox, oy, oz;
@@ -101,6 +126,17 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
 
     double u_acc = 0.0, w_acc = 0.0, k_acc = 0.0;
     bool bad = false, skin_out = false;
+    const size_t lrow = (static_cast<size_t>(a.cbase + c) * kWave + lane);  // this lane's kept words
+    uint4* lwords = reinterpret_cast<uint4*>(a.plist) + lrow * kListSpans;
+    const bool list_fits = total <= a.tile_cap && n_home <= kWave;          // uniform
+    int n_rec = 0;  // LIST 1: spans kept
+    int list_n = 0;
+    uint4 lw0 = make_uint4(0u, 0u, 0u, 0u);  // LIST 2: the first span's words, requested before staging
+    if (LIST == 2) {
+        list_n = a.plist_n[lrow];
+        lw0 = lwords[0];
+    }
+    const bool use_list = LIST == 2 && list_fits && __all(list_n <= kListSpans);
     for (int h0 = 0; h0 < n_home; h0 += kWave) {
         const int nh = min(kWave, n_home - h0);
         // 11..16 home atoms: matrix-core screen, lane = (atom lane % 16, slice
@@ -117,10 +153,13 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         if (act) pi = a.pos0[home_first + h0 + h];
         float4 vel = make_float4(0.f, 0.f, 0.f, 0.f);  // fetched now, used by the epilogue
         if ((KICK || ENERGY) && lead) vel = a.vel0[home_first + h0 + h];
+        float4 pref = pi;  // LIST: position when the lists were recorded
+        if (LIST == 2 && SKIN && lead) pref = a.posref[home_first + h0 + h];
+        if (LIST == 1 && lead) a.posref[home_first + h0 + h] = pi;
         const float xi = pi.x - ox, yi = pi.y - oy, zi = pi.z - oz;
         const float ai = fmaf(zi, zi, fmaf(yi, yi, xi * xi));
         // idle lanes get a bound no candidate can meet (q.w - thr_i = +inf)
-        const float thr_i = act ? a.screen2 - ai : -__builtin_huge_valf();
+        const float thr_i = act ? (LIST == 1 ? a.list_screen2 : a.screen2) - ai : -__builtin_huge_valf();
         const float mx = -2.0f * xi, my = -2.0f * yi, mz = -2.0f * zi;
         // matrix-core operands: this lane's element of B (component s of
         // (-2 x_i, -2 y_i, -2 z_i, 1)) and of C (-bound + |x_i|^2; +inf idle)
@@ -141,8 +180,13 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                 for (int b0 = 0; b0 < nblk_all; b0 += 8 * kWords) {
                     const int nblk = min(8 * kWords, nblk_all - b0);
                     uint32_t wd[kWords];
-                    screen_mfma(tile, 16 * b0, nblk, bval, cneg, wd);
-                    if (act) clear_self_blocked(self_t - 16 * b0, s, nblk, wd);
+                    if (LIST == 2 && use_list) {
+                        kept_words(lwords, lw0, b0 / (8 * kWords), wd);
+                    } else {
+                        screen_mfma(tile, 16 * b0, nblk, bval, cneg, wd);
+                        if (act) clear_self_blocked(self_t - 16 * b0, s, nblk, wd);
+                        if (LIST == 1) keep_words(lwords, n_rec, wd);
+                    }
                     ForceOp<ENERGY> op{a, reinterpret_cast<const char*>(tile + 16 * b0 + 4 * s), xi, yi, zi, fx, fy,
                                        fz, u_loc, w_loc};
                     walk_bits<ForceOp<ENERGY>, true>(ns, wd[0], wd[1], wd[2], wd[3], op);
@@ -159,15 +203,20 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                 const int groups = min(kGroups, groups_all - g0);
                 const int first = g0 * ns + (act ? s : 0);
                 uint32_t wd[kWords];
-                switch (ns) {
-                    case 2: screen_span<2>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
-                    case 3: screen_span<3>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
-                    case 4: screen_span<4>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
-                    case 5: screen_span<5>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
-                    case 6: screen_span<6>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
-                    default: screen_span<0>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
+                if (LIST == 2 && use_list) {
+                    kept_words(lwords, lw0, g0 / kGroups, wd);
+                } else {
+                    switch (ns) {
+                        case 2: screen_span<2>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
+                        case 3: screen_span<3>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
+                        case 4: screen_span<4>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
+                        case 5: screen_span<5>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
+                        case 6: screen_span<6>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
+                        default: screen_span<0>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
+                    }
+                    if (act) clear_self(self_t, first, ns, groups, wd);
+                    if (LIST == 1) keep_words(lwords, n_rec, wd);
                 }
-                if (act) clear_self(self_t, first, ns, groups, wd);
                 ForceOp<ENERGY> op{a, reinterpret_cast<const char*>(tile + first), xi, yi, zi, fx, fy, fz, u_loc,
                                    w_loc};
                 walk_bits(ns, wd[0], wd[1], wd[2], wd[3], op);
@@ -227,10 +276,15 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                         half_kick_drift_unwrapped(a, p_next, v_next, gx, gy, gz);
                         a.pos2[k] = p_next;
                         a.vel2[k] = v_next;
-                        const float ex = fmaxf(fmaxf(ox - p_next.x, p_next.x - (ox + a.s)), 0.f);
-                        const float ey = fmaxf(fmaxf(oy - p_next.y, p_next.y - (oy + a.s)), 0.f);
-                        const float ez = fmaxf(fmaxf(oz - p_next.z, p_next.z - (oz + a.s)), 0.f);
-                        if (ex * ex + ey * ey + ez * ez > a.skin_half * a.skin_half) skin_out = true;
+                        if (LIST != 0) {
+                            const float ex = p_next.x - pref.x, ey = p_next.y - pref.y, ez = p_next.z - pref.z;
+                            if (ex * ex + ey * ey + ez * ez > a.disp_half * a.disp_half) skin_out = true;
+                        } else {
+                            const float ex = fmaxf(fmaxf(ox - p_next.x, p_next.x - (ox + a.s)), 0.f);
+                            const float ey = fmaxf(fmaxf(oy - p_next.y, p_next.y - (oy + a.s)), 0.f);
+                            const float ez = fmaxf(fmaxf(oz - p_next.z, p_next.z - (oz + a.s)), 0.f);
+                            if (ex * ex + ey * ey + ez * ez > a.skin_half * a.skin_half) skin_out = true;
+                        }
                     } else {
                         c_next = half_kick_drift(a, p_next, v_next, gx, gy, gz);
                     }
@@ -239,6 +293,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         }
         if (DRIFT && !SKIN) bin_atom(a, p_next, v_next, c_next);  // all lanes
     }
+    if (LIST == 1) a.plist_n[lrow] = list_fits ? n_rec : kListSpans + 1;  // kept words of several passes are not used
     if (bad) atomicOr(&a.hdr[HDR_ERROR], DEV_NONFINITE);
     if (SKIN && skin_out) atomicOr(&a.hdr[HDR_ERROR], DEV_SKIN);
     if (ENERGY) {
@@ -279,6 +334,17 @@ __global__ void __launch_bounds__(kWave) k_forces_skin(SimArgs a) {
     __shared__ Neighbourhood nb;
     force_cell<true, ENERGY, false, true, true>(a, xcd_block_order(blockIdx.x, a.ncells), tile, nb,
                                                 reinterpret_cast<float*>(tile));
+}
+
+// Pair-list steps: RECORD right after a rebuild, else walk the recorded lists;
+// BIN: the drift bins for the next rebuild, else it goes to pos2/vel2.
+template <bool ENERGY, bool RECORD, bool BIN>
+__global__ void __launch_bounds__(kWave) k_forces_list(SimArgs a) {
+    if (a.hdr[HDR_ERROR] & DEV_ORDER) return;
+    extern __shared__ float4 tile[];
+    __shared__ Neighbourhood nb;
+    force_cell<true, ENERGY, false, true, !BIN, RECORD ? 1 : 2>(a, xcd_block_order(blockIdx.x, a.ncells), tile, nb,
+                                                                reinterpret_cast<float*>(tile));
 }
 
 // Batched forces: one workgroup per cell of any replica (global cell index,
@@ -440,6 +506,33 @@ hipError_t launch_forces_skin(const SimArgs& a, bool energy, hipStream_t st) {
     const size_t lds = sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
     if (energy) hipLaunchKernelGGL(k_forces_skin<true>, g, b, lds, st, a);
     else hipLaunchKernelGGL(k_forces_skin<false>, g, b, lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_forces_list(const SimArgs& a_in, bool energy, bool record, bool bin, int par, hipStream_t st) {
+    SimArgs a = a_in;
+    a.par = par;
+    const dim3 g(a.ncells), b(kWave);
+    const size_t lds = sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
+#define MD_LIST(E, R, B) hipLaunchKernelGGL((k_forces_list<E, R, B>), g, b, lds, st, a)
+    if (energy) {
+        if (record) {
+            if (bin) MD_LIST(true, true, true);
+            else MD_LIST(true, true, false);
+        } else {
+            if (bin) MD_LIST(true, false, true);
+            else MD_LIST(true, false, false);
+        }
+    } else {
+        if (record) {
+            if (bin) MD_LIST(false, true, true);
+            else MD_LIST(false, true, false);
+        } else {
+            if (bin) MD_LIST(false, false, true);
+            else MD_LIST(false, false, false);
+        }
+    }
+#undef MD_LIST
     return hipGetLastError();
 }
 

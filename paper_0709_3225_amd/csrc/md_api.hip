@@ -84,6 +84,8 @@ int bucket_capacity(double mean_occupancy) {
 
 size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
 
+constexpr int kWaveLanes = 64;  // lanes of the one-wavefront-per-cell kernels (pair-list rows)
+
 // Histograms, buckets, overflow list and CSR offsets of a build over n atoms
 // in ncells cells.
 template <class Take>
@@ -126,6 +128,9 @@ md_status make_layout(const md_params* p, Layout& L) {
     L.force = take(16 * n);
     L.pos2 = take(16 * n);
     L.vel2 = take(16 * n);
+    L.posref = take(16 * n);
+    L.plist = take(16 * static_cast<size_t>(L.ncells) * kWaveLanes * kListSpans);
+    L.plist_n = take(4 * static_cast<size_t>(L.ncells) * kWaveLanes);
     take_build_arrays(L, n, static_cast<size_t>(L.ncells), bucket_capacity(static_cast<double>(p->n) / L.ncells),
                       take);
     L.epart = take(sizeof(double) * 3 * static_cast<size_t>(L.nforce_blocks));
@@ -169,6 +174,9 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     a.force = reinterpret_cast<float4*>(b + L.force);
     a.pos2 = L.pos2 ? reinterpret_cast<float4*>(b + L.pos2) : nullptr;
     a.vel2 = L.vel2 ? reinterpret_cast<float4*>(b + L.vel2) : nullptr;
+    a.posref = L.posref ? reinterpret_cast<float4*>(b + L.posref) : nullptr;
+    a.plist = L.plist ? reinterpret_cast<uint32_t*>(b + L.plist) : nullptr;
+    a.plist_n = L.plist_n ? reinterpret_cast<int*>(b + L.plist_n) : nullptr;
     a.counts = reinterpret_cast<int*>(b + L.counts);
     a.bstart = reinterpret_cast<int*>(b + L.bstart);
     a.bpos = reinterpret_cast<float4*>(b + L.bpos);
@@ -211,6 +219,10 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     // half the margin of the cell side over r_c, less a relative 2^-20 for the
     // FP32 comparison
     a.skin_half = static_cast<float>(std::max(0.0, 0.5 * (static_cast<double>(L.s) - rc) * (1.0 - std::ldexp(1.0, -20))));
+    // pair lists: candidates within the cell side when the words are kept;
+    // valid while no atom has moved by half the side's margin over r_c
+    a.list_screen2 = screen_bound(static_cast<double>(L.s), L.s);
+    a.disp_half = a.skin_half;
     a.tile_cap = tile_capacity(p->n, L.ncells);
     a.dt = p->dt;
     a.hdt_m = static_cast<float>(0.5 * p->dt / p->mass);
@@ -478,6 +490,51 @@ md_status md_step_every(const md_params* p, void* ws, size_t ws_bytes, int32_t n
         } else {
             MD_TRY_HIP(launch_forces_skin(cur, energy, stream), "forces");
             live_alt = !live_alt;
+        }
+        if (energy)
+            MD_TRY_HIP(launch_energy_final(a, thermo + 3 * static_cast<size_t>(k / thermo_every - 1), stream),
+                       "energy");
+    }
+    if (nsteps > 0) MD_TRY_HIP(launch_zero_blocks(a, b & 1, stream), "counter clear");
+    return MD_OK;
+}
+
+md_status md_step_list(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps, int32_t rebuild_every,
+                       int32_t thermo_every, double* thermo, hipStream_t stream) {
+    Layout L{};
+    md_status s = make_layout(p, L);
+    if (s != MD_OK) return s;
+    if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
+    if (nsteps < 0) return fail(MD_ERR_ARG, "nsteps must be >= 0");
+    if (rebuild_every < 1) return fail(MD_ERR_ARG, "rebuild_every must be >= 1");
+    if (thermo_every < 0) return fail(MD_ERR_ARG, "thermo_every must be >= 0");
+    if (thermo_every > 0 && !thermo) return fail(MD_ERR_ARG, "thermo_every > 0 needs a thermo buffer");
+    const SimArgs a = make_args(p, L, ws);
+    SimArgs alt = a;
+    std::swap(alt.pos0, alt.pos2);
+    std::swap(alt.vel0, alt.vel2);
+    // The schedule of md_step_every; the force pass right after a rebuild
+    // keeps every lane's accept words (screened against the cell side), the
+    // others walk the kept words instead of screening.
+    int b = 0;
+    bool live_alt = false;
+    for (int32_t k = 1; k <= nsteps; ++k) {
+        const bool energy = thermo && thermo_every > 0 && (k % thermo_every) == 0;
+        const bool last = k == nsteps;
+        const bool rebuild_now = k == 1 || last || (k - 1) % rebuild_every == 0;
+        const bool rebuild_next = !last && (k + 1 == nsteps || k % rebuild_every == 0);
+        if (k == 1) MD_TRY_HIP(launch_integrate(a, stream), "integrate");
+        if (rebuild_now) {
+            if (k > 1) ++b;
+            if ((s = rebuild(a, b & 1, true, stream)) != MD_OK) return s;
+            live_alt = false;
+        }
+        const SimArgs& cur = live_alt ? alt : a;
+        if (last) {
+            MD_TRY_HIP(launch_forces(cur, true, energy, true, true, false, (b + 1) & 1, stream), "forces");
+        } else {
+            MD_TRY_HIP(launch_forces_list(cur, energy, rebuild_now, rebuild_next, (b + 1) & 1, stream), "forces");
+            if (!rebuild_next) live_alt = !live_alt;
         }
         if (energy)
             MD_TRY_HIP(launch_energy_final(a, thermo + 3 * static_cast<size_t>(k / thermo_every - 1), stream),

@@ -25,6 +25,10 @@ enum : int { STATE_BUILDING = 0x4D440000, STATE_CELLS = 0x4D440001, STATE_FORCES
 // kDirectBlocks blocks each workgroup sums the block counts before its own.
 constexpr int kBlockShift = 4;
 constexpr int kDirectBlocks = 2048;
+// Pair lists: a cell's lanes keep the accept words of its screen (one span
+// covers 128 candidates of a lane; a liquid-density neighbourhood of about
+// 400 atoms needs one span with four slices, two with two or three).
+constexpr int kListSpans = 4;  // kept accept-word spans (16 bytes each) per lane of a cell
 
 // Device error bits (same values as the public MD_DEV_* macros).
 enum : int { DEV_NONFINITE = 1, DEV_ORDER = 2, DEV_NB_OVERFLOW = 4, DEV_SKIN = 8 };
@@ -43,6 +47,15 @@ struct SimArgs {
     float4* pos2;
     float4* vel2;
     float skin_half;  // an atom may leave its cell's box by this much before a rebuild is due
+    // Pair lists (md_step_list): per cell and lane, the accept words of the
+    // screen against the list radius (the cell side), kListSpans spans of
+    // four words at most (plist_n: the count; more marks a cell that screens
+    // instead); posref: positions when the words were kept.
+    uint32_t* plist;
+    int* plist_n;
+    float4* posref;
+    float list_screen2;  // screen bound when the words are kept (cell side^2 plus the screen margin)
+    float disp_half;     // largest displacement since recording: (side - r_c) / 2
     // Cell build: per-cell histogram, zero between builds; a binned atom's
     // position and velocity go to its cell's bucket of cap entries, or to the
     // overflow list (pos1, vel1 and the cell) past the capacity.
@@ -100,7 +113,7 @@ struct Layout {
     float s, inv_s;
     int nblocks, cap;
     int nbstride;
-    size_t hdr, pos0, vel0, pos1, vel1, force, pos2, vel2, counts, bstart, bcounts, bpos, bvel, ovf_cell, start, epart, total;
+    size_t hdr, pos0, vel0, pos1, vel1, force, pos2, vel2, posref, plist, plist_n, counts, bstart, bcounts, bpos, bvel, ovf_cell, start, epart, total;
 };
 
 // Kernel launchers (each returns hipGetLastError() after its launch).
@@ -117,6 +130,9 @@ hipError_t launch_forces(const SimArgs& a, bool kick, bool energy, bool write_fo
                          int par, hipStream_t st);
 // A step between rebuilds: forces, kick, next drift into pos2/vel2 (md_step_every).
 hipError_t launch_forces_skin(const SimArgs& a, bool energy, hipStream_t st);
+// Pair-list steps (md_step_list): record (right after a rebuild) or use the
+// lists; the drift bins for a rebuild (bin) or goes to pos2/vel2.
+hipError_t launch_forces_list(const SimArgs& a, bool energy, bool record, bool bin, int par, hipStream_t st);
 hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st);
 hipError_t launch_gather_user(const SimArgs& a, float4* pos_out, float4* vel_out, float4* force_out,
                               hipStream_t st);

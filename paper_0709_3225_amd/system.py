@@ -63,6 +63,15 @@ class LJSystem:
         L.md_step_every(self.params, self.ws, nsteps, rebuild_every, thermo_every if thermo is not None else 0, thermo)
         return thermo
 
+    def step_list(self, nsteps: int, rebuild_every: int, thermo_every: int = 0):
+        """md_step_list: as step_every, with pair lists recorded at each
+        rebuild and walked in between."""
+        thermo = None
+        if thermo_every > 0 and nsteps >= thermo_every:
+            thermo = torch.empty((nsteps // thermo_every, 3), dtype=torch.float64, device=self.device)
+        L.md_step_list(self.params, self.ws, nsteps, rebuild_every, thermo_every if thermo is not None else 0, thermo)
+        return thermo
+
     def energy(self) -> torch.Tensor:
         out = torch.empty(3, dtype=torch.float64, device=self.device)
         L.md_energy_virial(self.params, self.ws, out)

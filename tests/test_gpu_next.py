@@ -219,3 +219,68 @@ def test_step_every_flags_a_thin_skin():
     s.load(_dev(pos4), _dev(vel4))
     s.step_every(40, 1000)
     assert s.check(raise_on_error=False) == 8  # MD_DEV_SKIN
+
+
+# ---- pair lists (md_step_list): the screen's candidates cached between rebuilds
+
+def _run_modes(pos4, vel4, box, n, cell_min, nsteps, every, modes, dt=0.005):
+    from paper_0709_3225_amd import LJSystem
+
+    out = {}
+    for mode in modes:
+        s = LJSystem(n, box, dt=dt, cell_min=cell_min)
+        s.load(_dev(pos4), None if vel4 is None else _dev(vel4))
+        run = {"every": s.step_every, "list": s.step_list}[mode]
+        th = run(nsteps, every, thermo_every=1)
+        flags = s.check(raise_on_error=False)
+        p, v = s.state()
+        out[mode] = (th.cpu().numpy(), p.cpu().numpy(), v.cpu().numpy(), s.forces().cpu().numpy(), flags)
+    return out
+
+
+@pytest.mark.parametrize("cell_min,every", [(0.0, 3), (2.9, 3), (2.9, 8)])
+def test_step_list_bitwise_equals_step_every(cell_min, every):
+    """The lists hold the screen's candidates in the screen's order, so a run
+    with pair lists is bitwise the run that screens every step (same
+    rebuild schedule)."""
+    w = ljsynth.WORKLOADS["lj4k"]
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05)
+    _say(f"md_step_list vs md_step_every lj4k cell_min={cell_min} e={every} 30 steps")
+    out = _run_modes(pos4, vel4, box, w.n, cell_min, 30, every, ("every", "list"))
+    for x, y in zip(out["every"][:4], out["list"][:4]):
+        assert np.array_equal(x, y)
+    if cell_min:
+        assert out["list"][4] == 0
+
+
+def test_step_list_full_size_and_overflow_fallback():
+    """N = 256,000 on the default grid, rebuilds every 3 steps, 12 steps; and
+    the dense block (cells of more than 64 atoms, neighbourhoods of more than
+    one LDS pass) whose cells keep screening: both bitwise equal to
+    md_step_every."""
+    w = ljsynth.WORKLOADS["lj256k"]
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05)
+    _say("md_step_list vs md_step_every lj256k e=3 12 steps")
+    out = _run_modes(pos4, vel4, box, w.n, 0.0, 12, 3, ("every", "list"))
+    for x, y in zip(out["every"][:4], out["list"][:4]):
+        assert np.array_equal(x, y)
+    g = np.arange(0.3, 5.9, 0.53)
+    pts = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    pts = pts + np.random.default_rng(9).uniform(-0.002, 0.002, pts.shape)
+    clump = np.zeros((len(pts), 4), np.float32)
+    clump[:, :3] = pts
+    _say(f"md_step_list vs md_step_every dense block n={len(clump)} e=2 6 steps")
+    out = _run_modes(clump, None, 12.0, len(clump), 0.0, 6, 2, ("every", "list"), dt=1e-5)
+    for x, y in zip(out["every"][:4], out["list"][:4]):
+        assert np.array_equal(x, y)
+
+
+def test_step_list_flags_displacement():
+    """Pair lists recorded once and walked for 40 steps of a T* = 1 fluid on
+    a grid with a 0.3 sigma margin: some atom moves more than 0.15 sigma and
+    the run reports MD_DEV_SKIN."""
+    w = ljsynth.WORKLOADS["lj4k"]
+    pos4, vel4, box = ljsynth.make_state(w)
+    _say("md_step_list thin skin lj4k 40 steps")
+    out = _run_modes(pos4, vel4, box, w.n, 0.0, 40, 1000, ("list",))
+    assert out["list"][4] == 8
