@@ -502,13 +502,10 @@ __device__ __forceinline__ void screen_span(const float4* tile, int first, int n
 // lanes that have spent their bits. The words rotate through four registers
 // (never indexed, which would put them in scratch memory); an exhausted word
 // is replaced by the next one without a branch.
-// BLOCKED: the words come from screen_mfma (bit 4b + i of a word is candidate
-// 16 b + i of the lane's span, whose first candidate is its slice's), so a bit
-// index k maps to byte offset 256 (k >> 2) + 16 (k & 3) and a word spans 2 KiB.
-template <class Op, bool BLOCKED = false>
+template <class Op>
 __device__ __forceinline__ void walk_bits(int ns, uint32_t m, uint32_t n1, uint32_t n2, uint32_t n3, Op& op) {
     const uint32_t cstep = static_cast<uint32_t>(ns) * sizeof(float4);   // bytes between candidates
-    const uint32_t wstep = BLOCKED ? 8u * 16u * sizeof(float4) : 32u * cstep;  // bytes between words
+    const uint32_t wstep = 32u * cstep;                                  // bytes between words
     uint32_t wb = 0;                                                     // byte offset of the word's candidate 0
     uint32_t left = __builtin_popcount(m) + __builtin_popcount(n1) + __builtin_popcount(n2) +
                     __builtin_popcount(n3);
@@ -526,9 +523,7 @@ __device__ __forceinline__ void walk_bits(int ns, uint32_t m, uint32_t n1, uint3
         left -= live ? 1u : 0u;
         // a spent lane keeps rotating (wb grows past its span): it reads its
         // span's first candidate instead, which is always staged
-        // blocked: 256 (k >> 2) + 16 (k & 3) = 16 k + 192 (k >> 2)
-        const uint32_t koff = BLOCKED ? (k << 4) + 192u * (k >> 2) : k * cstep;
-        op(live ? wb + koff : 0u, live);
+        op(live ? wb + __umul24(k, cstep) : 0u, live);
     } while (__any(left != 0u));
 }
 
@@ -553,23 +548,27 @@ __device__ __forceinline__ void clear_self(int self_t, int first, int ns, int gr
 // x, y, z, |x|^2 in the home frame), B the 16 home atoms (columns:
 // -2 x_i, -2 y_i, -2 z_i, 1) and C = -(bound - |x_i|^2) per column, so that
 // D[j][i] = |x_j|^2 - 2 x_i.x_j - (bound - |x_i|^2) = r^2 - bound, negative
-// iff accepted. Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
-// receives D[4 (l / 16) + q][l % 16], q = 0..3: lane (home atom l % 16,
-// slice l / 16) gets the verdicts on candidates 16 b + 4 (l / 16) + q of
-// every block b, four sign bits per block, one v_alignbit each (about one
-// VALU instruction per candidate instead of five). Unused home columns carry
-// C = +inf and B = (0, 0, 0, 1): their D is +inf. Padding entries (w = +inf)
-// are never accepted either.
+// iff accepted. Lane l supplies B[l / 16][l % 16] and A[l % 16][l / 16],
+// where row m of A is candidate 4 (m % 4) + m / 4 of the block, and receives
+// D[4 (l / 16) + q][l % 16], q = 0..3: lane (home atom l % 16, slice
+// s = l / 16) gets the verdicts on candidates 16 b + 4 q + s of every block
+// b, four sign bits per block, one v_alignbit each (about one VALU
+// instruction per candidate instead of five). A lane's bits thus follow its
+// candidates s, s + 4, s + 8, ... in order: the words are those of the VALU
+// screen with ns = 4 slices, and the same walk takes them. Unused home
+// columns carry C = +inf and B = (0, 0, 0, 1): their D is +inf. Padding
+// entries (w = +inf) are never accepted either.
 constexpr int kMfmaMinHome = 11;  // below this the VALU screen's extra slices win
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 
 // Screen one span of nblk <= 32 blocks starting at candidate first (a
-// multiple of 16): word w, bit 31 - (4 (b - 8 w) + q) holds the verdict on
-// block b, row q of this lane. bval: this lane's B element; cneg: C.
+// multiple of 16): word w, bit 31 - k holds the verdict on the lane's
+// candidate first + 4 (32 w + k) + s. bval: this lane's B element; cneg: C.
 __device__ __forceinline__ void screen_mfma(const float4* tile, int first, int nblk, float bval, float cneg,
                                             uint32_t (&wd)[kWords]) {
     const int lane = threadIdx.x;
-    const float* base = reinterpret_cast<const float*>(tile + first) + (lane & 15) * 4 + (lane >> 4);
+    const int row = lane & 15;  // A row: candidate 4 (row % 4) + row / 4 of each block
+    const float* base = reinterpret_cast<const float*>(tile + first) + (4 * (row & 3) + (row >> 2)) * 4 + (lane >> 4);
     const mfma_f4 c = {cneg, cneg, cneg, cneg};
 #pragma unroll
     for (int w = 0; w < kWords; ++w) {
@@ -592,19 +591,6 @@ __device__ __forceinline__ void screen_mfma(const float4* tile, int first, int n
         }
         wd[w] = bits;
     }
-}
-
-// Clear the home atom's own bit (span index self_t = tile index - first) in
-// the blocked layout, if it lies in this lane's slice s.
-__device__ __forceinline__ void clear_self_blocked(int self_t, int s, int nblk, uint32_t (&wd)[kWords]) {
-    if (self_t < 0 || self_t >= 16 * nblk || ((self_t & 15) >> 2) != s) return;
-    const int b = self_t >> 4;
-    const uint32_t bit = 0x80000000u >> (4 * (b & 7) + (self_t & 3));
-    const int w = b >> 3;
-    wd[0] &= (w == 0) ? ~bit : ~0u;
-    wd[1] &= (w == 1) ? ~bit : ~0u;
-    wd[2] &= (w == 2) ? ~bit : ~0u;
-    wd[3] &= (w == 3) ? ~bit : ~0u;
 }
 
 }  // namespace

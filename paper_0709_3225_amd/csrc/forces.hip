@@ -184,12 +184,13 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                         kept_words(lwords, lw0, b0 / (8 * kWords), wd);
                     } else {
                         screen_mfma(tile, 16 * b0, nblk, bval, cneg, wd);
-                        if (act) clear_self_blocked(self_t - 16 * b0, s, nblk, wd);
+                        if (act) clear_self(self_t - 16 * b0, s, 4, 4 * nblk, wd);
                         if (LIST == 1) keep_words(lwords, n_rec, wd);
                     }
-                    ForceOp<ENERGY> op{a, reinterpret_cast<const char*>(tile + 16 * b0 + 4 * s), xi, yi, zi, fx, fy,
-                                       fz, u_loc, w_loc};
-                    walk_bits<ForceOp<ENERGY>, true>(ns, wd[0], wd[1], wd[2], wd[3], op);
+                    // the lane's candidates are tile + 16 b0 + s + 4 g, as for four VALU slices
+                    ForceOp<ENERGY> op{a, reinterpret_cast<const char*>(tile + 16 * b0 + s), xi, yi, zi, fx, fy, fz,
+                                       u_loc, w_loc};
+                    walk_bits<ForceOp<ENERGY>>(4, wd[0], wd[1], wd[2], wd[3], op);
                     fx = op.fx;
                     fy = op.fy;
                     fz = op.fz;
