@@ -121,9 +121,13 @@ __global__ void __launch_bounds__(kWave)
     double acc0 = 0.0, acc1 = 0.0;
     for (int h0 = 0; h0 < n_home; h0 += kWave) {
         const int nh = min(kWave, n_home - h0);
-        const int ns = min(kMaxSlices, kWave / nh);
-        const int h = lane % nh, s = lane / nh;
-        const bool act = s < ns;
+        // 11..16 home atoms: matrix-core screen with four slices, lane =
+        // (atom lane % 16, slice lane / 16), as in the force kernel
+        const bool mf = nh >= kMfmaMinHome && nh <= 16;  // uniform
+        const int ns = mf ? 4 : min(kMaxSlices, kWave / nh);
+        const int hstride = mf ? 16 : nh;
+        const int h = lane % hstride, s = lane / hstride;
+        const bool act = mf ? h < nh : s < ns;
         float4 pi = make_float4(0.f, 0.f, 0.f, 0.f), wi = pi;
         if (act) {
             pi = a.pos0[home_first + h0 + h];
@@ -133,6 +137,8 @@ __global__ void __launch_bounds__(kWave)
         const float ai = fmaf(zi, zi, fmaf(yi, yi, xi * xi));
         const float thr_i = act ? a.screen2 - ai : -__builtin_huge_valf();
         const float mx = -2.0f * xi, my = -2.0f * yi, mz = -2.0f * zi;
+        const float bval = s == 3 ? 1.0f : (act ? (s == 0 ? mx : (s == 1 ? my : mz)) : 0.0f);
+        const float cneg = -thr_i;
         float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f;
         for (int t0 = 0; t0 < total; t0 += a.tile_cap) {
             const int tn = min(a.tile_cap, total - t0);
@@ -143,13 +149,24 @@ __global__ void __launch_bounds__(kWave)
                 if (ADJ) wtile[tn + t] = make_float4(0.f, 0.f, 0.f, 0.f);
             }
             __syncthreads();
-            const int groups_all = (tn + ns - 1) / ns;
             const int self_t = nb.home_pos + h0 + h - t0;
+            // spans: 128 candidates per lane (32 blocks of 16 with the matrix cores)
+            const int groups_all = mf ? 4 * ((tn + 15) / 16) : (tn + ns - 1) / ns;
             for (int g0 = 0; g0 < groups_all; g0 += kGroups) {
                 const int groups = min(kGroups, groups_all - g0);
-                const int first = g0 * ns + (act ? s : 0);
+                const int first = mf ? 4 * g0 + s : g0 * ns + (act ? s : 0);
                 uint32_t wd[kWords];
-                screen_span<0>(tile, first, ns, groups, mx, my, mz, thr_i, wd);
+                if (mf) {
+                    screen_mfma(tile, 4 * g0, groups / 4, bval, cneg, wd);
+                } else {
+                    switch (ns) {
+                        case 2: screen_span<2>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
+                        case 3: screen_span<3>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
+                        case 5: screen_span<5>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
+                        case 6: screen_span<6>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
+                        default: screen_span<0>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
+                    }
+                }
                 if (act) clear_self(self_t, first, ns, groups, wd);
                 if (ADJ) {
                     AdjOp op{a, reinterpret_cast<const char*>(tile + first), reinterpret_cast<const char*>(wtile + first),
@@ -179,10 +196,10 @@ __global__ void __launch_bounds__(kWave)
             red[6 * kWave + lane] = v6;
         }
         __syncthreads();
-        if (s == 0) {
+        if (act && s == 0) {
             float r[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             for (int q = 0; q < ns; ++q) {
-                const int l = h + q * nh;
+                const int l = h + q * hstride;
 #pragma unroll
                 for (int k = 0; k < 7; ++k)
                     if (ADJ || k < 5) r[k] += red[k * kWave + l];
