@@ -232,6 +232,21 @@ md_status md_adjoint_drift(const md_params* p, const float* lam_r4_dev, float* l
                            hipStream_t stream);
 
 /*
+ * One checkpoint segment of the backward pass, composed of the calls above
+ * with no host round trips: from the checkpoint (ckpt_pos4_dev,
+ * ckpt_vel4_dev: the state after step first_step) recompute the positions of
+ * the segment's nsteps steps into path4_dev (nsteps * n float4, caller-owned
+ * scratch), then from the last back to the first apply the drift adjoint and
+ * the kick adjoint at that step's positions, with coefficient 2h, or h for
+ * step 0 (h = dt / 2m). lam_r4_dev, lam_v4_dev and theta_dev accumulate as
+ * for md_adjoint_drift and md_adjoint_kick. The workspace is overwritten.
+ */
+md_status md_adjoint_segment(const md_params* p, void* ws, size_t ws_bytes, const float* ckpt_pos4_dev,
+                             const float* ckpt_vel4_dev, int32_t first_step, int32_t nsteps,
+                             float* path4_dev, float* lam_r4_dev, float* lam_v4_dev,
+                             double* theta_dev, hipStream_t stream);
+
+/*
  * Gradient of the loss k_coef * K + w_coef * W at the current workspace
  * state (K = m/2 sum v^2, W = sum over pairs r phi(r)):
  *   g_r4_dev = w_coef * dW/dr, g_v4_dev = k_coef * m * v (both written),

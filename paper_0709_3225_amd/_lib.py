@@ -39,6 +39,7 @@ SYMBOLS = (
     "md_cell_lists",
     "md_adjoint_kick",
     "md_adjoint_drift",
+    "md_adjoint_segment",
     "md_loss_grad",
     "md_batch_workspace_bytes",
     "md_batch_build",
@@ -125,6 +126,7 @@ def lib():
         L.md_adjoint_kick.argtypes = [P, vp, sz, vp, vp, vp, ctypes.c_float, vp]
         L.md_adjoint_drift.argtypes = [P, vp, vp, vp]
         L.md_loss_grad.argtypes = [P, vp, sz, ctypes.c_float, ctypes.c_float, vp, vp, vp, vp]
+        L.md_adjoint_segment.argtypes = [P, vp, sz, vp, vp, i32, i32, vp, vp, vp, vp, vp]
         R = ctypes.POINTER(MDReplica)
         L.md_batch_workspace_bytes.argtypes = [P, R, i32]
         L.md_batch_workspace_bytes.restype = sz
@@ -138,7 +140,7 @@ def lib():
         L.md_graph_destroy.argtypes = [vp]
         for name in ("md_cell_grid", "md_build_cells", "md_forces", "md_step", "md_step_every", "md_step_list", "md_energy_virial",
                      "md_get_state", "md_neighbors", "md_cell_lists", "md_check", "md_adjoint_kick",
-                     "md_adjoint_drift", "md_loss_grad", "md_batch_build", "md_batch_forces", "md_batch_step",
+                     "md_adjoint_drift", "md_adjoint_segment", "md_loss_grad", "md_batch_build", "md_batch_forces", "md_batch_step",
                      "md_batch_energy_virial", "md_batch_get_state", "md_batch_graph_create", "md_graph_launch",
                      "md_graph_destroy"):
             getattr(L, name).restype = ctypes.c_int
@@ -328,6 +330,23 @@ def md_adjoint_drift(p: MDParams, lam_r4, lam_v4, stream=None):
 
     _check(lib().md_adjoint_drift(ctypes.byref(p), _ptr(lam_r4, "lam_r4", torch.float32, (p.n, 4)),
                                   _ptr(lam_v4, "lam_v4", torch.float32, (p.n, 4)), _stream(stream)))
+
+
+def md_adjoint_segment(p: MDParams, ws, ckpt_pos4, ckpt_vel4, first_step: int, nsteps: int, path4, lam_r4, lam_v4,
+                       theta=None, stream=None):
+    """Recompute a checkpoint segment and run its drift and kick adjoints (md_adjoint_segment)."""
+    import torch
+
+    wp, wn = _ws(ws)
+    n = p.n
+    if path4.numel() < 4 * n * nsteps:
+        raise ValueError(f"path4 needs {nsteps} x {n} float4")
+    _check(lib().md_adjoint_segment(
+        ctypes.byref(p), wp, wn, _ptr(ckpt_pos4, "ckpt_pos4", torch.float32, (n, 4)),
+        _ptr(ckpt_vel4, "ckpt_vel4", torch.float32, (n, 4)), int(first_step), int(nsteps),
+        _ptr(path4, "path4", torch.float32), _ptr(lam_r4, "lam_r4", torch.float32, (n, 4)),
+        _ptr(lam_v4, "lam_v4", torch.float32, (n, 4)),
+        None if theta is None else _ptr(theta, "theta", torch.float64), _stream(stream)))
 
 
 def md_loss_grad(p: MDParams, ws, k_coef: float, w_coef: float, g_r4, g_v4, theta=None, stream=None):

@@ -65,18 +65,9 @@ def _backward(run: _Runner, ckpts, gl: float, every):
     L.md_adjoint_kick(run.p, run.ws, lam_v, lam_r, theta, run.h)
     path = torch.empty((every, run.n, 4), dtype=torch.float32, device=run.dev)
     for n0, k, cp, cv in reversed(ckpts):
-        # recompute r_{n0} .. r_{n0+k-1}
-        L.md_build_cells(run.p, run.ws, cp, cv)
-        L.md_forces(run.p, run.ws)
-        path[0].copy_(cp)
-        for j in range(1, k):
-            L.md_step(run.p, run.ws, 1)
-            L.md_get_state(run.p, run.ws, path[j], None)
-        for j in range(k - 1, -1, -1):
-            n = n0 + j
-            L.md_adjoint_drift(run.p, lam_r, lam_v)
-            L.md_build_cells(run.p, run.ws, path[j], None)
-            L.md_adjoint_kick(run.p, run.ws, lam_v, lam_r, theta, 2.0 * run.h if n >= 1 else run.h)
+        # recompute r_{n0} .. r_{n0+k-1}, then the drift and kick adjoints of
+        # steps n0+k-1 .. n0 (one library call per segment)
+        L.md_adjoint_segment(run.p, run.ws, cp, cv, n0, k, path, lam_r, lam_v, theta)
     L.md_check(run.ws)
     return lam_r, lam_v, theta
 

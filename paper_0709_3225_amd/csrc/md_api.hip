@@ -625,6 +625,38 @@ md_status md_adjoint_drift(const md_params* p, const float* lam_r4, float* lam_v
     return MD_OK;
 }
 
+md_status md_adjoint_segment(const md_params* p, void* ws, size_t ws_bytes, const float* ckpt_pos4,
+                             const float* ckpt_vel4, int32_t first_step, int32_t nsteps, float* path4, float* lam_r4,
+                             float* lam_v4, double* theta, hipStream_t stream) {
+    md_status s = validate(p);
+    if (s != MD_OK) return s;
+    if (p->shift_mode != 0) return fail(MD_ERR_ARG, "the adjoint needs shift_mode 0 (force shift)");
+    if (nsteps < 1 || first_step < 0) return fail(MD_ERR_ARG, "need nsteps >= 1 and first_step >= 0");
+    if (!ckpt_pos4 || !ckpt_vel4 || !path4 || !lam_r4 || !lam_v4)
+        return fail(MD_ERR_ARG, "segment arrays are NULL");
+    if (!aligned16(ckpt_pos4) || !aligned16(ckpt_vel4) || !aligned16(path4) || !aligned16(lam_r4) ||
+        !aligned16(lam_v4))
+        return fail(MD_ERR_ARG, "segment arrays must be 16-byte aligned");
+    const size_t n4 = 4 * static_cast<size_t>(p->n);
+    const float h = static_cast<float>(0.5 * p->dt / p->mass);
+    // recompute r_first .. r_{first + nsteps - 1} into path4[0 .. nsteps)
+    if ((s = md_build_cells(p, ws, ws_bytes, ckpt_pos4, ckpt_vel4, stream)) != MD_OK) return s;
+    if ((s = md_forces(p, ws, ws_bytes, nullptr, stream)) != MD_OK) return s;
+    MD_TRY_HIP(hipMemcpyAsync(path4, ckpt_pos4, n4 * sizeof(float), hipMemcpyDeviceToDevice, stream), "copy");
+    for (int32_t j = 1; j < nsteps; ++j) {
+        if ((s = md_step(p, ws, ws_bytes, 1, 0, nullptr, stream)) != MD_OK) return s;
+        if ((s = md_get_state(p, ws, ws_bytes, path4 + j * n4, nullptr, stream)) != MD_OK) return s;
+    }
+    // from the last step of the segment back to its first
+    for (int32_t j = nsteps - 1; j >= 0; --j) {
+        if ((s = md_adjoint_drift(p, lam_r4, lam_v4, stream)) != MD_OK) return s;
+        if ((s = md_build_cells(p, ws, ws_bytes, path4 + j * n4, nullptr, stream)) != MD_OK) return s;
+        const float coef = first_step + j >= 1 ? 2.0f * h : h;
+        if ((s = md_adjoint_kick(p, ws, ws_bytes, lam_v4, lam_r4, theta, coef, stream)) != MD_OK) return s;
+    }
+    return MD_OK;
+}
+
 md_status md_loss_grad(const md_params* p, void* ws, size_t ws_bytes, float k_coef, float w_coef, float* g_r4,
                        float* g_v4, double* theta, hipStream_t stream) {
     Layout L{};
