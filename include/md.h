@@ -234,17 +234,19 @@ md_status md_adjoint_drift(const md_params* p, const float* lam_r4_dev, float* l
 /*
  * One checkpoint segment of the backward pass, composed of the calls above
  * with no host round trips: from the checkpoint (ckpt_pos4_dev,
- * ckpt_vel4_dev: the state after step first_step) recompute the positions of
- * the segment's nsteps steps into path4_dev (nsteps * n float4, caller-owned
- * scratch), then from the last back to the first apply the drift adjoint and
- * the kick adjoint at that step's positions, with coefficient 2h, or h for
- * step 0 (h = dt / 2m). lam_r4_dev, lam_v4_dev and theta_dev accumulate as
- * for md_adjoint_drift and md_adjoint_kick. The workspace is overwritten.
+ * ckpt_vel4_dev: the state after step first_step) recompute the segment's
+ * nsteps states, keeping each one's cell-sorted positions in path4_dev
+ * (nsteps * n float4) and its cell offsets in path_start_dev
+ * (nsteps * (n_c^3 + 1) int32), both caller-owned scratch; then from the last
+ * step back to the first apply the drift adjoint and the kick adjoint on the
+ * kept cell list, with coefficient 2h, or h for step 0 (h = dt / 2m).
+ * lam_r4_dev, lam_v4_dev and theta_dev accumulate as for md_adjoint_drift and
+ * md_adjoint_kick. The workspace is overwritten.
  */
 md_status md_adjoint_segment(const md_params* p, void* ws, size_t ws_bytes, const float* ckpt_pos4_dev,
                              const float* ckpt_vel4_dev, int32_t first_step, int32_t nsteps,
-                             float* path4_dev, float* lam_r4_dev, float* lam_v4_dev,
-                             double* theta_dev, hipStream_t stream);
+                             float* path4_dev, int32_t* path_start_dev, float* lam_r4_dev,
+                             float* lam_v4_dev, double* theta_dev, hipStream_t stream);
 
 /*
  * Gradient of the loss k_coef * K + w_coef * W at the current workspace

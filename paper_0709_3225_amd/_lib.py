@@ -126,7 +126,7 @@ def lib():
         L.md_adjoint_kick.argtypes = [P, vp, sz, vp, vp, vp, ctypes.c_float, vp]
         L.md_adjoint_drift.argtypes = [P, vp, vp, vp]
         L.md_loss_grad.argtypes = [P, vp, sz, ctypes.c_float, ctypes.c_float, vp, vp, vp, vp]
-        L.md_adjoint_segment.argtypes = [P, vp, sz, vp, vp, i32, i32, vp, vp, vp, vp, vp]
+        L.md_adjoint_segment.argtypes = [P, vp, sz, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]
         R = ctypes.POINTER(MDReplica)
         L.md_batch_workspace_bytes.argtypes = [P, R, i32]
         L.md_batch_workspace_bytes.restype = sz
@@ -332,19 +332,23 @@ def md_adjoint_drift(p: MDParams, lam_r4, lam_v4, stream=None):
                                   _ptr(lam_v4, "lam_v4", torch.float32, (p.n, 4)), _stream(stream)))
 
 
-def md_adjoint_segment(p: MDParams, ws, ckpt_pos4, ckpt_vel4, first_step: int, nsteps: int, path4, lam_r4, lam_v4,
-                       theta=None, stream=None):
+def md_adjoint_segment(p: MDParams, ws, ckpt_pos4, ckpt_vel4, first_step: int, nsteps: int, path4, path_start,
+                       lam_r4, lam_v4, theta=None, stream=None):
     """Recompute a checkpoint segment and run its drift and kick adjoints (md_adjoint_segment)."""
     import torch
 
     wp, wn = _ws(ws)
     n = p.n
+    nc, _ = md_cell_grid(p)
     if path4.numel() < 4 * n * nsteps:
         raise ValueError(f"path4 needs {nsteps} x {n} float4")
+    if path_start.numel() < nsteps * (nc ** 3 + 1):
+        raise ValueError(f"path_start needs {nsteps} x {nc ** 3 + 1} int32")
     _check(lib().md_adjoint_segment(
         ctypes.byref(p), wp, wn, _ptr(ckpt_pos4, "ckpt_pos4", torch.float32, (n, 4)),
         _ptr(ckpt_vel4, "ckpt_vel4", torch.float32, (n, 4)), int(first_step), int(nsteps),
-        _ptr(path4, "path4", torch.float32), _ptr(lam_r4, "lam_r4", torch.float32, (n, 4)),
+        _ptr(path4, "path4", torch.float32), _ptr(path_start, "path_start", torch.int32),
+        _ptr(lam_r4, "lam_r4", torch.float32, (n, 4)),
         _ptr(lam_v4, "lam_v4", torch.float32, (n, 4)),
         None if theta is None else _ptr(theta, "theta", torch.float64), _stream(stream)))
 

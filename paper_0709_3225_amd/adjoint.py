@@ -64,10 +64,12 @@ def _backward(run: _Runner, ckpts, gl: float, every):
     L.md_loss_grad(run.p, run.ws, gl / run.n, gl / (3.0 * run.box ** 3), lam_r, lam_v, theta)
     L.md_adjoint_kick(run.p, run.ws, lam_v, lam_r, theta, run.h)
     path = torch.empty((every, run.n, 4), dtype=torch.float32, device=run.dev)
+    nc, _ = L.md_cell_grid(run.p)
+    path_start = torch.empty((every, nc ** 3 + 1), dtype=torch.int32, device=run.dev)
     for n0, k, cp, cv in reversed(ckpts):
         # recompute r_{n0} .. r_{n0+k-1}, then the drift and kick adjoints of
         # steps n0+k-1 .. n0 (one library call per segment)
-        L.md_adjoint_segment(run.p, run.ws, cp, cv, n0, k, path, lam_r, lam_v, theta)
+        L.md_adjoint_segment(run.p, run.ws, cp, cv, n0, k, path, path_start, lam_r, lam_v, theta)
     L.md_check(run.ws)
     return lam_r, lam_v, theta
 

@@ -626,31 +626,51 @@ md_status md_adjoint_drift(const md_params* p, const float* lam_r4, float* lam_v
 }
 
 md_status md_adjoint_segment(const md_params* p, void* ws, size_t ws_bytes, const float* ckpt_pos4,
-                             const float* ckpt_vel4, int32_t first_step, int32_t nsteps, float* path4, float* lam_r4,
-                             float* lam_v4, double* theta, hipStream_t stream) {
-    md_status s = validate(p);
+                             const float* ckpt_vel4, int32_t first_step, int32_t nsteps, float* path4,
+                             int32_t* path_start, float* lam_r4, float* lam_v4, double* theta, hipStream_t stream) {
+    Layout L{};
+    md_status s = make_layout(p, L);
     if (s != MD_OK) return s;
+    if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
     if (p->shift_mode != 0) return fail(MD_ERR_ARG, "the adjoint needs shift_mode 0 (force shift)");
     if (nsteps < 1 || first_step < 0) return fail(MD_ERR_ARG, "need nsteps >= 1 and first_step >= 0");
-    if (!ckpt_pos4 || !ckpt_vel4 || !path4 || !lam_r4 || !lam_v4)
+    if (!ckpt_pos4 || !ckpt_vel4 || !path4 || !path_start || !lam_r4 || !lam_v4)
         return fail(MD_ERR_ARG, "segment arrays are NULL");
     if (!aligned16(ckpt_pos4) || !aligned16(ckpt_vel4) || !aligned16(path4) || !aligned16(lam_r4) ||
         !aligned16(lam_v4))
         return fail(MD_ERR_ARG, "segment arrays must be 16-byte aligned");
-    const size_t n4 = 4 * static_cast<size_t>(p->n);
+    char* b = static_cast<char*>(ws);
+    const size_t pos_bytes = 16 * static_cast<size_t>(p->n);
+    const size_t start_n = static_cast<size_t>(L.ncells) + 1;
     const float h = static_cast<float>(0.5 * p->dt / p->mass);
-    // recompute r_first .. r_{first + nsteps - 1} into path4[0 .. nsteps)
+    // Recompute the segment's states; keep each step's cell-sorted positions
+    // and cell offsets (the cell list the kick adjoint walks) instead of
+    // rebuilding cells from user-order positions on the way back.
+    auto keep = [&](int32_t j) -> md_status {
+        MD_TRY_HIP(hipMemcpyAsync(reinterpret_cast<char*>(path4) + j * pos_bytes, b + L.pos0, pos_bytes,
+                                  hipMemcpyDeviceToDevice, stream),
+                   "keep positions");
+        MD_TRY_HIP(hipMemcpyAsync(path_start + j * start_n, b + L.start, start_n * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, stream),
+                   "keep cell offsets");
+        return MD_OK;
+    };
     if ((s = md_build_cells(p, ws, ws_bytes, ckpt_pos4, ckpt_vel4, stream)) != MD_OK) return s;
     if ((s = md_forces(p, ws, ws_bytes, nullptr, stream)) != MD_OK) return s;
-    MD_TRY_HIP(hipMemcpyAsync(path4, ckpt_pos4, n4 * sizeof(float), hipMemcpyDeviceToDevice, stream), "copy");
+    if ((s = keep(0)) != MD_OK) return s;
     for (int32_t j = 1; j < nsteps; ++j) {
         if ((s = md_step(p, ws, ws_bytes, 1, 0, nullptr, stream)) != MD_OK) return s;
-        if ((s = md_get_state(p, ws, ws_bytes, path4 + j * n4, nullptr, stream)) != MD_OK) return s;
+        if ((s = keep(j)) != MD_OK) return s;
     }
     // from the last step of the segment back to its first
     for (int32_t j = nsteps - 1; j >= 0; --j) {
         if ((s = md_adjoint_drift(p, lam_r4, lam_v4, stream)) != MD_OK) return s;
-        if ((s = md_build_cells(p, ws, ws_bytes, path4 + j * n4, nullptr, stream)) != MD_OK) return s;
+        MD_TRY_HIP(hipMemcpyAsync(b + L.pos0, reinterpret_cast<char*>(path4) + j * pos_bytes, pos_bytes,
+                                  hipMemcpyDeviceToDevice, stream),
+                   "restore positions");
+        MD_TRY_HIP(hipMemcpyAsync(b + L.start, path_start + j * start_n, start_n * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, stream),
+                   "restore cell offsets");
         const float coef = first_step + j >= 1 ? 2.0f * h : h;
         if ((s = md_adjoint_kick(p, ws, ws_bytes, lam_v4, lam_r4, theta, coef, stream)) != MD_OK) return s;
     }
