@@ -527,6 +527,41 @@ __device__ __forceinline__ void walk_bits(int ns, uint32_t m, uint32_t n1, uint3
     } while (__any(left != 0u));
 }
 
+// The same walk taking two accepted candidates per iteration (the second may
+// come from the next word), in the same order: op sees the same sequence of
+// (offset, live) calls as from walk_bits, so sums are bitwise equal. The loop
+// overhead and the final masked iterations of the slowest lanes are paid
+// once per pair of candidates.
+template <class Op>
+__device__ __forceinline__ void walk_bits2(int ns, uint32_t m, uint32_t n1, uint32_t n2, uint32_t n3, Op& op) {
+    const uint32_t cstep = static_cast<uint32_t>(ns) * sizeof(float4);
+    const uint32_t wstep = 32u * cstep;
+    uint32_t wb = 0;
+    uint32_t left = __builtin_popcount(m) + __builtin_popcount(n1) + __builtin_popcount(n2) +
+                    __builtin_popcount(n3);
+    if (!__any(left != 0u)) return;
+    do {
+        uint32_t off[2];
+        bool live[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const bool next = (m == 0u);
+            m = next ? n1 : m;
+            n1 = next ? n2 : n1;
+            n2 = next ? n3 : n2;
+            n3 = next ? 0u : n3;
+            wb = next ? wb + wstep : wb;
+            live[u] = m != 0u;
+            const uint32_t k = live[u] ? __builtin_clz(m) : 0u;
+            m &= ~(0x80000000u >> k);
+            left -= live[u] ? 1u : 0u;
+            off[u] = live[u] ? wb + __umul24(k, cstep) : 0u;
+        }
+        op(off[0], live[0]);
+        op(off[1], live[1]);
+    } while (__any(left != 0u));
+}
+
 // Clear the screen bit of the home atom itself (tile index self_t) if it lies
 // in this lane's span: span candidates are first + g * ns for g < groups.
 __device__ __forceinline__ void clear_self(int self_t, int first, int ns, int groups, uint32_t (&wd)[kWords]) {
