@@ -269,15 +269,18 @@ md_status md_loss_grad(const md_params* p, void* ws, size_t ws_bytes, float k_co
  * on that system alone (same cell grid, LDS pass length and summation order),
  * so its results are bitwise those of a solo run.
  *
- * Shared parameters (epsilon, sigma, mass, rc_over_sigma, dt, cell_min,
- * shift_mode) come from p; p->n and p->box are ignored. Replica b owns atoms
+ * Shared parameters (epsilon, sigma, mass, rc_over_sigma, dt, shift_mode)
+ * come from p; p->n and p->box are ignored. The minimum cell side is the
+ * replica's own cell_min when that is nonzero, else p->cell_min; the grid
+ * rule is that of md_cell_grid. Replica b owns atoms
  * [A_b, A_b + n_b) of the concatenated float4 arrays, A_b = n_0 + ... +
  * n_(b-1); every replica needs box >= 2 r_c. The table is re-validated on
  * every call and must not change between calls on one workspace.
  */
 typedef struct md_replica {
-    int32_t n;  /* atoms of this replica, >= 1 */
-    float box;  /* its cubic periodic box side */
+    int32_t n;       /* atoms of this replica, >= 1 */
+    float box;       /* its cubic periodic box side */
+    float cell_min;  /* its minimum cell side (finite, >= 0); 0 takes p->cell_min */
 } md_replica;
 
 /* Workspace bytes for this batch (0 if invalid). Host only. */

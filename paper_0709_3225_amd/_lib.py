@@ -78,15 +78,17 @@ class MDParams(ctypes.Structure):
 
 
 class MDReplica(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int32), ("box", ctypes.c_float)]
+    _fields_ = [("n", ctypes.c_int32), ("box", ctypes.c_float), ("cell_min", ctypes.c_float)]
 
 
 def replica_table(reps):
-    """ctypes array of md_replica from (n, box) pairs."""
+    """ctypes array of md_replica from (n, box) or (n, box, cell_min) tuples
+    (cell_min 0: the batch's shared cell_min)."""
     arr = (MDReplica * len(reps))()
-    for i, (n, box) in enumerate(reps):
-        arr[i].n = int(n)
-        arr[i].box = float(box)
+    for i, r in enumerate(reps):
+        arr[i].n = int(r[0])
+        arr[i].box = float(r[1])
+        arr[i].cell_min = float(r[2]) if len(r) > 2 else 0.0
     return arr
 
 

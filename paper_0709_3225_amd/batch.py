@@ -19,8 +19,9 @@ from . import _lib as L
 class BatchedLJ:
     def __init__(self, replicas, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_over_sigma=2.5, dt=0.005, cell_min=0.0,
                  shift_mode=0, device="cuda"):
-        """replicas: sequence of (n, box)."""
-        self.replicas = [(int(n), float(b)) for n, b in replicas]
+        """replicas: sequence of (n, box) or (n, box, cell_min); a replica's
+        nonzero cell_min replaces the shared one (tune.tune_batch picks them)."""
+        self.replicas = [(int(r[0]), float(r[1]), float(r[2]) if len(r) > 2 else 0.0) for r in replicas]
         self.count = len(self.replicas)
         self.table = L.replica_table(self.replicas)
         self.params = L.make_params(1, 1.0, epsilon, sigma, mass, rc_over_sigma, dt, cell_min, shift_mode)
@@ -31,10 +32,10 @@ class BatchedLJ:
             raise L.MDError(L.MD_ERR_ARG, "invalid batch")
         self.device = torch.device(device)
         self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
-        self.n_total = sum(n for n, _ in self.replicas)
+        self.n_total = sum(r[0] for r in self.replicas)
         self.offsets = [0]
-        for n, _ in self.replicas:
-            self.offsets.append(self.offsets[-1] + n)
+        for r in self.replicas:
+            self.offsets.append(self.offsets[-1] + r[0])
 
     def _args(self):
         wp, wn = L._ws(self.ws)

@@ -134,12 +134,15 @@ __global__ void __launch_bounds__(kBlock) k_batch_integrate(SimArgs base, const 
 // the header (k_build_init has cleared the rest). One workgroup per replica.
 __global__ void __launch_bounds__(kBlock) k_batch_setup(SimArgs base, const Replica* __restrict__ reps,
                                                         int* __restrict__ atom_rep, int* __restrict__ cell_rep,
-                                                        int count) {
+                                                        int* __restrict__ class_cells, int count) {
     const int b = blockIdx.x;
     const Replica r = reps[b];
     if (b == 0 && threadIdx.x == 0) base.hdr[HDR_NC] = -count;  // marks a batch workspace
     for (int i = threadIdx.x; i < r.n; i += kBlock) atom_rep[r.abase + i] = b;
-    for (int c = threadIdx.x; c < r.ncells; c += kBlock) cell_rep[r.cbase + c] = b;
+    for (int c = threadIdx.x; c < r.ncells; c += kBlock) {
+        cell_rep[r.cbase + c] = b;
+        if (class_cells) class_cells[r.lbase + c] = r.cbase + c;
+    }
 }
 
 // Block scan: bstart[b] = atoms in the cells of blocks 0 .. b - 1 (16 cells
@@ -441,9 +444,10 @@ hipError_t launch_gather_user(const SimArgs& a, float4* pos_out, float4* vel_out
     return hipGetLastError();
 }
 
-hipError_t launch_batch_setup(const SimArgs& base, const Replica* reps, int* atom_rep, int* cell_rep, int count,
-                              hipStream_t st) {
-    hipLaunchKernelGGL(k_batch_setup, dim3(count), dim3(kBlock), 0, st, base, reps, atom_rep, cell_rep, count);
+hipError_t launch_batch_setup(const SimArgs& base, const Replica* reps, int* atom_rep, int* cell_rep,
+                              int* class_cells, int count, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_setup, dim3(count), dim3(kBlock), 0, st, base, reps, atom_rep, cell_rep, class_cells,
+                       count);
     return hipGetLastError();
 }
 

@@ -348,16 +348,18 @@ __global__ void __launch_bounds__(kWave) k_forces_list(SimArgs a) {
                                                                 reinterpret_cast<float*>(tile));
 }
 
-// Batched forces: one workgroup per cell of any replica (global cell index,
-// XCD-ordered); the replica's own geometry comes from its descriptor.
+// Batched forces: one workgroup per listed cell (global cell indices of the
+// replicas of one tile class, XCD-ordered); the replica's own geometry comes
+// from its descriptor.
 template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT>
 __global__ void __launch_bounds__(kWave)
-    k_batch_forces(SimArgs base, const Replica* __restrict__ reps, const int* __restrict__ cell_rep, int total_cells) {
+    k_batch_forces(SimArgs base, const Replica* __restrict__ reps, const int* __restrict__ cell_rep,
+                   const int* __restrict__ cells, int ncl) {
     if (base.hdr[HDR_ERROR] & DEV_ORDER) return;
-    extern __shared__ float4 tile[];  // max tile_cap over replicas + kTilePad entries
+    extern __shared__ float4 tile[];  // the class's largest tile_cap + kTilePad entries
     __shared__ Neighbourhood nb;
     float* red = reinterpret_cast<float*>(tile);  // slice reduction, as in k_forces
-    const int gc = xcd_block_order(blockIdx.x, total_cells);
+    const int gc = cells[xcd_block_order(blockIdx.x, ncl)];
     const SimArgs a = replica_view(base, reps[cell_rep[gc]]);
     force_cell<KICK, ENERGY, WRITE, DRIFT>(a, gc - a.cbase, tile, nb, red);
     if (WRITE && blockIdx.x == 0 && threadIdx.x == 0) base.hdr[HDR_STATE] = STATE_FORCES;
@@ -542,15 +544,15 @@ hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch_forces(const SimArgs& base_in, const Replica* reps, const int* cell_rep, int total_cells,
-                               int max_tile_cap, bool kick, bool energy, bool write_force, bool drift, int par,
+hipError_t launch_batch_forces(const SimArgs& base_in, const Replica* reps, const int* cell_rep, const int* cells,
+                               int ncl, int tile_cap, bool kick, bool energy, bool write_force, bool drift, int par,
                                hipStream_t st) {
     SimArgs base = base_in;
     base.par = par;
-    const dim3 g(total_cells), b(kWave);
-    const size_t lds = sizeof(float4) * static_cast<size_t>(max_tile_cap + kTilePad);
+    const dim3 g(ncl), b(kWave);
+    const size_t lds = sizeof(float4) * static_cast<size_t>(tile_cap + kTilePad);
 #define MD_FORCES(K, E, W, D) \
-    hipLaunchKernelGGL((k_batch_forces<K, E, W, D>), g, b, lds, st, base, reps, cell_rep, total_cells)
+    hipLaunchKernelGGL((k_batch_forces<K, E, W, D>), g, b, lds, st, base, reps, cell_rep, cells, ncl)
     if (kick && drift && !write_force) {
         if (energy) MD_FORCES(true, true, false, true);
         else MD_FORCES(true, false, false, true);

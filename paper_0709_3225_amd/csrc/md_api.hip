@@ -247,13 +247,32 @@ md_status rebuild(const SimArgs& a, int par, bool from_step, hipStream_t st) {
 
 // ---- batches of independent replicas -------------------------------------
 
+// The batched force pass runs one launch per tile class: replicas whose
+// neighbourhood tile (tile_capacity) falls into the same band share a launch
+// whose LDS fits the band's largest tile, so a few replicas with crowded
+// cells do not cut the number of resident waves for all the others (about 16
+// per CU with tiles of up to 512 atoms, 9 with 1,024). Band upper bounds:
+constexpr int kTileBands[] = {512, 640, 768, 1024, 2048};
+constexpr int kNumTileBands = sizeof(kTileBands) / sizeof(kTileBands[0]);
+
+struct TileClass {
+    int first = 0, ncells = 0, tile_cap = 0;  // range in the class cell list; largest tile_cap
+};
+
 struct BatchPlan {
     Layout L;                    // shared arrays; n = total atoms, ncells = total cells
-    int count = 0, max_tile = 0;
+    int count = 0;
     double max_mean = 0.0;  // largest mean cell occupancy of any replica
-    size_t reps = 0, atom_rep = 0, cell_rep = 0;
+    size_t reps = 0, atom_rep = 0, cell_rep = 0, class_cells = 0;
     std::vector<Replica> table;  // host copy of the replica table
+    TileClass classes[kNumTileBands];
 };
+
+int tile_band(int tile_cap) {
+    for (int k = 0; k < kNumTileBands; ++k)
+        if (tile_cap <= kTileBands[k]) return k;
+    return kNumTileBands - 1;  // tile_capacity never exceeds the last band
+}
 
 constexpr int32_t kMaxReplicas = 1 << 16;
 
@@ -270,6 +289,7 @@ md_status batch_plan(const md_params* p, const md_replica* reps, int32_t count, 
         md_params q = *p;
         q.n = reps[b].n;
         q.box = reps[b].box;
+        if (reps[b].cell_min != 0.f) q.cell_min = reps[b].cell_min;  // validated by make_layout
         Layout Lb{};
         const md_status s = make_layout(&q, Lb);
         if (s != MD_OK) {
@@ -288,12 +308,28 @@ md_status batch_plan(const md_params* p, const md_replica* reps, int32_t count, 
         r.s = Lb.s;
         r.inv_s = Lb.inv_s;
         r.screen2 = screen_bound(static_cast<double>(cutoff(&q)), Lb.s);
-        B.max_tile = std::max(B.max_tile, r.tile_cap);
         B.max_mean = std::max(B.max_mean, static_cast<double>(q.n) / Lb.ncells);
         ntot += q.n;
         ctot += Lb.ncells;
         if (ntot > kMaxAtoms) return fail(MD_ERR_ARG, "batch holds more than 2^27 atoms");
         if (ctot > (int64_t{1} << 30)) return fail(MD_ERR_ARG, "batch holds more than 2^30 cells");
+    }
+    // tile classes: each band's replicas in table order, bands one after another
+    for (const Replica& r : B.table) {
+        TileClass& t = B.classes[tile_band(r.tile_cap)];
+        t.ncells += r.ncells;
+        t.tile_cap = std::max(t.tile_cap, r.tile_cap);
+    }
+    int first = 0;
+    for (TileClass& t : B.classes) {
+        t.first = first;
+        first += t.ncells;
+    }
+    int fill[kNumTileBands] = {};
+    for (Replica& r : B.table) {
+        const int k = tile_band(r.tile_cap);
+        r.lbase = B.classes[k].first + fill[k];
+        fill[k] += r.ncells;
     }
     Layout& L = B.L;
     L.n = static_cast<int>(ntot);
@@ -311,6 +347,7 @@ md_status batch_plan(const md_params* p, const md_replica* reps, int32_t count, 
     B.reps = take(sizeof(Replica) * static_cast<size_t>(count));
     B.atom_rep = take(4 * n);
     B.cell_rep = take(4 * c);
+    B.class_cells = take(4 * c);
     L.pos0 = take(16 * n);
     L.vel0 = take(16 * n);
     L.pos1 = take(16 * n);
@@ -327,6 +364,7 @@ struct BatchArgs {
     const Replica* reps;
     int* atom_rep;
     int* cell_rep;
+    int* class_cells;
 };
 
 BatchArgs batch_args(const md_params* p, const BatchPlan& B, void* ws) {
@@ -339,7 +377,20 @@ BatchArgs batch_args(const md_params* p, const BatchPlan& B, void* ws) {
     ba.reps = reinterpret_cast<const Replica*>(b + B.reps);
     ba.atom_rep = reinterpret_cast<int*>(b + B.atom_rep);
     ba.cell_rep = reinterpret_cast<int*>(b + B.cell_rep);
+    ba.class_cells = reinterpret_cast<int*>(b + B.class_cells);
     return ba;
+}
+
+// The batched force pass: one launch per non-empty tile class.
+hipError_t batch_forces(const BatchPlan& B, const BatchArgs& ba, bool kick, bool energy, bool write_force,
+                        bool drift, int par, hipStream_t st) {
+    for (const TileClass& t : B.classes) {
+        if (t.ncells == 0) continue;
+        const hipError_t e = launch_batch_forces(ba.base, ba.reps, ba.cell_rep, ba.class_cells + t.first, t.ncells,
+                                                 t.tile_cap, kick, energy, write_force, drift, par, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 md_status batch_prepare(const md_params* p, const md_replica* reps, int32_t count, const void* ws, size_t ws_bytes,
@@ -359,9 +410,7 @@ md_status batch_steps(const BatchPlan& B, const BatchArgs& ba, int32_t nsteps, i
         if (k == 1) MD_TRY_HIP(launch_batch_integrate(ba.base, ba.reps, ba.atom_rep, st), "batch integrate");
         md_status s = rebuild(ba.base, (k - 1) & 1, true, st);
         if (s != MD_OK) return s;
-        MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, true, energy, last,
-                                       !last, k & 1, st),
-                   "batch forces");
+        MD_TRY_HIP(batch_forces(B, ba, true, energy, last, !last, k & 1, st), "batch forces");
         if (energy)
             MD_TRY_HIP(launch_batch_energy_final(ba.base, ba.reps, B.count,
                                                  thermo + 3 * static_cast<size_t>(B.count) * (k / thermo_every - 1), st),
@@ -714,7 +763,8 @@ md_status md_batch_build(const md_params* p, const md_replica* reps, int32_t cou
                "replica table upload");
     MD_TRY_HIP(hipStreamSynchronize(stream), "replica table upload");
     MD_TRY_HIP(launch_build_init(ba.base, stream), "batch init");
-    MD_TRY_HIP(launch_batch_setup(ba.base, ba.reps, ba.atom_rep, ba.cell_rep, B.count, stream), "batch setup");
+    MD_TRY_HIP(launch_batch_setup(ba.base, ba.reps, ba.atom_rep, ba.cell_rep, ba.class_cells, B.count, stream),
+               "batch setup");
     MD_TRY_HIP(launch_batch_load(ba.base, ba.reps, ba.atom_rep, reinterpret_cast<const float4*>(pos4),
                                  reinterpret_cast<const float4*>(vel4), stream),
                "batch load");
@@ -730,7 +780,7 @@ md_status md_batch_forces(const md_params* p, const md_replica* reps, int32_t co
     if (s != MD_OK) return s;
     if (force4 && !aligned16(force4)) return fail(MD_ERR_ARG, "force array must be 16-byte aligned");
     const BatchArgs ba = batch_args(p, B, ws);
-    MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, false, false, true, false, 0, stream),
+    MD_TRY_HIP(batch_forces(B, ba, false, false, true, false, 0, stream),
                "batch forces");
     if (force4) MD_TRY_HIP(launch_gather_user(ba.base, nullptr, nullptr, reinterpret_cast<float4*>(force4), stream), "gather");
     return MD_OK;
@@ -754,7 +804,7 @@ md_status md_batch_energy_virial(const md_params* p, const md_replica* reps, int
     if (s != MD_OK) return s;
     if (!out) return fail(MD_ERR_ARG, "output is NULL");
     const BatchArgs ba = batch_args(p, B, ws);
-    MD_TRY_HIP(launch_batch_forces(ba.base, ba.reps, ba.cell_rep, B.L.ncells, B.max_tile, false, true, false, false, 0, stream),
+    MD_TRY_HIP(batch_forces(B, ba, false, true, false, false, 0, stream),
                "batch energy pass");
     MD_TRY_HIP(launch_batch_energy_final(ba.base, ba.reps, B.count, out, stream), "batch energy");
     return MD_OK;

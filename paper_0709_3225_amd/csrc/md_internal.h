@@ -105,6 +105,7 @@ struct SimArgs {
 struct Replica {
     int n, abase, nc, ncells, cbase, tile_cap;
     float box, s, inv_s, screen2;
+    int lbase;  // first entry of the replica's cells in the tile-class cell list
 };
 
 // Workspace layout (byte offsets, each 256-byte aligned).
@@ -147,13 +148,17 @@ hipError_t launch_adjoint_drift(int n, float dt, const float4* lam_r, float4* la
 
 // Batched replicas: base = the batch's arrays and shared constants (n and
 // ncells are the batch totals), reps = device replica table.
-hipError_t launch_batch_setup(const SimArgs& base, const Replica* reps, int* atom_rep, int* cell_rep, int count,
-                              hipStream_t st);
+// class_cells (nullable) receives the global cell indices grouped by tile
+// class: replica b's cells at [lbase_b, lbase_b + ncells_b).
+hipError_t launch_batch_setup(const SimArgs& base, const Replica* reps, int* atom_rep, int* cell_rep,
+                              int* class_cells, int count, hipStream_t st);
 hipError_t launch_batch_load(const SimArgs& base, const Replica* reps, const int* atom_rep, const float4* pos_in,
                              const float4* vel_in, hipStream_t st);
 hipError_t launch_batch_integrate(const SimArgs& base, const Replica* reps, const int* atom_rep, hipStream_t st);
-hipError_t launch_batch_forces(const SimArgs& base, const Replica* reps, const int* cell_rep, int total_cells,
-                               int max_tile_cap, bool kick, bool energy, bool write_force, bool drift, int par,
+// One launch over the ncl global cells listed at cells (a tile class), with
+// LDS for tile_cap staged atoms (at least every listed replica's tile_cap).
+hipError_t launch_batch_forces(const SimArgs& base, const Replica* reps, const int* cell_rep, const int* cells,
+                               int ncl, int tile_cap, bool kick, bool energy, bool write_force, bool drift, int par,
                                hipStream_t st);
 hipError_t launch_batch_energy_final(const SimArgs& base, const Replica* reps, int count, double* out, hipStream_t st);
 

@@ -1,0 +1,122 @@
+"""Cell-side autotuner for batches of replicas.
+
+The only geometric choice the method leaves open is the cell side: section 3
+asks for cells of side at least r_c, and section 3.2 takes the finest such
+grid, n_c = int(L / r_c). Coarser grids stage more candidates per home cell
+but fill more lanes of the one-wavefront-per-cell kernel; which wins depends
+on the occupancy of the cells, so it is measured, not modelled.
+
+Replicas are grouped into size buckets (their default grid and its mean
+occupancy). For each bucket the tuner times batched steps of a probe made of
+copies of one member replica's own state, once per candidate grid (the
+default and up to ``extra`` coarser ones), and keeps a coarser grid only if it
+is faster per atom-step by at least ``min_gain``. The result is a per-replica
+``cell_min`` for the replica table (0 keeps the default grid).
+
+This module is host logic: every step it times runs in the library's kernels
+through the C-ABI.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import torch
+
+from . import _lib as L
+from .batch import BatchedLJ
+
+
+def grid_options(n: int, box: float, *, rc_over_sigma: float = 2.5, sigma: float = 1.0, extra: int = 1,
+                 max_occupancy: float = 48.0):
+    """Candidate cell grids of one replica as (cells_per_dim, cell_min): the
+    default grid of md_cell_grid (cell_min 0) and up to ``extra`` coarser ones
+    with at least 2 cells per dimension and at most ``max_occupancy`` atoms
+    per cell on average. A coarser grid n_c is selected by
+    cell_min = L / (n_c + 1/2), and md_cell_grid confirms it."""
+    base = dict(rc_over_sigma=rc_over_sigma, sigma=sigma)
+    nc0, _ = L.md_cell_grid(L.make_params(n, box, **base))
+    out = [(nc0, 0.0)]
+    for k in range(1, extra + 1):
+        nc = nc0 - k
+        if nc < 2 or n / nc ** 3 > max_occupancy:
+            break
+        cm = float(box) / (nc + 0.5)
+        got, _ = L.md_cell_grid(L.make_params(n, box, cell_min=cm, **base))
+        if got == nc:
+            out.append((nc, cm))
+    return out
+
+
+def bucket_key(n: int, nc0: int):
+    """Replica-size bucket: the default grid and its mean occupancy, rounded."""
+    return nc0, int(round(n / nc0 ** 3))
+
+
+def _time_probe(n, box, cell_min, p4, v4, copies, steps, warmup, shared, stream):
+    table = [(n, box, cell_min)] * copies
+    b = BatchedLJ(table, **shared)
+    pos = p4.repeat(copies, 1).contiguous()
+    vel = v4.repeat(copies, 1).contiguous()
+    with torch.cuda.stream(stream):
+        b.load(pos, vel)
+        b.step(warmup)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.step(steps)
+        e1.record(stream)
+    stream.synchronize()
+    b.check()
+    return e0.elapsed_time(e1) / 1e3 / (steps * n * copies)  # seconds per atom-step
+
+
+def tune_batch(replicas, pos4: torch.Tensor, vel4: torch.Tensor, *, epsilon=1.0, sigma=1.0, mass=1.0,
+               rc_over_sigma=2.5, dt=0.005, shift_mode=0, extra=1, min_atoms=131072, steps=8, warmup=2,
+               min_gain=0.03):
+    """Pick a cell grid per replica.
+
+    replicas: sequence of (n, box); pos4/vel4: the batch's concatenated float4
+    state on the GPU (each bucket's probe copies one member's own atoms).
+    Returns (cell_mins, report): cell_mins[b] goes into replica b's table
+    entry; report lists, per bucket, the grids tried with their measured
+    seconds per atom-step and the choice."""
+    shared = dict(epsilon=epsilon, sigma=sigma, mass=mass, rc_over_sigma=rc_over_sigma, dt=dt,
+                  shift_mode=shift_mode)
+    reps = [(int(n), float(box)) for n, box, *_ in replicas]
+    offsets = [0]
+    for n, _ in reps:
+        offsets.append(offsets[-1] + n)
+    options = [grid_options(n, box, rc_over_sigma=rc_over_sigma, sigma=sigma, extra=extra) for n, box in reps]
+    buckets = {}
+    for i, (n, _) in enumerate(reps):
+        buckets.setdefault(bucket_key(n, options[i][0][0]), []).append(i)
+    stream = torch.cuda.Stream()
+    t_start = time.perf_counter()
+    cell_mins = [0.0] * len(reps)
+    report = []
+    for key, members in sorted(buckets.items()):
+        i = members[0]
+        n, box = reps[i]
+        p4 = pos4[offsets[i]:offsets[i + 1]]
+        v4 = vel4[offsets[i]:offsets[i + 1]]
+        copies = max(1, math.ceil(min_atoms / n))
+        tried = []
+        for nc, cm in options[i]:
+            t = _time_probe(n, box, cm, p4, v4, copies, steps, warmup, shared, stream)
+            tried.append({"cells_per_dim": nc, "cell_min": cm, "s_per_atom_step": t})
+        best = tried[0]
+        for cand in tried[1:]:
+            if cand["s_per_atom_step"] < best["s_per_atom_step"] * (1.0 - min_gain):
+                best = cand
+        for j in members:
+            # members share the default grid; the chosen coarser grid is
+            # re-derived for each (same n_c, its own box)
+            if best["cell_min"] == 0.0:
+                continue
+            for nc, cm in options[j]:
+                if nc == best["cells_per_dim"]:
+                    cell_mins[j] = cm
+        report.append({"bucket": {"cells_per_dim": key[0], "atoms_per_cell": key[1]}, "replicas": len(members),
+                       "tried": tried, "chosen_cells_per_dim": best["cells_per_dim"]})
+    return cell_mins, {"buckets": report, "seconds": time.perf_counter() - t_start}

@@ -142,3 +142,43 @@ def test_batch_validation_on_host():
     assert lib.md_batch_graph_create(ctypes.byref(p), ok, 2, fake, need, 10, 0, None, None, ctypes.byref(g)) \
         == _lib.MD_ERR_ARG
     assert lib.md_graph_destroy(None) == 0
+
+
+def test_batch_replica_cell_min_on_host():
+    """A replica's own cell_min replaces the shared one (0 keeps it); invalid
+    values are refused with the replica's index, before any device work."""
+    import ctypes
+    import math
+
+    lib = _lib.lib()
+    p = md.make_params(1, 1.0)
+    base = _lib.replica_table([(4000, 17.878), (4000, 17.878)])
+    coarse = _lib.replica_table([(4000, 17.878), (4000, 17.878, 17.878 / 6.5)])
+    assert lib.md_batch_workspace_bytes(ctypes.byref(p), coarse, 2) > 0
+    assert lib.md_batch_workspace_bytes(ctypes.byref(p), coarse, 2) != \
+        lib.md_batch_workspace_bytes(ctypes.byref(p), base, 2)  # fewer cells, larger buckets
+    for badval in (-1.0, math.inf, math.nan):
+        bad = _lib.replica_table([(4000, 17.878), (4000, 17.878, badval)])
+        assert lib.md_batch_workspace_bytes(ctypes.byref(p), bad, 2) == 0
+        assert lib.md_batch_build(ctypes.byref(p), bad, 2, None, 0, None, None, None) == _lib.MD_ERR_ARG
+        assert b"replica 1" in lib.md_last_error()
+        assert b"cell_min" in lib.md_last_error()
+
+
+def test_grid_options_and_buckets():
+    """The tuner's candidate grids: the default grid first, then coarser grids
+    that md_cell_grid confirms, never below 2 cells per dimension or above the
+    occupancy limit; members of one bucket share grid and occupancy."""
+    from paper_0709_3225_amd.tune import bucket_key, grid_options
+
+    L = 17.878  # N = 4000 at rho = 0.70: 7 cells of 2.554
+    opts = grid_options(4000, L, extra=2)
+    assert opts[0] == (7, 0.0)
+    assert [nc for nc, _ in opts] == [7, 6, 5]
+    for nc, cm in opts[1:]:
+        got, side = md.md_cell_grid(md.make_params(4000, L, cell_min=cm))
+        assert got == nc and side >= cm and side >= 2.5
+    assert grid_options(500, 8.939, extra=2) == [(3, 0.0)]  # 2 cells would hold 62 atoms each
+    assert grid_options(4000, L, extra=2, max_occupancy=20.0) == [(7, 0.0), (6, L / 6.5)]
+    assert bucket_key(4000, 7) == (7, 12)
+    assert bucket_key(4000, 7) == bucket_key(4100, 7)

@@ -177,3 +177,65 @@ def test_batch_validation():
     b.load(_cuda(pos4), _cuda(vel4))
     with pytest.raises(MDError):
         b.make_graph(5, stream=torch.cuda.default_stream())  # the null stream cannot be captured
+
+
+def test_replica_cell_grids_bitwise_equal_solo_runs():
+    """Replicas on their own cell grids (default and coarser, so that their
+    neighbourhood tiles fall into different LDS classes) are bitwise equal to
+    solo runs with the same cell_min."""
+    torch = _torch()
+    from paper_0709_3225_amd import BatchedLJ, LJSystem, grid_options
+
+    ws, table, states = _small_batch()
+    grids = []
+    for i, (n, box) in enumerate(table):
+        opts = grid_options(n, box, extra=1, max_occupancy=64.0)
+        grids.append(opts[-1][1] if i % 2 == 0 else 0.0)  # coarser grid on every other replica
+    table3 = [(n, box, cm) for (n, box), cm in zip(table, grids)]
+    _say(f"batch with per-replica cell grids {grids}")
+    pos = np.concatenate([s[0] for s in states])
+    vel = np.concatenate([s[1] for s in states])
+    b = BatchedLJ(table3)
+    b.load(_cuda(pos), _cuda(vel))
+    th = b.step(10, thermo_every=5)
+    bp, bv = b.state()
+    f = torch.empty((b.n_total, 4), dtype=torch.float32, device="cuda")
+    b.forces(f)
+    b.check()
+    for i, ((n, box, cm), (p4, v4, _)) in enumerate(zip(table3, states)):
+        s = LJSystem(n, box, cell_min=cm)
+        s.load(_cuda(p4), _cuda(v4))
+        sth = s.step(10, thermo_every=5)
+        sp, sv = s.state()
+        sf = s.forces()
+        s.check()
+        lo, hi = b.offsets[i], b.offsets[i + 1]
+        assert torch.equal(bp[lo:hi], sp), i
+        assert torch.equal(bv[lo:hi], sv), i
+        assert torch.equal(f[lo:hi], sf), i
+        assert torch.equal(th[:, i, :], sth), i
+
+
+def test_tuned_batch_matches_oracle(orc):
+    """tune_batch returns one valid cell_min per replica (0 or a coarser grid
+    of that replica), and the tuned batch still matches the oracle."""
+    torch = _torch()
+    from paper_0709_3225_amd import BatchedLJ, LJSystem, grid_options, tune_batch
+
+    ws, table, pos, vel = _replicas(24, max_fcc=10)
+    _say(f"tune a 24-replica batch, n_total={len(pos)}")
+    cms, report = tune_batch(table, _cuda(pos), _cuda(vel), min_atoms=16384, steps=3, warmup=1)
+    assert len(cms) == len(table)
+    for (n, box), cm in zip(table, cms):
+        assert cm in [c for _, c in grid_options(n, box)]
+    assert sum(r["replicas"] for r in report["buckets"]) == len(table)
+    b = BatchedLJ([(n, box, cm) for (n, box), cm in zip(table, cms)])
+    b.load(_cuda(pos), _cuda(vel))
+    f = torch.empty((b.n_total, 4), dtype=torch.float32, device="cuda")
+    b.forces(f)
+    b.check()
+    f = f.cpu().numpy()[:, :3]
+    for i in (0, 7, 19):
+        lo, hi = b.offsets[i], b.offsets[i + 1]
+        fo, _, _ = orc.forces(orc.params(table[i][1]), pos[lo:hi])
+        assert np.linalg.norm(f[lo:hi] - fo) <= 1e-5 * np.linalg.norm(fo), i
