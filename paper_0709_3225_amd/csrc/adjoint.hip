@@ -276,6 +276,33 @@ __global__ void __launch_bounds__(256) k_gather_vec(SimArgs a, const float4* __r
     a.vel1[k] = (id >= 0 && id < a.n) ? w_user[id] : make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// Drift adjoint fused with the gather of the kick adjoint that follows it:
+// for sorted slot k (atom id = the slot's user index) lam_v[id] += dt
+// lam_r[id], as k_adjoint_drift computes it, and the new lam_v[id] goes to
+// the staging velocity array. Each id is one slot's, so no two lanes touch
+// the same atom.
+__global__ void __launch_bounds__(256) k_drift_gather(SimArgs a, float dt, const float4* __restrict__ lam_r,
+                                                      float4* __restrict__ lam_v) {
+    if (!state_ok(a, false)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&a.hdr[HDR_ERROR], DEV_ORDER);
+        return;
+    }
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= a.n) return;
+    const int id = __float_as_int(a.pos0[k].w);
+    if (id < 0 || id >= a.n) {
+        a.vel1[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        return;
+    }
+    const float4 r = lam_r[id];
+    float4 v = lam_v[id];
+    v.x = fmaf(dt, r.x, v.x);
+    v.y = fmaf(dt, r.y, v.y);
+    v.z = fmaf(dt, r.z, v.z);
+    lam_v[id] = v;
+    a.vel1[k] = v;
+}
+
 // Adjoint of the drift r += dt v: lam_v += dt lam_r (user order).
 __global__ void __launch_bounds__(256) k_adjoint_drift(int n, float dt, const float4* __restrict__ lam_r,
                                                        float4* __restrict__ lam_v) {
@@ -294,6 +321,17 @@ __global__ void __launch_bounds__(256) k_adjoint_drift(int n, float dt, const fl
 hipError_t launch_adjoint_kick(const SimArgs& a, const float4* w_user, float4* lam_r, double* theta, float coef,
                                hipStream_t st) {
     hipLaunchKernelGGL(k_gather_vec, dim3((a.n + 255) / 256), dim3(256), 0, st, a, w_user);
+    const size_t lds = 2 * sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
+    hipLaunchKernelGGL((k_pair_pass<OP_ADJ>), dim3(a.ncells), dim3(kWave), lds, st, a,
+                       static_cast<const float4*>(a.vel1), lam_r, static_cast<float4*>(nullptr), coef, 0.f);
+    if (theta) hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(kRedBlock), 0, st, a, theta, static_cast<double>(coef));
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_drift_kick(const SimArgs& a, float dt, float4* lam_r, float4* lam_v, double* theta,
+                                     float coef, hipStream_t st) {
+    hipLaunchKernelGGL(k_drift_gather, dim3((a.n + 255) / 256), dim3(256), 0, st, a, dt,
+                       static_cast<const float4*>(lam_r), lam_v);
     const size_t lds = 2 * sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
     hipLaunchKernelGGL((k_pair_pass<OP_ADJ>), dim3(a.ncells), dim3(kWave), lds, st, a,
                        static_cast<const float4*>(a.vel1), lam_r, static_cast<float4*>(nullptr), coef, 0.f);

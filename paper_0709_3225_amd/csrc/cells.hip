@@ -43,6 +43,10 @@ __global__ void __launch_bounds__(kBlock) k_build_init(SimArgs a) {
     for (int b = t; b < 2 * a.nbstride; b += stride) a.bcounts[b] = 0;
 }
 
+__global__ void k_set_state(SimArgs a, int state) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.hdr[HDR_STATE] = state;
+}
+
 // Clear the counters of parity par (overflow count, block histogram).
 __global__ void __launch_bounds__(kBlock) k_zero_blocks(SimArgs a, int par) {
     const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -428,6 +432,11 @@ hipError_t launch_block_scan(const SimArgs& a, bool from_step, hipStream_t st) {
 
 hipError_t launch_cell_order(const SimArgs& a, int par, bool from_step, hipStream_t st) {
     hipLaunchKernelGGL(k_cell_order, dim3(a.nblocks), dim3(kOrderBlock), 0, st, with_par(a, par), from_step);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_state(const SimArgs& a, int state, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_state, dim3(1), dim3(kWave), 0, st, a, state);
     return hipGetLastError();
 }
 

@@ -688,41 +688,49 @@ md_status md_adjoint_segment(const md_params* p, void* ws, size_t ws_bytes, cons
     if (!aligned16(ckpt_pos4) || !aligned16(ckpt_vel4) || !aligned16(path4) || !aligned16(lam_r4) ||
         !aligned16(lam_v4))
         return fail(MD_ERR_ARG, "segment arrays must be 16-byte aligned");
-    char* b = static_cast<char*>(ws);
-    const size_t pos_bytes = 16 * static_cast<size_t>(p->n);
     const size_t start_n = static_cast<size_t>(L.ncells) + 1;
     const float h = static_cast<float>(0.5 * p->dt / p->mass);
-    // Recompute the segment's states; keep each step's cell-sorted positions
-    // and cell offsets (the cell list the kick adjoint walks) instead of
-    // rebuilding cells from user-order positions on the way back.
-    auto keep = [&](int32_t j) -> md_status {
-        MD_TRY_HIP(hipMemcpyAsync(reinterpret_cast<char*>(path4) + j * pos_bytes, b + L.pos0, pos_bytes,
-                                  hipMemcpyDeviceToDevice, stream),
-                   "keep positions");
-        MD_TRY_HIP(hipMemcpyAsync(path_start + j * start_n, b + L.start, start_n * sizeof(int32_t),
-                                  hipMemcpyDeviceToDevice, stream),
-                   "keep cell offsets");
-        return MD_OK;
+    // State j of the segment is cell-sorted straight into path slice j: the
+    // rebuild that produces it writes its sorted positions and cell offsets
+    // there, the force pass and the kick adjoint at r_j read them from there,
+    // so nothing is copied.
+    const SimArgs a = make_args(p, L, ws);
+    auto at = [&](int32_t j) {
+        SimArgs x = a;
+        x.pos0 = reinterpret_cast<float4*>(path4) + static_cast<size_t>(j) * static_cast<size_t>(p->n);
+        x.start = path_start + static_cast<size_t>(j) * start_n;
+        return x;
     };
-    if ((s = md_build_cells(p, ws, ws_bytes, ckpt_pos4, ckpt_vel4, stream)) != MD_OK) return s;
-    if ((s = md_forces(p, ws, ws_bytes, nullptr, stream)) != MD_OK) return s;
-    if ((s = keep(0)) != MD_OK) return s;
-    for (int32_t j = 1; j < nsteps; ++j) {
-        if ((s = md_step(p, ws, ws_bytes, 1, 0, nullptr, stream)) != MD_OK) return s;
-        if ((s = keep(j)) != MD_OK) return s;
+    // Recompute: the checkpoint's cells (as md_build_cells), then the steps in
+    // md_step's fused order (bitwise the states md_step produces). The last
+    // state needs no forces: only its positions are used on the way back.
+    const SimArgs a0 = at(0);
+    MD_TRY_HIP(launch_build_init(a0, stream), "build init");
+    MD_TRY_HIP(launch_load(a0, reinterpret_cast<const float4*>(ckpt_pos4), reinterpret_cast<const float4*>(ckpt_vel4),
+                           stream),
+               "load");
+    if ((s = rebuild(a0, 0, false, stream)) != MD_OK) return s;
+    MD_TRY_HIP(launch_zero_blocks(a0, 0, stream), "counter clear");
+    if (nsteps > 1) {
+        MD_TRY_HIP(launch_forces(a0, false, false, true, false, false, 0, stream), "forces");
+        MD_TRY_HIP(launch_integrate(a0, stream), "integrate");
+        for (int32_t k = 1; k < nsteps; ++k) {
+            const SimArgs ak = at(k);
+            if ((s = rebuild(ak, (k - 1) & 1, true, stream)) != MD_OK) return s;
+            if (k + 1 < nsteps) MD_TRY_HIP(launch_forces(ak, true, false, false, true, true, k & 1, stream), "forces");
+        }
+        MD_TRY_HIP(launch_zero_blocks(a, (nsteps - 2) & 1, stream), "counter clear");
     }
-    // from the last step of the segment back to its first
+    // from the last step of the segment back to its first: drift adjoint, then
+    // the kick adjoint on state j's kept cell list
     for (int32_t j = nsteps - 1; j >= 0; --j) {
-        if ((s = md_adjoint_drift(p, lam_r4, lam_v4, stream)) != MD_OK) return s;
-        MD_TRY_HIP(hipMemcpyAsync(b + L.pos0, reinterpret_cast<char*>(path4) + j * pos_bytes, pos_bytes,
-                                  hipMemcpyDeviceToDevice, stream),
-                   "restore positions");
-        MD_TRY_HIP(hipMemcpyAsync(b + L.start, path_start + j * start_n, start_n * sizeof(int32_t),
-                                  hipMemcpyDeviceToDevice, stream),
-                   "restore cell offsets");
         const float coef = first_step + j >= 1 ? 2.0f * h : h;
-        if ((s = md_adjoint_kick(p, ws, ws_bytes, lam_v4, lam_r4, theta, coef, stream)) != MD_OK) return s;
+        MD_TRY_HIP(launch_adjoint_drift_kick(at(j), p->dt, reinterpret_cast<float4*>(lam_r4),
+                                             reinterpret_cast<float4*>(lam_v4), theta, coef, stream),
+                   "adjoint drift and kick");
     }
+    // the workspace's own sorted arrays were not written: it holds no state now
+    MD_TRY_HIP(launch_set_state(a, STATE_BUILDING, stream), "state reset");
     return MD_OK;
 }
 

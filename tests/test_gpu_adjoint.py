@@ -196,3 +196,57 @@ def test_autograd_function_matches_direct_call():
     assert float(loss) == l2
     assert torch.equal(x.grad, gr) and torch.equal(v.grad, gv)
     assert float(e.grad) == ge and float(sg.grad) == gs
+
+
+@pytest.mark.parametrize("first_step", [0, 3])
+def test_segment_equals_composed_calls(first_step):
+    """md_adjoint_segment is bitwise the composition of the public calls it
+    stands for: the states by md_build_cells + md_forces + md_step(1), and per
+    step (last to first) md_adjoint_drift, then md_adjoint_kick on cells built
+    from that state. Afterwards the workspace holds no built state."""
+    torch = _torch()
+    from paper_0709_3225_amd import _lib as L, LJSystem, MDError
+
+    w = ljsynth.WORKLOADS["lj4k"]
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05)
+    n, k = len(pos4), 6
+    _say(f"segment vs composed calls n={n} steps={k} first_step={first_step}")
+    s = LJSystem(n, box, dt=w.dt)
+    h = 0.5 * w.dt
+    rng = np.random.default_rng(7)
+    lam_r0 = _dev(rng.standard_normal((n, 4)))
+    lam_v0 = _dev(rng.standard_normal((n, 4)))
+    cp, cv = _dev(pos4), _dev(vel4)
+    # composed
+    states = []
+    L.md_build_cells(s.params, s.ws, cp, cv)
+    L.md_forces(s.params, s.ws)
+    for j in range(k):
+        if j > 0:
+            L.md_step(s.params, s.ws, 1)
+        p_j = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+        L.md_get_state(s.params, s.ws, p_j, None)
+        states.append(p_j)
+    lr, lv = lam_r0.clone(), lam_v0.clone()
+    th = torch.zeros(2, dtype=torch.float64, device="cuda")
+    for j in range(k - 1, -1, -1):
+        L.md_adjoint_drift(s.params, lr, lv)
+        L.md_build_cells(s.params, s.ws, states[j], None)
+        L.md_adjoint_kick(s.params, s.ws, lv, lr, th, 2 * h if first_step + j >= 1 else h)
+    s.check()
+    # one segment call
+    nc, _ = L.md_cell_grid(s.params)
+    path = torch.empty((k, n, 4), dtype=torch.float32, device="cuda")
+    path_start = torch.empty((k, nc ** 3 + 1), dtype=torch.int32, device="cuda")
+    sr, sv = lam_r0.clone(), lam_v0.clone()
+    st = torch.zeros(2, dtype=torch.float64, device="cuda")
+    L.md_adjoint_segment(s.params, s.ws, cp, cv, first_step, k, path, path_start, sr, sv, st)
+    s.check()
+    assert torch.equal(sr, lr) and torch.equal(sv, lv) and torch.equal(st, th)
+    # the kept state j is the composed run's state j, cell-sorted
+    for j in range(k):
+        ids = path[j][:, 3].view(torch.int32).long()
+        assert torch.equal(path[j][:, :3], states[j][ids, :3]), j
+    L.md_forces(s.params, s.ws)
+    with pytest.raises(MDError):
+        s.check()
