@@ -184,9 +184,10 @@ def _widened_point(torch, w, cell_min, nsteps, warm):
 def density_leg(torch, nsteps=100, warm=20):
     """LJ (r_c = 2.5 sigma) at N = 256,000 along the density axis of the
     paper's cell-list measurements (section 4): md_step atom-steps/s with the
-    paper's cells (side >= r_c) and with cells sized for about 14 atoms."""
+    paper's cells (side >= r_c), with cells sized for about 14 atoms, and with
+    the grid the autotuner picks by measurement."""
     import ljsynth
-    from paper_0709_3225_amd import occupancy_cell_min
+    from paper_0709_3225_amd import occupancy_cell_min, tune_cell_min
 
     points = []
     for rho in ljsynth.DENSITY_SWEEP:
@@ -196,6 +197,12 @@ def density_leg(torch, nsteps=100, warm=20):
             pt = _widened_point(torch, w, cm, nsteps, warm)
             pt.update({"rho": rho, "cells": cells})
             points.append(pt)
+        pos4, vel4, _ = ljsynth.make_state(w)
+        cm, rep = tune_cell_min(w.n, box, torch.from_numpy(pos4).cuda(), torch.from_numpy(vel4).cuda(),
+                                rc_over_sigma=w.rc_over_sigma, shift_mode=w.shift_mode, dt=w.dt)
+        pt = _widened_point(torch, w, cm, nsteps, warm)
+        pt.update({"rho": rho, "cells": "tuned", "tune_seconds": round(rep["seconds"], 3)})
+        points.append(pt)
     return {"workload": "LJ N=256000 (40^3 FCC start), T*=0.722, rc=2.5 sigma force-shifted, dt=0.005, "
                         f"{nsteps} steps after {warm}, rho in {list(ljsynth.DENSITY_SWEEP)}",
             "unit": "atom-steps/s", "points": points}

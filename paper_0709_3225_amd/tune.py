@@ -9,8 +9,9 @@ on the occupancy of the cells, so it is measured, not modelled.
 Replicas are grouped into size buckets (their default grid and its mean
 occupancy). For each bucket the tuner times batched steps of a probe made of
 copies of one member replica's own state, once per candidate grid (the
-default and up to ``extra`` coarser ones), and keeps a coarser grid only if it
-is faster per atom-step by at least ``min_gain``. The result is a per-replica
+default, up to ``extra`` coarser ones, and the grid sized for about 14 atoms
+per cell), and keeps a coarser grid only if it is faster per atom-step by at
+least ``min_gain``. The result is a per-replica
 ``cell_min`` for the replica table (0 keeps the default grid).
 
 This module is host logic: every step it times runs in the library's kernels
@@ -28,19 +29,26 @@ from .batch import BatchedLJ
 
 
 def grid_options(n: int, box: float, *, rc_over_sigma: float = 2.5, sigma: float = 1.0, extra: int = 1,
-                 max_occupancy: float = 48.0):
+                 max_occupancy: float = 48.0, target: float = 14.0):
     """Candidate cell grids of one replica as (cells_per_dim, cell_min): the
-    default grid of md_cell_grid (cell_min 0) and up to ``extra`` coarser ones
-    with at least 2 cells per dimension and at most ``max_occupancy`` atoms
-    per cell on average. A coarser grid n_c is selected by
-    cell_min = L / (n_c + 1/2), and md_cell_grid confirms it."""
+    default grid of md_cell_grid (cell_min 0), up to ``extra`` coarser ones,
+    and the grid whose cells hold about ``target`` atoms (sparse systems,
+    where the default cells hold one or two), each with at least 2 cells per
+    dimension and at most ``max_occupancy`` atoms per cell on average. A
+    coarser grid n_c is selected by cell_min = L / (n_c + 1/2), and
+    md_cell_grid confirms it."""
+    from .system import occupancy_cell_min
+
     base = dict(rc_over_sigma=rc_over_sigma, sigma=sigma)
     nc0, _ = L.md_cell_grid(L.make_params(n, box, **base))
+    wanted = [nc0 - k for k in range(1, extra + 1)]
+    nc_occ, _ = L.md_cell_grid(L.make_params(n, box, cell_min=occupancy_cell_min(n, box, rc_over_sigma * sigma,
+                                                                                   target), **base))
+    wanted.append(nc_occ)
     out = [(nc0, 0.0)]
-    for k in range(1, extra + 1):
-        nc = nc0 - k
-        if nc < 2 or n / nc ** 3 > max_occupancy:
-            break
+    for nc in wanted:
+        if nc >= nc0 or nc < 2 or n / nc ** 3 > max_occupancy or any(nc == o for o, _ in out):
+            continue
         cm = float(box) / (nc + 0.5)
         got, _ = L.md_cell_grid(L.make_params(n, box, cell_min=cm, **base))
         if got == nc:
@@ -53,27 +61,30 @@ def bucket_key(n: int, nc0: int):
     return nc0, int(round(n / nc0 ** 3))
 
 
-def _time_probe(n, box, cell_min, p4, v4, copies, steps, warmup, shared, stream):
+def _time_probe(n, box, cell_min, p4, v4, copies, steps, warmup, repeats, shared, stream):
+    """Seconds per atom-step of a probe batch: the fastest of ``repeats``
+    timed runs of ``steps`` steps after ``warmup`` untimed ones."""
     table = [(n, box, cell_min)] * copies
     b = BatchedLJ(table, **shared)
     pos = p4.repeat(copies, 1).contiguous()
     vel = v4.repeat(copies, 1).contiguous()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(repeats)]
     with torch.cuda.stream(stream):
         b.load(pos, vel)
         b.step(warmup)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        b.step(steps)
-        e1.record(stream)
+        for e0, e1 in events:
+            e0.record(stream)
+            b.step(steps)
+            e1.record(stream)
     stream.synchronize()
     b.check()
-    return e0.elapsed_time(e1) / 1e3 / (steps * n * copies)  # seconds per atom-step
+    best = min(e0.elapsed_time(e1) for e0, e1 in events) / 1e3
+    return best / (steps * n * copies)
 
 
 def tune_batch(replicas, pos4: torch.Tensor, vel4: torch.Tensor, *, epsilon=1.0, sigma=1.0, mass=1.0,
-               rc_over_sigma=2.5, dt=0.005, shift_mode=0, extra=1, min_atoms=131072, steps=8, warmup=2,
-               min_gain=0.03):
+               rc_over_sigma=2.5, dt=0.005, shift_mode=0, extra=1, min_atoms=131072, steps=10, warmup=3,
+               repeats=3, min_gain=0.03):
     """Pick a cell grid per replica.
 
     replicas: sequence of (n, box); pos4/vel4: the batch's concatenated float4
@@ -103,7 +114,7 @@ def tune_batch(replicas, pos4: torch.Tensor, vel4: torch.Tensor, *, epsilon=1.0,
         copies = max(1, math.ceil(min_atoms / n))
         tried = []
         for nc, cm in options[i]:
-            t = _time_probe(n, box, cm, p4, v4, copies, steps, warmup, shared, stream)
+            t = _time_probe(n, box, cm, p4, v4, copies, steps, warmup, repeats, shared, stream)
             tried.append({"cells_per_dim": nc, "cell_min": cm, "s_per_atom_step": t})
         best = tried[0]
         for cand in tried[1:]:
@@ -120,3 +131,9 @@ def tune_batch(replicas, pos4: torch.Tensor, vel4: torch.Tensor, *, epsilon=1.0,
         report.append({"bucket": {"cells_per_dim": key[0], "atoms_per_cell": key[1]}, "replicas": len(members),
                        "tried": tried, "chosen_cells_per_dim": best["cells_per_dim"]})
     return cell_mins, {"buckets": report, "seconds": time.perf_counter() - t_start}
+
+
+def tune_cell_min(n: int, box: float, pos4: torch.Tensor, vel4: torch.Tensor, **kw):
+    """The tuner on one system (for LJSystem): returns (cell_min, report)."""
+    cms, report = tune_batch([(n, box)], pos4, vel4, **kw)
+    return cms[0], report

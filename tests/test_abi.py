@@ -180,5 +180,8 @@ def test_grid_options_and_buckets():
         assert got == nc and side >= cm and side >= 2.5
     assert grid_options(500, 8.939, extra=2) == [(3, 0.0)]  # 2 cells would hold 62 atoms each
     assert grid_options(4000, L, extra=2, max_occupancy=20.0) == [(7, 0.0), (6, L / 6.5)]
+    # a sparse system also gets the grid sized for about 14 atoms per cell
+    Ls = (256000 / 0.1) ** (1.0 / 3.0)
+    assert [nc for nc, _ in grid_options(256000, Ls)] == [54, 53, 26]
     assert bucket_key(4000, 7) == (7, 12)
     assert bucket_key(4000, 7) == bucket_key(4100, 7)

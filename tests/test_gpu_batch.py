@@ -224,7 +224,7 @@ def test_tuned_batch_matches_oracle(orc):
 
     ws, table, pos, vel = _replicas(24, max_fcc=10)
     _say(f"tune a 24-replica batch, n_total={len(pos)}")
-    cms, report = tune_batch(table, _cuda(pos), _cuda(vel), min_atoms=16384, steps=3, warmup=1)
+    cms, report = tune_batch(table, _cuda(pos), _cuda(vel), min_atoms=16384, steps=3, warmup=1, repeats=1)
     assert len(cms) == len(table)
     for (n, box), cm in zip(table, cms):
         assert cm in [c for _, c in grid_options(n, box)]
@@ -239,3 +239,28 @@ def test_tuned_batch_matches_oracle(orc):
         lo, hi = b.offsets[i], b.offsets[i + 1]
         fo, _, _ = orc.forces(orc.params(table[i][1]), pos[lo:hi])
         assert np.linalg.norm(f[lo:hi] - fo) <= 1e-5 * np.linalg.norm(fo), i
+
+
+def test_tuner_moves_a_sparse_system_to_larger_cells(orc):
+    """At rho = 0.1 the default cells (side >= r_c) hold 1.6 atoms and the
+    grid sized for about 14 atoms runs several times faster per atom-step;
+    the tuner must find a coarser grid, and the result still matches the
+    oracle on sampled rows."""
+    torch = _torch()
+    from paper_0709_3225_amd import LJSystem, grid_options, tune_cell_min
+
+    w = ljsynth.Workload("sparse", 20, 0.1, 0.722, 20, 77)
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05)
+    _say(f"tune a sparse system n={w.n} box={box:.3f}")
+    cm, report = tune_cell_min(w.n, box, _cuda(pos4), _cuda(vel4), steps=4, warmup=1, repeats=2)
+    opts = grid_options(w.n, box)
+    assert cm > 0.0 and cm in [c for _, c in opts]
+    s = LJSystem(w.n, box, cell_min=cm)
+    assert s.cells_per_dim < opts[0][0]
+    assert len(report["buckets"]) == 1 and report["buckets"][0]["chosen_cells_per_dim"] == s.cells_per_dim
+    s.load(_cuda(pos4), _cuda(vel4))
+    f = s.forces().cpu().numpy()[:, :3]
+    s.check()
+    sel = np.random.default_rng(5).choice(w.n, size=256, replace=False)
+    fo, _, _ = orc.forces_rows(orc.params(box), pos4, sel)
+    assert np.linalg.norm(f[sel] - fo) <= 1e-5 * np.linalg.norm(fo)
