@@ -241,7 +241,8 @@ md_status md_adjoint_drift(const md_params* p, const float* lam_r4_dev, float* l
  * step back to the first apply the drift adjoint and the kick adjoint on the
  * kept cell list, with coefficient 2h, or h for step 0 (h = dt / 2m).
  * lam_r4_dev, lam_v4_dev and theta_dev accumulate as for md_adjoint_drift and
- * md_adjoint_kick. The workspace is overwritten and left without a built
+ * md_adjoint_kick (theta's terms are summed per cell over the segment, then
+ * over cells in a fixed order). The workspace is overwritten and left without a built
  * state: calls that read one raise MD_DEV_ORDER until md_build_cells.
  */
 md_status md_adjoint_segment(const md_params* p, void* ws, size_t ws_bytes, const float* ckpt_pos4_dev,

@@ -98,7 +98,7 @@ struct VGradOp {
 template <int OP>
 __global__ void __launch_bounds__(kWave)
     k_pair_pass(SimArgs a, const float4* __restrict__ wvec, float4* __restrict__ out_r, float4* __restrict__ out_v,
-                float coef, float kcoef) {
+                float coef, float kcoef, double pcoef, bool accumulate) {
     if (!state_ok(a, false)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&a.hdr[HDR_ERROR], DEV_ORDER);
         return;
@@ -231,9 +231,12 @@ __global__ void __launch_bounds__(kWave)
     }
     acc0 = wave_sum(acc0);
     acc1 = wave_sum(acc1);
+    // the cell's parameter partials, scaled by pcoef; accumulate adds them to
+    // the cell's running sums (the passes of one segment), else replaces them
     if (lane == 0) {
-        a.epart[3 * blockIdx.x + 0] = acc0;
-        a.epart[3 * blockIdx.x + 1] = acc1;
+        double* e = a.epart + 3 * static_cast<size_t>(blockIdx.x);
+        e[0] = (accumulate ? e[0] : 0.0) + pcoef * acc0;
+        e[1] = (accumulate ? e[1] : 0.0) + pcoef * acc1;
     }
 }
 
@@ -323,19 +326,24 @@ hipError_t launch_adjoint_kick(const SimArgs& a, const float4* w_user, float4* l
     hipLaunchKernelGGL(k_gather_vec, dim3((a.n + 255) / 256), dim3(256), 0, st, a, w_user);
     const size_t lds = 2 * sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
     hipLaunchKernelGGL((k_pair_pass<OP_ADJ>), dim3(a.ncells), dim3(kWave), lds, st, a,
-                       static_cast<const float4*>(a.vel1), lam_r, static_cast<float4*>(nullptr), coef, 0.f);
+                       static_cast<const float4*>(a.vel1), lam_r, static_cast<float4*>(nullptr), coef, 0.f, 1.0, false);
     if (theta) hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(kRedBlock), 0, st, a, theta, static_cast<double>(coef));
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_drift_kick(const SimArgs& a, float dt, float4* lam_r, float4* lam_v, double* theta,
-                                     float coef, hipStream_t st) {
+hipError_t launch_adjoint_drift_kick(const SimArgs& a, float dt, float4* lam_r, float4* lam_v, float coef,
+                                     bool accumulate, hipStream_t st) {
     hipLaunchKernelGGL(k_drift_gather, dim3((a.n + 255) / 256), dim3(256), 0, st, a, dt,
                        static_cast<const float4*>(lam_r), lam_v);
     const size_t lds = 2 * sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
     hipLaunchKernelGGL((k_pair_pass<OP_ADJ>), dim3(a.ncells), dim3(kWave), lds, st, a,
-                       static_cast<const float4*>(a.vel1), lam_r, static_cast<float4*>(nullptr), coef, 0.f);
-    if (theta) hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(kRedBlock), 0, st, a, theta, static_cast<double>(coef));
+                       static_cast<const float4*>(a.vel1), lam_r, static_cast<float4*>(nullptr), coef, 0.f,
+                       static_cast<double>(coef), accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_theta_final(const SimArgs& a, double* theta, double coef, hipStream_t st) {
+    hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(kRedBlock), 0, st, a, theta, coef);
     return hipGetLastError();
 }
 
@@ -343,7 +351,7 @@ hipError_t launch_loss_grad(const SimArgs& a, float kcoef, float wcoef, float4* 
                             hipStream_t st) {
     const size_t lds = sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
     hipLaunchKernelGGL((k_pair_pass<OP_VGRAD>), dim3(a.ncells), dim3(kWave), lds, st, a,
-                       static_cast<const float4*>(nullptr), g_r, g_v, wcoef, kcoef);
+                       static_cast<const float4*>(nullptr), g_r, g_v, wcoef, kcoef, 1.0, false);
     if (theta) hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(kRedBlock), 0, st, a, theta, static_cast<double>(wcoef));
     return hipGetLastError();
 }

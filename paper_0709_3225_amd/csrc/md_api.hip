@@ -722,13 +722,15 @@ md_status md_adjoint_segment(const md_params* p, void* ws, size_t ws_bytes, cons
         MD_TRY_HIP(launch_zero_blocks(a, (nsteps - 2) & 1, stream), "counter clear");
     }
     // from the last step of the segment back to its first: drift adjoint, then
-    // the kick adjoint on state j's kept cell list
+    // the kick adjoint on state j's kept cell list; the parameter terms are
+    // summed per cell over the segment and added to theta once
     for (int32_t j = nsteps - 1; j >= 0; --j) {
         const float coef = first_step + j >= 1 ? 2.0f * h : h;
         MD_TRY_HIP(launch_adjoint_drift_kick(at(j), p->dt, reinterpret_cast<float4*>(lam_r4),
-                                             reinterpret_cast<float4*>(lam_v4), theta, coef, stream),
+                                             reinterpret_cast<float4*>(lam_v4), coef, j < nsteps - 1, stream),
                    "adjoint drift and kick");
     }
+    if (theta) MD_TRY_HIP(launch_theta_final(a, theta, 1.0, stream), "parameter sums");
     // the workspace's own sorted arrays were not written: it holds no state now
     MD_TRY_HIP(launch_set_state(a, STATE_BUILDING, stream), "state reset");
     return MD_OK;

@@ -145,10 +145,14 @@ hipError_t launch_adjoint_kick(const SimArgs& a, const float4* w_user, float4* l
 hipError_t launch_loss_grad(const SimArgs& a, float kcoef, float wcoef, float4* g_r, float4* g_v, double* theta,
                             hipStream_t st);
 hipError_t launch_adjoint_drift(int n, float dt, const float4* lam_r, float4* lam_v, hipStream_t st);
-// launch_adjoint_drift followed by launch_adjoint_kick with w = lam_v, with
-// the drift folded into the gather (same arithmetic, one launch fewer).
-hipError_t launch_adjoint_drift_kick(const SimArgs& a, float dt, float4* lam_r, float4* lam_v, double* theta,
-                                     float coef, hipStream_t st);
+// launch_adjoint_drift followed by the gather and pair pass of
+// launch_adjoint_kick with w = lam_v, the drift folded into the gather (same
+// arithmetic, one launch fewer). The parameter terms times coef go to the
+// per-cell sums in epart (added to them with accumulate, else replacing
+// them); launch_theta_final adds coef times their fixed-order total to theta.
+hipError_t launch_adjoint_drift_kick(const SimArgs& a, float dt, float4* lam_r, float4* lam_v, float coef,
+                                     bool accumulate, hipStream_t st);
+hipError_t launch_theta_final(const SimArgs& a, double* theta, double coef, hipStream_t st);
 // Mark the workspace as holding no built state (the header's state word only).
 hipError_t launch_set_state(const SimArgs& a, int state, hipStream_t st);
 
