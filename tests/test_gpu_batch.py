@@ -264,3 +264,39 @@ def test_tuner_moves_a_sparse_system_to_larger_cells(orc):
     sel = np.random.default_rng(5).choice(w.n, size=256, replace=False)
     fo, _, _ = orc.forces_rows(orc.params(box), pos4, sel)
     assert np.linalg.norm(f[sel] - fo) <= 1e-5 * np.linalg.norm(fo)
+
+
+def test_tile_classes_with_multipass_tiles():
+    """One batch whose replicas fall into three LDS tile classes, one of them
+    with cells so large (about 148 atoms) that the neighbourhood is staged in
+    several passes: every replica is bitwise equal to its solo run."""
+    torch = _torch()
+    from paper_0709_3225_amd import BatchedLJ, LJSystem
+
+    specs = [(10, 0.85, 0.0), (10, 0.85, 5.5), (4, 0.85, 0.0), (7, 0.80, 0.0)]
+    ws = [ljsynth.Workload(f"t{i}", n, rho, 1.0, 5, 300 + i) for i, (n, rho, _) in enumerate(specs)]
+    states = [ljsynth.make_state(w, jitter_amp=0.05) for w in ws]
+    table = [(w.n, box, cm) for w, (_, _, box), (_, _, cm) in zip(ws, states, specs)]
+    _say(f"tile classes {table}")
+    pos = np.concatenate([s[0] for s in states])
+    vel = np.concatenate([s[1] for s in states])
+    b = BatchedLJ(table)
+    b.load(_cuda(pos), _cuda(vel))
+    b.step(5)
+    bp, bv = b.state()
+    f = torch.empty((b.n_total, 4), dtype=torch.float32, device="cuda")
+    b.forces(f)
+    b.check()
+    for i, ((n, box, cm), (p4, v4, _)) in enumerate(zip(table, states)):
+        s = LJSystem(n, box, cell_min=cm)
+        if cm > 0.0:
+            assert s.cells_per_dim == 3 and n / s.n_cells > 100  # several tile passes
+        s.load(_cuda(p4), _cuda(v4))
+        s.step(5)
+        sp, sv = s.state()
+        sf = s.forces()
+        s.check()
+        lo, hi = b.offsets[i], b.offsets[i + 1]
+        assert torch.equal(bp[lo:hi], sp), i
+        assert torch.equal(bv[lo:hi], sv), i
+        assert torch.equal(f[lo:hi], sf), i
