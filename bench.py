@@ -213,7 +213,7 @@ def wca_leg(torch, nsteps=100, warm=20):
     rho = 0.8442, T* = 0.722: md_step atom-steps/s with the paper's cells
     (side >= r_c) and with larger cells."""
     import ljsynth
-    from paper_0709_3225_amd import occupancy_cell_min
+    from paper_0709_3225_amd import occupancy_cell_min, tune_cell_min
 
     w = ljsynth.wca_workload()
     box = ljsynth.box_length(w.n, w.density)
@@ -223,6 +223,12 @@ def wca_leg(torch, nsteps=100, warm=20):
         pt = _widened_point(torch, w, cm, nsteps, warm)
         pt["cells"] = cells
         points.append(pt)
+    pos4, vel4, _ = ljsynth.make_state(w)
+    cm, rep = tune_cell_min(w.n, box, torch.from_numpy(pos4).cuda(), torch.from_numpy(vel4).cuda(),
+                            rc_over_sigma=w.rc_over_sigma, shift_mode=w.shift_mode, dt=w.dt)
+    pt = _widened_point(torch, w, cm, nsteps, warm)
+    pt.update({"cells": "tuned", "tune_seconds": round(rep["seconds"], 3)})
+    points.append(pt)
     best = max(points, key=lambda p: p["value"])
     return {"workload": f"{w.name}: WCA N={w.n} (40^3 FCC start), rho={w.density}, T*={w.temperature}, "
                         f"rc=2^(1/6) sigma energy-shifted, dt={w.dt}, {nsteps} steps after {warm}",
