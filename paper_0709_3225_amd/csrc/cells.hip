@@ -150,64 +150,78 @@ __global__ void __launch_bounds__(kBlock) k_batch_setup(SimArgs base, const Repl
 }
 
 // Block scan: bstart[b] = atoms in the cells of blocks 0 .. b - 1 (16 cells
-// a block), by one workgroup of 1024 lanes. One workgroup runs on one CU,
-// whose memory pipeline serves a few cache lines per clock, so a lane reads
-// kScanBlocks whole blocks as consecutive int4 (adjacent lanes read adjacent
-// 128-byte runs) and all of a tile's loads are issued before any arithmetic.
-// A lane's blocks then get a running prefix, a wavefront scan and a scan of
-// the 16 wave totals give the lane's offset, and tiles are linked by a carry.
+// a block), for grids of more than kDirectBlocks blocks. Workgroup g of 1024
+// lanes owns tile g of kScanTile blocks; a lane reads kScanBlocks whole
+// blocks as consecutive int4 (adjacent lanes read adjacent 128-byte runs),
+// all loads issued before any arithmetic, and a wavefront scan plus a scan of
+// the 16 wave totals give each block's offset within the tile. Two launches:
+// PHASE 0 stores each tile's total, PHASE 1 adds the totals of the tiles
+// before its own (read by every workgroup; there are at most a few thousand)
+// and writes bstart. The tile totals live in the block-count array, which
+// the binning only fills on grids of at most kDirectBlocks blocks.
 constexpr int kScanBlock = 1024;
 constexpr int kScanBlocks = 2;                          // blocks per lane per tile
 constexpr int kScanTile = kScanBlock * kScanBlocks;      // 2048 blocks = 32768 cells
 constexpr int kBlockInts = 1 << kBlockShift;
+template <int PHASE>
 __global__ void __launch_bounds__(kScanBlock) k_block_scan(SimArgs a, bool from_step) {
     __shared__ int wave_tot[kScanBlock / kWave];
+    __shared__ int wave_carry[kScanBlock / kWave];
     const int err = a.hdr[HDR_ERROR];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int nb = a.nblocks;
+    const int g = blockIdx.x;
+    int* tile_tot_arr = a.bcounts;
+    const int b0 = g * kScanTile + tid * kScanBlocks;
+    int4 v[kScanBlocks * kBlockInts / 4];
+#pragma unroll
+    for (int q = 0; q < kScanBlocks * kBlockInts / 4; ++q) {
+        // counts holds whole blocks (zero past the last cell)
+        v[q] = (b0 + q / (kBlockInts / 4) < nb) ? reinterpret_cast<const int4*>(a.counts)[b0 * (kBlockInts / 4) + q]
+                                                : make_int4(0, 0, 0, 0);
+    }
     int carry = 0;
-    for (int base = 0; base < nb; base += kScanTile) {
-        const int b0 = base + tid * kScanBlocks;
-        int4 v[kScanBlocks * kBlockInts / 4];
+    if (PHASE == 1) {
+        for (int k = tid; k < g; k += kScanBlock) carry += tile_tot_arr[k];
+    }
+    if (from_step && (err & DEV_ORDER)) return;  // uniform over the grid
+    int bsum[kScanBlocks];
+    int tsum = 0;
 #pragma unroll
-        for (int q = 0; q < kScanBlocks * kBlockInts / 4; ++q) {
-            // counts holds whole blocks (zero past the last cell)
-            v[q] = (b0 + q / (kBlockInts / 4) < nb)
-                       ? reinterpret_cast<const int4*>(a.counts)[b0 * (kBlockInts / 4) + q]
-                       : make_int4(0, 0, 0, 0);
+    for (int j = 0; j < kScanBlocks; ++j) {
+        int t = 0;
+#pragma unroll
+        for (int q = 0; q < kBlockInts / 4; ++q) {
+            const int4 x = v[j * (kBlockInts / 4) + q];
+            t += x.x + x.y + x.z + x.w;
         }
-        if (from_step && (err & DEV_ORDER)) return;  // uniform over the workgroup
-        int bsum[kScanBlocks];
-        int tsum = 0;
+        bsum[j] = t;
+        tsum += t;
+    }
+    const int incl = wave_incl_scan(tsum);
+    if (lane == kWave - 1) wave_tot[wave] = incl;
+    if (PHASE == 1) {
+        carry = wave_sum_int(carry);
+        if (lane == 0) wave_carry[wave] = carry;
+    }
+    __syncthreads();
+    int wave_off = 0, tile_tot = 0, before = 0;
 #pragma unroll
-        for (int j = 0; j < kScanBlocks; ++j) {
-            int t = 0;
+    for (int k = 0; k < kScanBlock / kWave; ++k) {
+        const int t = wave_tot[k];
+        if (k < wave) wave_off += t;
+        tile_tot += t;
+        if (PHASE == 1) before += wave_carry[k];
+    }
+    if (PHASE == 0) {
+        if (tid == 0) tile_tot_arr[g] = tile_tot;
+        return;
+    }
+    int run = before + wave_off + incl - tsum;
 #pragma unroll
-            for (int q = 0; q < kBlockInts / 4; ++q) {
-                const int4 x = v[j * (kBlockInts / 4) + q];
-                t += x.x + x.y + x.z + x.w;
-            }
-            bsum[j] = t;
-            tsum += t;
-        }
-        const int incl = wave_incl_scan(tsum);
-        if (lane == kWave - 1) wave_tot[wave] = incl;
-        __syncthreads();
-        int wave_off = 0, tile_tot = 0;
-#pragma unroll
-        for (int k = 0; k < kScanBlock / kWave; ++k) {
-            const int t = wave_tot[k];
-            if (k < wave) wave_off += t;
-            tile_tot += t;
-        }
-        int run = carry + wave_off + incl - tsum;
-#pragma unroll
-        for (int j = 0; j < kScanBlocks; ++j) {
-            if (b0 + j < nb) a.bstart[b0 + j] = run;
-            run += bsum[j];
-        }
-        carry += tile_tot;
-        __syncthreads();
+    for (int j = 0; j < kScanBlocks; ++j) {
+        if (b0 + j < nb) a.bstart[b0 + j] = run;
+        run += bsum[j];
     }
 }
 
@@ -426,7 +440,9 @@ hipError_t launch_integrate(const SimArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_block_scan(const SimArgs& a, bool from_step, hipStream_t st) {
-    hipLaunchKernelGGL(k_block_scan, dim3(1), dim3(kScanBlock), 0, st, a, from_step);
+    const int tiles = (a.nblocks + kScanTile - 1) / kScanTile;  // <= 2 nbstride: the tile totals fit
+    hipLaunchKernelGGL(k_block_scan<0>, dim3(tiles), dim3(kScanBlock), 0, st, a, from_step);
+    hipLaunchKernelGGL(k_block_scan<1>, dim3(tiles), dim3(kScanBlock), 0, st, a, from_step);
     return hipGetLastError();
 }
 
