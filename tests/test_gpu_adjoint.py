@@ -46,12 +46,21 @@ def _loaded(pos4, box, vel4=None):
     return s
 
 
-@pytest.mark.parametrize("name", ["lj256_check", "lj4k", "lj32k_adjoint"])
+# dense grids of 8 to 2,197 cells, and a sparse one of 19,683 cells
+HVP_CASES = {
+    "lj256_check": lambda: ljsynth.WORKLOADS["lj256_check"],
+    "lj4k": lambda: ljsynth.WORKLOADS["lj4k"],
+    "lj32k_adjoint": lambda: ljsynth.WORKLOADS["lj32k_adjoint"],
+    "rho0.1_32k": lambda: ljsynth.Workload("rho0.1_32k", 20, 0.1, 1.0, 0, 55),
+}
+
+
+@pytest.mark.parametrize("name", list(HVP_CASES))
 def test_hvp_and_force_parameter_derivatives(name, orc):
     torch = _torch()
     from paper_0709_3225_amd import _lib as L
 
-    pos4, vel4, box = ljsynth.make_state(ljsynth.WORKLOADS[name], jitter_amp=0.05, shuffle=True)
+    pos4, vel4, box = ljsynth.make_state(HVP_CASES[name](), jitter_amp=0.05, shuffle=True)
     _say(f"hvp {name} n={len(pos4)}")
     w = np.zeros_like(pos4)
     w[:, :3] = np.random.default_rng(7).normal(size=(len(pos4), 3))
@@ -110,12 +119,12 @@ def test_hvp_symmetry_and_translation():
     assert s.check() == 0
 
 
-@pytest.mark.parametrize("name", ["lj256_check", "lj4k"])
+@pytest.mark.parametrize("name", ["lj256_check", "lj4k", "rho0.1_32k"])
 def test_loss_gradient(name, orc):
     torch = _torch()
     from paper_0709_3225_amd import _lib as L
 
-    pos4, vel4, box = ljsynth.make_state(ljsynth.WORKLOADS[name], jitter_amp=0.05)
+    pos4, vel4, box = ljsynth.make_state(HVP_CASES[name](), jitter_amp=0.05)
     _say(f"loss gradient {name}")
     n = len(pos4)
     s = _loaded(pos4, box, vel4)
