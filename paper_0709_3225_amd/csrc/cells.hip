@@ -288,7 +288,11 @@ __global__ void __launch_bounds__(kOrderBlock) k_cell_order(SimArgs a, bool from
     const int err = a.hdr[HDR_ERROR];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int cl = tid / kOrderGroup, sub = tid & (kOrderGroup - 1);
-    const int c0 = blockIdx.x * kOrderCells, c = c0 + cl;
+    // blocks in the force kernel's XCD order: the cells a workgroup orders are
+    // those whose bins the same XCD's force waves filled, and whose sorted
+    // arrays its next force waves stage
+    const int blk = xcd_block_order(blockIdx.x, gridDim.x);
+    const int c0 = blk * kOrderCells, c = c0 + cl;
     const int nct = a.ncells;
     // Everything the first window needs is requested at once: the first 32
     // bucket entries of the cell (the capacity is at least 32; entries past
@@ -313,12 +317,12 @@ __global__ void __launch_bounds__(kOrderBlock) k_cell_order(SimArgs a, bool from
 #pragma unroll
         for (int u = 0; u < kDirectBlocks / kOrderBlock; ++u) {
             const int j = tid + u * kOrderBlock;
-            v[u] = j < static_cast<int>(blockIdx.x) ? bc[j] : 0;
+            v[u] = j < blk ? bc[j] : 0;
         }
 #pragma unroll
         for (int u = 0; u < kDirectBlocks / kOrderBlock; ++u) part += v[u];
     }
-    const int bs = a.direct ? 0 : a.bstart[blockIdx.x];
+    const int bs = a.direct ? 0 : a.bstart[blk];
     const int novf = min(a.hdr[HDR_OVF + a.par], a.natoms);
     if (from_step && (err & DEV_ORDER)) return;  // uniform over the workgroup
     part = wave_sum_int(part);
@@ -336,7 +340,7 @@ __global__ void __launch_bounds__(kOrderBlock) k_cell_order(SimArgs a, bool from
         a.counts[c] = 0;  // the next build's histogram
     }
     // the other parity's counters, for the next build
-    if (a.direct && tid == 0) a.bcounts[(1 - a.par) * a.nbstride + blockIdx.x] = 0;
+    if (a.direct && tid == 0) a.bcounts[(1 - a.par) * a.nbstride + blk] = 0;
     if (blockIdx.x == 0 && tid == 0) a.hdr[HDR_OVF + 1 - a.par] = 0;
     int* wids = reinterpret_cast<int*>(win[cl]);
     for (int m0 = 0; m0 < nmax; m0 += kOrderWin) {
