@@ -337,7 +337,8 @@ def algorithmic_force_flops(sys_, torch):
 
 FORCE_SOURCES = ("paper_0709_3225_amd/csrc/forces.hip", "paper_0709_3225_amd/csrc/cell_pairs.h",
                  "paper_0709_3225_amd/csrc/md_device.h",
-                 "paper_0709_3225_amd/csrc/md_internal.h")
+                 "paper_0709_3225_amd/csrc/md_internal.h",
+                 "paper_0709_3225_amd/build.py")  # the compiler flags shape the kernel too
 
 
 def recorded_traffic(workload):

@@ -2,7 +2,8 @@
 
 hipcc builds every ``csrc/*.hip`` file (kernels and the C-ABI layer) into one
 shared library next to this file. Packed-FP32 instruction selection is
-switched off for all device code.
+switched off for all device code, and matrix-core instructions write their
+results to ordinary VGPRs.
 """
 from __future__ import annotations
 
@@ -23,6 +24,9 @@ FLAGS = [
     "-fPIC",
     "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results in ordinary VGPRs: the screen shifts each verdict
+    # straight into its accept word instead of copying it out of an AGPR first
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall",
 ]
 
