@@ -491,6 +491,9 @@ def main():
             "flops_per_launch": flops,
             "candidates": candidates,
             "accepted_pairs": accepted,
+            # the interaction-only count: 25 flop per accepted ordered pair,
+            # the floor of any exact method, over the same kernel time
+            "interaction_only_tflops": (FLOP_PER_CANDIDATE + FLOP_PER_ACCEPTED) * accepted / (force_us * 1e-6) / 1e12,
         },
         "thermo_last": e_th,
     }
