@@ -173,13 +173,13 @@ __global__ void __launch_bounds__(kWave)
                              xi, yi, zi, wi.x, wi.y, wi.z};
                     op.inv_sig = inv_sig;
                     op.jx = v0; op.jy = v1; op.jz = v2; op.fx = v3; op.fy = v4; op.fz = v5; op.sg = v6;
-                    walk_bits2(ns, wd[0], wd[1], wd[2], wd[3], op);
+                    walk_bits(ns, wd[0], wd[1], wd[2], wd[3], op);
                     v0 = op.jx; v1 = op.jy; v2 = op.jz; v3 = op.fx; v4 = op.fy; v5 = op.fz; v6 = op.sg;
                 } else {
                     VGradOp op{a, reinterpret_cast<const char*>(tile + first), xi, yi, zi};
                     op.inv_sig = inv_sig;
                     op.gx = v0; op.gy = v1; op.gz = v2; op.wsum = v3; op.wsig = v4;
-                    walk_bits2(ns, wd[0], wd[1], wd[2], wd[3], op);
+                    walk_bits(ns, wd[0], wd[1], wd[2], wd[3], op);
                     v0 = op.gx; v1 = op.gy; v2 = op.gz; v3 = op.wsum; v4 = op.wsig;
                 }
             }

@@ -496,47 +496,20 @@ __device__ __forceinline__ void screen_span(const float4* tile, int first, int n
     }
 }
 
-// Walk the accepted bits of one span, calling op(byte_offset, live) once per
-// iteration: byte_offset locates the accepted candidate relative to
+// Walk the accepted bits of one span in order, calling op(byte_offset, live)
+// for each: byte_offset locates the accepted candidate relative to
 // tile + first (and the same offset in any parallel tile); live is false for
 // lanes that have spent their bits. The words rotate through four registers
 // (never indexed, which would put them in scratch memory); an exhausted word
-// is replaced by the next one without a branch.
+// is replaced by the next one without a branch. Each iteration takes two
+// candidates (the second may come from the next word), so the wave-wide loop
+// test and branch run once per pair; the calls keep the one-at-a-time order,
+// so sums do not depend on the unrolling.
 template <class Op>
 __device__ __forceinline__ void walk_bits(int ns, uint32_t m, uint32_t n1, uint32_t n2, uint32_t n3, Op& op) {
     const uint32_t cstep = static_cast<uint32_t>(ns) * sizeof(float4);   // bytes between candidates
     const uint32_t wstep = 32u * cstep;                                  // bytes between words
     uint32_t wb = 0;                                                     // byte offset of the word's candidate 0
-    uint32_t left = __builtin_popcount(m) + __builtin_popcount(n1) + __builtin_popcount(n2) +
-                    __builtin_popcount(n3);
-    if (!__any(left != 0u)) return;
-    do {
-        const bool next = (m == 0u);
-        m = next ? n1 : m;
-        n1 = next ? n2 : n1;
-        n2 = next ? n3 : n2;
-        n3 = next ? 0u : n3;
-        wb = next ? wb + wstep : wb;
-        const bool live = m != 0u;
-        const uint32_t k = live ? __builtin_clz(m) : 0u;
-        m &= ~(0x80000000u >> k);
-        left -= live ? 1u : 0u;
-        // a spent lane keeps rotating (wb grows past its span): it reads its
-        // span's first candidate instead, which is always staged
-        op(live ? wb + __umul24(k, cstep) : 0u, live);
-    } while (__any(left != 0u));
-}
-
-// The same walk taking two accepted candidates per iteration (the second may
-// come from the next word), in the same order: op sees the same sequence of
-// (offset, live) calls as from walk_bits, so sums are bitwise equal. The loop
-// overhead and the final masked iterations of the slowest lanes are paid
-// once per pair of candidates.
-template <class Op>
-__device__ __forceinline__ void walk_bits2(int ns, uint32_t m, uint32_t n1, uint32_t n2, uint32_t n3, Op& op) {
-    const uint32_t cstep = static_cast<uint32_t>(ns) * sizeof(float4);
-    const uint32_t wstep = 32u * cstep;
-    uint32_t wb = 0;
     uint32_t left = __builtin_popcount(m) + __builtin_popcount(n1) + __builtin_popcount(n2) +
                     __builtin_popcount(n3);
     if (!__any(left != 0u)) return;
@@ -555,6 +528,8 @@ __device__ __forceinline__ void walk_bits2(int ns, uint32_t m, uint32_t n1, uint
             const uint32_t k = live[u] ? __builtin_clz(m) : 0u;
             m &= ~(0x80000000u >> k);
             left -= live[u] ? 1u : 0u;
+            // a spent lane keeps rotating (wb grows past its span): it reads
+            // its span's first candidate instead, which is always staged
             off[u] = live[u] ? wb + __umul24(k, cstep) : 0u;
         }
         op(off[0], live[0]);

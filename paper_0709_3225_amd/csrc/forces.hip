@@ -190,7 +190,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                     // the lane's candidates are tile + 16 b0 + s + 4 g, as for four VALU slices
                     ForceOp<ENERGY> op{a, reinterpret_cast<const char*>(tile + 16 * b0 + s), xi, yi, zi, fx, fy, fz,
                                        u_loc, w_loc};
-                    walk_bits2<ForceOp<ENERGY>>(4, wd[0], wd[1], wd[2], wd[3], op);
+                    walk_bits<ForceOp<ENERGY>>(4, wd[0], wd[1], wd[2], wd[3], op);
                     fx = op.fx;
                     fy = op.fy;
                     fz = op.fz;
@@ -220,7 +220,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                 }
                 ForceOp<ENERGY> op{a, reinterpret_cast<const char*>(tile + first), xi, yi, zi, fx, fy, fz, u_loc,
                                    w_loc};
-                walk_bits2(ns, wd[0], wd[1], wd[2], wd[3], op);
+                walk_bits(ns, wd[0], wd[1], wd[2], wd[3], op);
                 fx = op.fx;
                 fy = op.fy;
                 fz = op.fz;
