@@ -141,11 +141,23 @@ def adjoint_leg(torch):
     s.check()
     adj = w.n * w.steps / t_adj
     plain = w.n * w.steps / t_plain
+    # the same gradient at the headline size (N = 256,000), where the grid
+    # fills the chip: context for how the ratio depends on the size
+    wl = ljsynth.WORKLOADS["lj256k"]
+    pos4, vel4, boxl = ljsynth.make_state(wl)
+    xl, vl = torch.from_numpy(pos4).cuda(), torch.from_numpy(vel4).cuda()
+    trajectory_gradients(xl, vl, boxl, nsteps=20, every=20)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    trajectory_gradients(xl, vl, boxl, nsteps=w.steps, every=20)
+    torch.cuda.synchronize()
+    adj_l = wl.n * w.steps / (time.perf_counter() - t0)
     return {
         "workload": f"{w.name}: N={w.n}, rho={w.density}, T*={w.temperature}, {w.steps} steps, checkpoints every 20, "
                     "loss K_T/N + W_T/(3V), gradients w.r.t. r0, v0, eps, sigma",
         "value": adj, "unit": "atom-steps/s (forward + backward)", "plain_value": plain,
         "ratio_vs_plain": adj / plain, "loss": loss, "dL_deps": ge, "dL_dsigma": gs,
+        "value_at_256k": adj_l,
     }
 
 
