@@ -368,16 +368,39 @@ __global__ void __launch_bounds__(kWave)
 // Fixed-order final sum of the per-block partials: U = 1/2 sum, W = 1/2 sum
 // (every pair is visited from both sides), K as is.
 constexpr int kRedBlock = 256;
+constexpr int kRedUnroll = 8;
+
+// Lane t's running sums of the (U, W, K) partials of blocks t, t + kRedBlock,
+// t + 2 kRedBlock, ... in that order; the loads of kRedUnroll blocks are
+// issued before their sums, so the sequential order costs no round trips.
+__device__ __forceinline__ void sum_partials(const double* __restrict__ e, int n, int t, double& u, double& w,
+                                             double& k) {
+    for (int b0 = t; b0 < n; b0 += kRedBlock * kRedUnroll) {
+        double pu[kRedUnroll], pw[kRedUnroll], pk[kRedUnroll];
+#pragma unroll
+        for (int q = 0; q < kRedUnroll; ++q) {
+            const int b = b0 + q * kRedBlock;
+            const bool ok = b < n;
+            pu[q] = ok ? e[3 * b + 0] : 0.0;
+            pw[q] = ok ? e[3 * b + 1] : 0.0;
+            pk[q] = ok ? e[3 * b + 2] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kRedUnroll; ++q) {
+            if (b0 + q * kRedBlock < n) {
+                u += pu[q];
+                w += pw[q];
+                k += pk[q];
+            }
+        }
+    }
+}
 __global__ void __launch_bounds__(kRedBlock) k_energy_final(SimArgs a, double* out3, bool from_step) {
     if (from_step && (a.hdr[HDR_ERROR] & DEV_ORDER)) return;
     __shared__ double su[kRedBlock], sw[kRedBlock], sk[kRedBlock];
     const int t = threadIdx.x;
     double u = 0.0, w = 0.0, k = 0.0;
-    for (int b = t; b < a.ncells; b += kRedBlock) {
-        u += a.epart[3 * b + 0];
-        w += a.epart[3 * b + 1];
-        k += a.epart[3 * b + 2];
-    }
+    sum_partials(a.epart, a.ncells, t, u, w, k);
     su[t] = u;
     sw[t] = w;
     sk[t] = k;
@@ -406,12 +429,7 @@ __global__ void __launch_bounds__(kRedBlock)
     const Replica r = reps[blockIdx.x];
     const int t = threadIdx.x;
     double u = 0.0, w = 0.0, k = 0.0;
-    for (int c = t; c < r.ncells; c += kRedBlock) {
-        const double* e = base.epart + 3 * static_cast<size_t>(r.cbase + c);
-        u += e[0];
-        w += e[1];
-        k += e[2];
-    }
+    sum_partials(base.epart + 3 * static_cast<size_t>(r.cbase), r.ncells, t, u, w, k);
     su[t] = u;
     sw[t] = w;
     sk[t] = k;
