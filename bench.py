@@ -375,6 +375,29 @@ def recorded_traffic(workload):
     return float(rec["traffic_bytes_per_launch"])
 
 
+def cpu_cell_list(pos4, vel4, box, headline, steps=3):
+    """Algorithm-matched CPU baseline: the same cell-list method in C with
+    OpenMP on the host cores (built here for this host's CPU), FP32 and FP64,
+    on the same state; per-step time from runs of `steps` and 0 steps."""
+    import cpu_cells
+
+    cpu_cells.build(force=True, native=True)
+    out = {"unit": "atom-steps/s", "cores": cpu_cells.num_threads(), "kind": "cell list (C, OpenMP)",
+           "sample": f"{steps} velocity-Verlet steps of the N={len(pos4)} state, cell list rebuilt every step"}
+    for prec in ("f32", "f64"):
+        cpu_cells.run(pos4, vel4, box, 1, precision=prec)  # warm (threads, pages)
+        t0 = time.perf_counter()
+        cpu_cells.run(pos4, vel4, box, 0, precision=prec)
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        cpu_cells.run(pos4, vel4, box, steps, precision=prec)
+        t_steps = time.perf_counter() - t0
+        per_step = max(t_steps - t_setup, 1e-9) / steps
+        v = len(pos4) / per_step
+        out[prec] = {"value": v, "ms_per_step": per_step * 1e3, "gpu_ratio": headline / v}
+    return out
+
+
 def cpu_baseline(pos4, box, target_s):
     """FP64 oracle: force rows of the same state (each row = all N partners),
     repeated until about target_s seconds; one oracle MD step costs one row
@@ -533,6 +556,8 @@ def main():
         out["pair_list"] = pair_list_leg(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s.state()[0].cpu().numpy(), box, args.cpu_seconds)
+        sp, sv = s.state()
+        out["cpu_cell_list"] = cpu_cell_list(sp.cpu().numpy(), sv.cpu().numpy(), box, value)
     print(json.dumps(out), flush=True)
 
 
