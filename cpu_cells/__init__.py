@@ -51,12 +51,19 @@ def _load():
             f.argtypes = [P, ctypes.c_int64, rp, rp, rp, ctypes.c_int32]
             f.restype = ctypes.c_int
         lib.cc_num_threads.restype = ctypes.c_int
+        lib.cc_set_threads.argtypes = [ctypes.c_int]
+        lib.cc_set_threads.restype = None
         _lib = lib
     return _lib
 
 
 def num_threads() -> int:
     return int(_load().cc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the following runs."""
+    _load().cc_set_threads(int(n))
 
 
 def run(pos, vel, box, nsteps, *, precision="f64", epsilon=1.0, sigma=1.0, rc_over_sigma=2.5, mass=1.0, dt=0.005):

@@ -24,6 +24,14 @@ int cc_num_threads(void) {
 #endif
 }
 
+void cc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 #define REAL float
 #define FLOOR floorf
 #define SQRT sqrtf
