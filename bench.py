@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint throughput leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-replica throughput leg")
     ap.add_argument("--no-widened", action="store_true", help="skip the density-axis, WCA and skin legs")
+    ap.add_argument("--only", choices=("adjoint", "batched"),
+                    help="run only this leg and print its JSON (for kernel traces of one leg)")
     return ap.parse_args()
 
 
@@ -462,6 +464,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.only:
+        leg = adjoint_leg(torch) if args.only == "adjoint" else batched_leg(torch)
+        print(json.dumps({args.only: leg}), flush=True)
+        return
     w = ljsynth.WORKLOADS[args.workload]
     pos4, vel4, box = ljsynth.make_state(w)
     s = LJSystem(w.n, box, epsilon=w.epsilon, sigma=w.sigma, mass=w.mass, rc_over_sigma=w.rc_over_sigma, dt=w.dt)
