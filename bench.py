@@ -211,7 +211,7 @@ def full_size_leg(torch, nsteps=100, warm=20):
 
 def density_leg(torch, nsteps=100, warm=20):
     """LJ (r_c = 2.5 sigma) at N = 256,000 along the density axis of the
-    paper's cell-list measurements (section 4): md_step atom-steps/s with the
+    paper's cell-list measurements (section 3.2): md_step atom-steps/s with the
     paper's cells (side >= r_c), with cells sized for about 14 atoms, and with
     the grid the autotuner picks by measurement."""
     import ljsynth
@@ -303,7 +303,7 @@ def pair_list_leg(torch, nsteps=100, warm=20):
     pos4, vel4, box = ljsynth.make_state(w)
     points = []
     for cm, every in ((0.0, 2), (0.0, 3), (0.0, 4), (2.7, 6), (2.7, 10), (2.9, 10), (2.9, 15)):
-        s = LJSystem(w.n, box, dt=w.dt, cell_min=cm)
+        s = LJSystem(w.n, box, dt=w.dt, cell_min=cm, pair_lists=True)
         s.load(torch.from_numpy(pos4).cuda(), torch.from_numpy(vel4).cuda())
         s.step(warm)
         stream = torch.cuda.current_stream()

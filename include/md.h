@@ -72,8 +72,13 @@ typedef struct md_params {
     float cell_min;        /* minimum cell side; 0 selects r_c */
     int32_t shift_mode;    /* 0: force shifted to zero at r_c (section 2);
                               1: plain truncated force, energy shifted */
-    int32_t flags;         /* reserved, must be 0 */
+    int32_t flags;         /* MD_FLAG_* bits; 0 for a plain workspace */
 } md_params;
+
+/* md_params.flags: lay the workspace out with md_step_list's pair-list
+ * arrays (about 4.3 KB per cell and 16 B per atom more); md_step_list
+ * refuses a workspace without them. */
+#define MD_FLAG_PAIR_LISTS 1
 
 /*
  * Bytes of device workspace for these parameters (0 if they are invalid).
@@ -162,7 +167,8 @@ md_status md_step_every(const md_params* p, void* ws, size_t ws_bytes, int32_t n
  * if an atom moves more than (cell side - r_c) / 2 from where it was when the
  * words were kept. Cells that need more than one LDS pass, or more than four
  * 128-candidate spans per lane, screen as usual. Arguments and return values
- * as for md_step_every.
+ * as for md_step_every; the workspace must have been sized with
+ * MD_FLAG_PAIR_LISTS in p->flags (MD_ERR_ARG otherwise).
  */
 md_status md_step_list(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps,
                        int32_t rebuild_every, int32_t thermo_every, double* thermo_dev,
@@ -260,6 +266,26 @@ md_status md_adjoint_segment(const md_params* p, void* ws, size_t ws_bytes, cons
  */
 md_status md_loss_grad(const md_params* p, void* ws, size_t ws_bytes, float k_coef, float w_coef,
                        float* g_r4_dev, float* g_v4_dev, double* theta_dev, hipStream_t stream);
+
+/*
+ * The loss of the adjoint workload at the current workspace state (cells
+ * built): L = K / N + W / (3 V), V = L_box^3, the mean kinetic energy per
+ * particle plus the virial part of the pressure (K and W as for
+ * md_energy_virial; FP64 fixed-order sums). loss_dev: one device double.
+ */
+md_status md_loss(const md_params* p, void* ws, size_t ws_bytes, double* loss_dev, hipStream_t stream);
+
+/*
+ * Seed of the backward pass through md_step from md_loss at the current
+ * (final) state r_T, v_T: with h = dt / (2 m),
+ *   lam_v4_dev = scale dL/dv_T, lam_r4_dev = scale dL/dr_T + h J(r_T) lam_v4_dev
+ * (written, not accumulated; the second term is the kick adjoint of the
+ * step's closing half kick), theta_dev[0..1] += the matching scale
+ * dL/d(epsilon, sigma) terms (nullable). Then md_adjoint_segment runs the
+ * segments from the last back to the first. Force-shift mode only.
+ */
+md_status md_adjoint_seed(const md_params* p, void* ws, size_t ws_bytes, float scale, float* lam_r4_dev,
+                          float* lam_v4_dev, double* theta_dev, hipStream_t stream);
 
 /*
  * ---- Batches of independent replicas ----

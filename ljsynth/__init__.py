@@ -64,7 +64,7 @@ WORKLOADS = {
 
 
 # Widened workloads. The density axis of the paper's cell-list measurements
-# (section 4, rho from 0.1 to 1.0) at the headline size, and WCA: LJ cut at
+# (section 3.2, rho from 0.1 to 1.0) at the headline size, and WCA: LJ cut at
 # its minimum 2^(1/6) sigma and shifted by eps (a short-range pair potential
 # in place of LJ, as the paper's closing section allows). The WCA cutoff is
 # the FP32 value both the GPU path and the oracle use.

@@ -23,6 +23,9 @@ MD_ERR_DEVICE = 6
 MD_DEV_NONFINITE = 1
 MD_DEV_ORDER = 2
 MD_DEV_NB_OVERFLOW = 4
+MD_DEV_SKIN = 8
+
+MD_FLAG_PAIR_LISTS = 1
 
 # Symbols declared in include/md.h, in declaration order.
 SYMBOLS = (
@@ -41,6 +44,8 @@ SYMBOLS = (
     "md_adjoint_drift",
     "md_adjoint_segment",
     "md_loss_grad",
+    "md_loss",
+    "md_adjoint_seed",
     "md_batch_workspace_bytes",
     "md_batch_build",
     "md_batch_forces",
@@ -129,6 +134,8 @@ def lib():
         L.md_adjoint_drift.argtypes = [P, vp, vp, vp]
         L.md_loss_grad.argtypes = [P, vp, sz, ctypes.c_float, ctypes.c_float, vp, vp, vp, vp]
         L.md_adjoint_segment.argtypes = [P, vp, sz, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.md_loss.argtypes = [P, vp, sz, vp, vp]
+        L.md_adjoint_seed.argtypes = [P, vp, sz, ctypes.c_float, vp, vp, vp, vp]
         R = ctypes.POINTER(MDReplica)
         L.md_batch_workspace_bytes.argtypes = [P, R, i32]
         L.md_batch_workspace_bytes.restype = sz
@@ -142,7 +149,8 @@ def lib():
         L.md_graph_destroy.argtypes = [vp]
         for name in ("md_cell_grid", "md_build_cells", "md_forces", "md_step", "md_step_every", "md_step_list", "md_energy_virial",
                      "md_get_state", "md_neighbors", "md_cell_lists", "md_check", "md_adjoint_kick",
-                     "md_adjoint_drift", "md_adjoint_segment", "md_loss_grad", "md_batch_build", "md_batch_forces", "md_batch_step",
+                     "md_adjoint_drift", "md_adjoint_segment", "md_loss_grad", "md_loss", "md_adjoint_seed",
+                     "md_batch_build", "md_batch_forces", "md_batch_step",
                      "md_batch_energy_virial", "md_batch_get_state", "md_batch_graph_create", "md_graph_launch",
                      "md_graph_destroy"):
             getattr(L, name).restype = ctypes.c_int
@@ -363,3 +371,21 @@ def md_loss_grad(p: MDParams, ws, k_coef: float, w_coef: float, g_r4, g_v4, thet
     _check(lib().md_loss_grad(ctypes.byref(p), wp, wn, float(k_coef), float(w_coef),
                               _ptr(g_r4, "g_r4", torch.float32, (p.n, 4)), _ptr(g_v4, "g_v4", torch.float32, (p.n, 4)),
                               _ptr(theta, "theta", torch.float64, (2,)), _stream(stream)))
+
+
+def md_loss(p: MDParams, ws, loss, stream=None):
+    """loss[0] = K/N + W/(3V) at the workspace state (FP64, on the device)."""
+    import torch
+
+    wp, wn = _ws(ws)
+    _check(lib().md_loss(ctypes.byref(p), wp, wn, _ptr(loss, "loss", torch.float64, (1,)), _stream(stream)))
+
+
+def md_adjoint_seed(p: MDParams, ws, scale: float, lam_r4, lam_v4, theta=None, stream=None):
+    """Seed the backward pass from scale * md_loss at the workspace (final) state."""
+    import torch
+
+    wp, wn = _ws(ws)
+    _check(lib().md_adjoint_seed(ctypes.byref(p), wp, wn, float(scale), _ptr(lam_r4, "lam_r4", torch.float32, (p.n, 4)),
+                                 _ptr(lam_v4, "lam_v4", torch.float32, (p.n, 4)),
+                                 _ptr(theta, "theta", torch.float64, (2,)), _stream(stream)))

@@ -1,11 +1,12 @@
 """Differentiating an LJ velocity-Verlet trajectory through the HIP library.
 
 `LJTrajectory` is a torch.autograd.Function: its forward advances a state T
-steps with md_step and returns L = K_T / N + W_T / (3 V) (mean kinetic energy
-per particle plus the virial part of the pressure, FP64); its backward runs
-the discrete adjoint of velocity Verlet with the library's kick and drift
-adjoints, recomputing each segment of `every` steps from a checkpoint
-(positions and velocities saved every `every` steps in the forward).
+steps with md_step and returns the library's md_loss, L = K_T / N +
+W_T / (3 V) (mean kinetic energy per particle plus the virial part of the
+pressure, FP64); its backward seeds the adjoint with md_adjoint_seed and runs
+the discrete adjoint of velocity Verlet with md_adjoint_segment, recomputing
+each segment of `every` steps from a checkpoint (positions and velocities
+saved every `every` steps in the forward).
 
 With h = dt / (2 m), one Verlet step is v' = v + h F(r), r' = r + dt v',
 v'' = v' + h F(r'). Its transpose, applied from the last step back, is a kick
@@ -31,7 +32,6 @@ class _Runner:
         self.n = int(n)
         self.box = float(box)
         self.p = L.make_params(n, box, float(eps), float(sigma), mass, 2.5, dt)
-        self.h = 0.5 * float(dt) / float(mass)
         self.dev = device
         self.ws = torch.empty(L.md_workspace_bytes(self.p), dtype=torch.uint8, device=device)
 
@@ -51,18 +51,16 @@ def _forward(run: _Runner, pos4, vel4, nsteps, every):
         ckpts.append((done, k, cp, cv))
         L.md_step(run.p, run.ws, k)
         done += k
-    e = torch.empty(3, dtype=torch.float64, device=run.dev)
-    L.md_energy_virial(run.p, run.ws, e)
-    loss = e[1] / run.n + e[2] / (3.0 * run.box ** 3)
-    return loss, ckpts
+    loss = torch.empty(1, dtype=torch.float64, device=run.dev)
+    L.md_loss(run.p, run.ws, loss)
+    return loss[0], ckpts
 
 
 def _backward(run: _Runner, ckpts, gl: float, every):
     lam_r, lam_v = run.vec(), run.vec()
     theta = torch.zeros(2, dtype=torch.float64, device=run.dev)
     # the workspace still holds the final state r_T, v_T
-    L.md_loss_grad(run.p, run.ws, gl / run.n, gl / (3.0 * run.box ** 3), lam_r, lam_v, theta)
-    L.md_adjoint_kick(run.p, run.ws, lam_v, lam_r, theta, run.h)
+    L.md_adjoint_seed(run.p, run.ws, gl, lam_r, lam_v, theta)
     path = torch.empty((every, run.n, 4), dtype=torch.float32, device=run.dev)
     nc, _ = L.md_cell_grid(run.p)
     path_start = torch.empty((every, nc ** 3 + 1), dtype=torch.int32, device=run.dev)

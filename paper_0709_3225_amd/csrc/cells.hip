@@ -38,6 +38,8 @@ __global__ void __launch_bounds__(kBlock) k_build_init(SimArgs a) {
         a.hdr[HDR_NC] = a.nc;
         a.hdr[HDR_OVF] = 0;
         a.hdr[HDR_OVF + 1] = 0;
+        a.hdr[HDR_OVFA] = 0;
+        a.hdr[HDR_OVFA + 1] = 0;
     }
     for (int c = t; c < (a.nblocks << kBlockShift); c += stride) a.counts[c] = 0;
     for (int b = t; b < 2 * a.nbstride; b += stride) a.bcounts[b] = 0;
@@ -50,7 +52,10 @@ __global__ void k_set_state(SimArgs a, int state) {
 // Clear the counters of parity par (overflow count, block histogram).
 __global__ void __launch_bounds__(kBlock) k_zero_blocks(SimArgs a, int par) {
     const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t == 0) a.hdr[HDR_OVF + par] = 0;
+    if (t == 0) {
+        a.hdr[HDR_OVF + par] = 0;
+        a.hdr[HDR_OVFA + par] = 0;
+    }
     for (int b = t; b < a.nbstride; b += gridDim.x * kBlock) a.bcounts[par * a.nbstride + b] = 0;
 }
 
@@ -245,34 +250,30 @@ constexpr int kOrderCells = kOrderBlock / kOrderGroup;
 constexpr int kNoId = 0x7fffffff;  // larger than any user index
 
 // Member m of cell c: bucket entry m, or past the capacity the cell's
-// (m - cap)-th entry of the overflow list (rare: a cell beyond its
-// capacity). Returns the overflow index, or -1 for a bucket entry.
-__device__ __forceinline__ int overflow_entry(const SimArgs& a, int c, int m, int novf) {
-    int want = m - a.cap;
-    for (int j = 0; j < novf; ++j) {
-        if (a.ovf_cell[j] == c) {
-            if (want == 0) return j;
-            --want;
-        }
-    }
-    return 0;  // not reached while the histogram and the list agree
+// (m - cap)-th overflow entry, found through the per-cell overflow index the
+// workgroup built (ovf0: the cell's first slot there). Both indices are
+// clamped to the arrays: a histogram and list that disagree (a call sequence
+// cut short, reported as DEV_ORDER) give a wrong but in-bounds member.
+__device__ __forceinline__ int overflow_slot(const SimArgs& a, int m, int ovf0) {
+    const int k = min(ovf0 + m - a.cap, a.natoms - 1);
+    return min(max(a.ovf_idx[k], 0), a.natoms - 1);
 }
 
-__device__ __forceinline__ void load_member(const SimArgs& a, int c, int m, int novf, float4& p, float4& v) {
+__device__ __forceinline__ void load_member(const SimArgs& a, int c, int m, int ovf0, float4& p, float4& v) {
     if (m < a.cap) {
         const size_t e = static_cast<size_t>(c) * a.cap + m;
         p = a.bpos[e];
         v = a.bvel[e];
     } else {
-        const int j = overflow_entry(a, c, m, novf);
+        const int j = overflow_slot(a, m, ovf0);
         p = a.pos1[j];
         v = a.vel1[j];
     }
 }
 
-__device__ __forceinline__ int member_id(const SimArgs& a, int c, int m, int n, int novf) {
+__device__ __forceinline__ int member_id(const SimArgs& a, int c, int m, int n, int ovf0) {
     if (m >= n) return kNoId;
-    const float4 p = m < a.cap ? a.bpos[static_cast<size_t>(c) * a.cap + m] : a.pos1[overflow_entry(a, c, m, novf)];
+    const float4 p = m < a.cap ? a.bpos[static_cast<size_t>(c) * a.cap + m] : a.pos1[overflow_slot(a, m, ovf0)];
     return __float_as_int(p.w);
 }
 
@@ -285,6 +286,7 @@ __global__ void __launch_bounds__(kOrderBlock) k_cell_order(SimArgs a, bool from
     __shared__ int4 win[kOrderCells][kOrderWin / 4];
     __shared__ int cnt_s[kOrderCells];
     __shared__ int part_s[kOrderBlock / kWave];
+    __shared__ int ovf_base_s;
     const int err = a.hdr[HDR_ERROR];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int cl = tid / kOrderGroup, sub = tid & (kOrderGroup - 1);
@@ -341,14 +343,45 @@ __global__ void __launch_bounds__(kOrderBlock) k_cell_order(SimArgs a, bool from
     }
     // the other parity's counters, for the next build
     if (a.direct && tid == 0) a.bcounts[(1 - a.par) * a.nbstride + blk] = 0;
-    if (blockIdx.x == 0 && tid == 0) a.hdr[HDR_OVF + 1 - a.par] = 0;
+    if (blockIdx.x == 0 && tid == 0) {
+        a.hdr[HDR_OVF + 1 - a.par] = 0;
+        a.hdr[HDR_OVFA + 1 - a.par] = 0;
+    }
+    // Cells past the bucket capacity (rare): the workgroup takes a range of
+    // the overflow index, scans the overflow list once and files each entry of
+    // its cells under (cell, overflow rank), so that a member past the
+    // capacity is one indexed load away, at any cell size.
+    int ovf0 = 0;
+    if (nmax > a.cap) {  // uniform over the workgroup
+        int before = 0, ovf_tot = 0;
+#pragma unroll
+        for (int j = 0; j < kOrderCells; ++j) {
+            const int e = max(0, cnt_s[j] - a.cap);
+            if (j < cl) before += e;
+            ovf_tot += e;
+        }
+        if (tid == 0) ovf_base_s = atomicAdd(&a.hdr[HDR_OVFA + a.par], ovf_tot);
+        __syncthreads();
+        const int base = ovf_base_s;
+        ovf0 = base + before;
+        for (int j = tid; j < novf; j += kOrderBlock) {
+            const int cj = a.ovf_cell[j];
+            if (cj < c0 || cj >= c0 + kOrderCells) continue;
+            int off = base;
+            for (int q = 0; q < cj - c0; ++q) off += max(0, cnt_s[q] - a.cap);
+            const int slot = off + a.ovf_rank[j];
+            if (slot >= 0 && slot < a.natoms) a.ovf_idx[slot] = j;
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
     int* wids = reinterpret_cast<int*>(win[cl]);
     for (int m0 = 0; m0 < nmax; m0 += kOrderWin) {
         const int ma = m0 + sub, mb = ma + kOrderGroup;
         float4 pa = pa0, va = va0, pb = pb0, vb = vb0;
         if (m0 > 0) {
-            if (ma < n) load_member(a, c, ma, novf, pa, va);
-            if (mb < n) load_member(a, c, mb, novf, pb, vb);
+            if (ma < n) load_member(a, c, ma, ovf0, pa, va);
+            if (mb < n) load_member(a, c, mb, ovf0, pb, vb);
         }
         const int ida = ma < n ? __float_as_int(pa.w) : kNoId;
         const int idb = mb < n ? __float_as_int(pb.w) : kNoId;
@@ -356,8 +389,8 @@ __global__ void __launch_bounds__(kOrderBlock) k_cell_order(SimArgs a, bool from
         for (int k0 = 0; k0 < nmax; k0 += kOrderWin) {
             int ka = ida, kb = idb;
             if (k0 != m0) {
-                ka = member_id(a, c, k0 + sub, n, novf);
-                kb = member_id(a, c, k0 + kOrderGroup + sub, n, novf);
+                ka = member_id(a, c, k0 + sub, n, ovf0);
+                kb = member_id(a, c, k0 + kOrderGroup + sub, n, ovf0);
             }
             __syncthreads();  // the previous window has been read
             wids[sub] = ka;

@@ -395,7 +395,10 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ e, int n
         }
     }
 }
-__global__ void __launch_bounds__(kRedBlock) k_energy_final(SimArgs a, double* out3, bool from_step) {
+// LOSS: out3[0] = kcoef K + wcoef W instead of (U, K, W).
+template <bool LOSS>
+__global__ void __launch_bounds__(kRedBlock) k_energy_final(SimArgs a, double* out3, bool from_step, double kcoef,
+                                                            double wcoef) {
     if (from_step && (a.hdr[HDR_ERROR] & DEV_ORDER)) return;
     __shared__ double su[kRedBlock], sw[kRedBlock], sk[kRedBlock];
     const int t = threadIdx.x;
@@ -414,9 +417,13 @@ __global__ void __launch_bounds__(kRedBlock) k_energy_final(SimArgs a, double* o
         __syncthreads();
     }
     if (t == 0) {
-        out3[0] = 0.5 * su[0];
-        out3[1] = sk[0];
-        out3[2] = 0.5 * sw[0];
+        if (LOSS) {
+            out3[0] = kcoef * sk[0] + wcoef * (0.5 * sw[0]);
+        } else {
+            out3[0] = 0.5 * su[0];
+            out3[1] = sk[0];
+            out3[2] = 0.5 * sw[0];
+        }
     }
 }
 
@@ -558,7 +565,12 @@ hipError_t launch_forces_list(const SimArgs& a_in, bool energy, bool record, boo
 }
 
 hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st) {
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kRedBlock), 0, st, a, out3, true);
+    hipLaunchKernelGGL(k_energy_final<false>, dim3(1), dim3(kRedBlock), 0, st, a, out3, true, 0.0, 0.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_final(const SimArgs& a, double kcoef, double wcoef, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_energy_final<true>, dim3(1), dim3(kRedBlock), 0, st, a, out, true, kcoef, wcoef);
     return hipGetLastError();
 }
 

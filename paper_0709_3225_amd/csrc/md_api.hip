@@ -55,7 +55,7 @@ md_status validate(const md_params* p) {
     if (!(std::isfinite(p->cell_min) && p->cell_min >= 0.f))
         return fail(MD_ERR_ARG, "cell_min must be finite and >= 0");
     if (p->shift_mode != 0 && p->shift_mode != 1) return fail(MD_ERR_ARG, "shift_mode must be 0 or 1");
-    if (p->flags != 0) return fail(MD_ERR_ARG, "flags must be 0");
+    if ((p->flags & ~MD_FLAG_PAIR_LISTS) != 0) return fail(MD_ERR_ARG, "flags hold unknown bits 0x%x", p->flags);
     const float rc = cutoff(p);
     if (!(rc > 0.f) || !std::isfinite(rc)) return fail(MD_ERR_ARG, "cutoff must be finite and > 0");
     if (!(p->box >= 2.0f * rc)) return fail(MD_ERR_BOX, "box %g is shorter than two cutoffs (2 * %g)", p->box, rc);
@@ -99,6 +99,8 @@ void take_build_arrays(Layout& L, size_t n, size_t ncells, int cap, Take& take) 
     L.bpos = take(16 * ncells * static_cast<size_t>(cap));
     L.bvel = take(16 * ncells * static_cast<size_t>(cap));
     L.ovf_cell = take(4 * n);
+    L.ovf_rank = take(4 * n);
+    L.ovf_idx = take(4 * n);
     L.start = take(4 * (ncells + 1) + 16);
 }
 
@@ -128,9 +130,11 @@ md_status make_layout(const md_params* p, Layout& L) {
     L.force = take(16 * n);
     L.pos2 = take(16 * n);
     L.vel2 = take(16 * n);
-    L.posref = take(16 * n);
-    L.plist = take(16 * static_cast<size_t>(L.ncells) * kWaveLanes * kListSpans);
-    L.plist_n = take(4 * static_cast<size_t>(L.ncells) * kWaveLanes);
+    if (p->flags & MD_FLAG_PAIR_LISTS) {  // md_step_list's arrays, only where asked for
+        L.posref = take(16 * n);
+        L.plist = take(16 * static_cast<size_t>(L.ncells) * kWaveLanes * kListSpans);
+        L.plist_n = take(4 * static_cast<size_t>(L.ncells) * kWaveLanes);
+    }
     take_build_arrays(L, n, static_cast<size_t>(L.ncells), bucket_capacity(static_cast<double>(p->n) / L.ncells),
                       take);
     L.epart = take(sizeof(double) * 3 * static_cast<size_t>(L.nforce_blocks));
@@ -182,6 +186,8 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     a.bpos = reinterpret_cast<float4*>(b + L.bpos);
     a.bvel = reinterpret_cast<float4*>(b + L.bvel);
     a.ovf_cell = reinterpret_cast<int*>(b + L.ovf_cell);
+    a.ovf_rank = reinterpret_cast<int*>(b + L.ovf_rank);
+    a.ovf_idx = reinterpret_cast<int*>(b + L.ovf_idx);
     a.start = reinterpret_cast<int*>(b + L.start);
     a.nblocks = L.nblocks;
     a.cap = L.cap;
@@ -230,6 +236,15 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     return a;
 }
 
+// The trajectory loss of the adjoint: L = K / N + W / (3 V), the mean kinetic
+// energy per particle plus the virial part of the pressure; scale * L has
+// coefficients kc on K and wc on W.
+void loss_coefficients(const md_params* p, double scale, double& kc, double& wc) {
+    const double box = p->box;
+    kc = scale / static_cast<double>(p->n);
+    wc = scale / (3.0 * box * box * box);
+}
+
 #define MD_TRY_HIP(expr, where)                  \
     do {                                         \
         hipError_t e_ = (expr);                  \
@@ -242,6 +257,38 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
 md_status rebuild(const SimArgs& a, int par, bool from_step, hipStream_t st) {
     if (!a.direct) MD_TRY_HIP(launch_block_scan(a, from_step, st), "block scan");
     MD_TRY_HIP(launch_cell_order(a, par, from_step, st), "cell order");
+    return MD_OK;
+}
+
+// Load a state and build its cell list (md_build_cells after validation).
+md_status build_cells_impl(const SimArgs& a, const float4* pos4, const float4* vel4, hipStream_t stream) {
+    MD_TRY_HIP(launch_build_init(a, stream), "build init");
+    MD_TRY_HIP(launch_load(a, pos4, vel4, stream), "load");
+    md_status s = rebuild(a, 0, false, stream);
+    if (s != MD_OK) return s;
+    MD_TRY_HIP(launch_zero_blocks(a, 0, stream), "counter clear");
+    return MD_OK;
+}
+
+// nsteps fused velocity-Verlet steps (md_step after validation).
+md_status steps_impl(const SimArgs& a, int32_t nsteps, int32_t thermo_every, double* thermo, hipStream_t stream) {
+    // The force pass of every step but the last also performs the next step's
+    // half kick, drift and binning, so the drift kernel runs only on the first
+    // step; a rebuild is then the block scan (large grids) and the cell order.
+    // Step k's atoms are binned with parity (k - 1) mod 2; the counters of
+    // both parities are zero again on return.
+    for (int32_t k = 1; k <= nsteps; ++k) {
+        const bool energy = thermo && thermo_every > 0 && (k % thermo_every) == 0;
+        const bool last = k == nsteps;
+        if (k == 1) MD_TRY_HIP(launch_integrate(a, stream), "integrate");
+        md_status s = rebuild(a, (k - 1) & 1, true, stream);
+        if (s != MD_OK) return s;
+        MD_TRY_HIP(launch_forces(a, true, energy, last, true, !last, k & 1, stream), "forces");
+        if (energy)
+            MD_TRY_HIP(launch_energy_final(a, thermo + 3 * static_cast<size_t>(k / thermo_every - 1), stream),
+                       "energy");
+    }
+    if (nsteps > 0) MD_TRY_HIP(launch_zero_blocks(a, (nsteps - 1) & 1, stream), "counter clear");
     return MD_OK;
 }
 
@@ -260,7 +307,7 @@ struct TileClass {
 };
 
 struct BatchPlan {
-    Layout L;                    // shared arrays; n = total atoms, ncells = total cells
+    Layout L{};                  // shared arrays; n = total atoms, ncells = total cells (unused offsets 0)
     int count = 0;
     double max_mean = 0.0;  // largest mean cell occupancy of any replica
     size_t reps = 0, atom_rep = 0, cell_rep = 0, class_cells = 0;
@@ -451,12 +498,7 @@ md_status md_build_cells(const md_params* p, void* ws, size_t ws_bytes, const fl
     if (!pos4) return fail(MD_ERR_ARG, "positions are NULL");
     if (!aligned16(pos4) || (vel4 && !aligned16(vel4))) return fail(MD_ERR_ARG, "particle arrays must be 16-byte aligned");
     const SimArgs a = make_args(p, L, ws);
-    MD_TRY_HIP(launch_build_init(a, stream), "build init");
-    MD_TRY_HIP(launch_load(a, reinterpret_cast<const float4*>(pos4), reinterpret_cast<const float4*>(vel4), stream),
-               "load");
-    if ((s = rebuild(a, 0, false, stream)) != MD_OK) return s;
-    MD_TRY_HIP(launch_zero_blocks(a, 0, stream), "counter clear");
-    return MD_OK;
+    return build_cells_impl(a, reinterpret_cast<const float4*>(pos4), reinterpret_cast<const float4*>(vel4), stream);
 }
 
 md_status md_forces(const md_params* p, void* ws, size_t ws_bytes, float* force4, hipStream_t stream) {
@@ -480,24 +522,7 @@ md_status md_step(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps,
     if (nsteps < 0) return fail(MD_ERR_ARG, "nsteps must be >= 0");
     if (thermo_every < 0) return fail(MD_ERR_ARG, "thermo_every must be >= 0");
     if (thermo_every > 0 && !thermo) return fail(MD_ERR_ARG, "thermo_every > 0 needs a thermo buffer");
-    const SimArgs a = make_args(p, L, ws);
-    // The force pass of every step but the last also performs the next step's
-    // half kick, drift and binning, so the drift kernel runs only on the first
-    // step; a rebuild is then the block scan (large grids) and the cell order.
-    // Step k's atoms are binned with parity (k - 1) mod 2; the counters of
-    // both parities are zero again on return.
-    for (int32_t k = 1; k <= nsteps; ++k) {
-        const bool energy = thermo && thermo_every > 0 && (k % thermo_every) == 0;
-        const bool last = k == nsteps;
-        if (k == 1) MD_TRY_HIP(launch_integrate(a, stream), "integrate");
-        if ((s = rebuild(a, (k - 1) & 1, true, stream)) != MD_OK) return s;
-        MD_TRY_HIP(launch_forces(a, true, energy, last, true, !last, k & 1, stream), "forces");
-        if (energy)
-            MD_TRY_HIP(launch_energy_final(a, thermo + 3 * static_cast<size_t>(k / thermo_every - 1), stream),
-                       "energy");
-    }
-    if (nsteps > 0) MD_TRY_HIP(launch_zero_blocks(a, (nsteps - 1) & 1, stream), "counter clear");
-    return MD_OK;
+    return steps_impl(make_args(p, L, ws), nsteps, thermo_every, thermo, stream);
 }
 
 md_status md_step_every(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps, int32_t rebuild_every,
@@ -558,6 +583,8 @@ md_status md_step_list(const md_params* p, void* ws, size_t ws_bytes, int32_t ns
     if (rebuild_every < 1) return fail(MD_ERR_ARG, "rebuild_every must be >= 1");
     if (thermo_every < 0) return fail(MD_ERR_ARG, "thermo_every must be >= 0");
     if (thermo_every > 0 && !thermo) return fail(MD_ERR_ARG, "thermo_every > 0 needs a thermo buffer");
+    if (!(p->flags & MD_FLAG_PAIR_LISTS))
+        return fail(MD_ERR_ARG, "md_step_list needs a workspace laid out with MD_FLAG_PAIR_LISTS");
     const SimArgs a = make_args(p, L, ws);
     SimArgs alt = a;
     std::swap(alt.pos0, alt.pos2);
@@ -750,6 +777,45 @@ md_status md_loss_grad(const md_params* p, void* ws, size_t ws_bytes, float k_co
     MD_TRY_HIP(launch_loss_grad(a, k_coef, w_coef, reinterpret_cast<float4*>(g_r4), reinterpret_cast<float4*>(g_v4),
                                 theta, stream),
                "loss gradient");
+    return MD_OK;
+}
+
+md_status md_loss(const md_params* p, void* ws, size_t ws_bytes, double* loss, hipStream_t stream) {
+    Layout L{};
+    md_status s = make_layout(p, L);
+    if (s != MD_OK) return s;
+    if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
+    if (!loss) return fail(MD_ERR_ARG, "loss output is NULL");
+    const SimArgs a = make_args(p, L, ws);
+    double kc, wc;
+    loss_coefficients(p, 1.0, kc, wc);
+    MD_TRY_HIP(launch_forces(a, false, true, false, false, false, 0, stream), "energy pass");
+    MD_TRY_HIP(launch_loss_final(a, kc, wc, loss, stream), "loss");
+    return MD_OK;
+}
+
+md_status md_adjoint_seed(const md_params* p, void* ws, size_t ws_bytes, float scale, float* lam_r4, float* lam_v4,
+                          double* theta, hipStream_t stream) {
+    Layout L{};
+    md_status s = make_layout(p, L);
+    if (s != MD_OK) return s;
+    if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
+    if (p->shift_mode != 0) return fail(MD_ERR_ARG, "the adjoint needs shift_mode 0 (force shift)");
+    if (!lam_r4 || !lam_v4) return fail(MD_ERR_ARG, "adjoint vectors are NULL");
+    if (!aligned16(lam_r4) || !aligned16(lam_v4)) return fail(MD_ERR_ARG, "adjoint vectors must be 16-byte aligned");
+    if (lam_r4 == lam_v4) return fail(MD_ERR_ARG, "lam_r and lam_v must not alias");
+    if (!std::isfinite(scale)) return fail(MD_ERR_ARG, "scale must be finite");
+    const SimArgs a = make_args(p, L, ws);
+    double kc, wc;
+    loss_coefficients(p, scale, kc, wc);
+    // lam = scale dL/d(r, v) at the final state, then the kick adjoint that
+    // ends the last step (coefficient dt / 2m)
+    MD_TRY_HIP(launch_loss_grad(a, static_cast<float>(kc), static_cast<float>(wc), reinterpret_cast<float4*>(lam_r4),
+                                reinterpret_cast<float4*>(lam_v4), theta, stream),
+               "loss gradient");
+    MD_TRY_HIP(launch_adjoint_kick(a, reinterpret_cast<const float4*>(lam_v4), reinterpret_cast<float4*>(lam_r4), theta,
+                                   a.hdt_m, stream),
+               "adjoint kick");
     return MD_OK;
 }
 

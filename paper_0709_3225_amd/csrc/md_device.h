@@ -103,6 +103,7 @@ __device__ __forceinline__ void bin_atom(const SimArgs& a, float4 p, float4 v, i
         const int j = atomicAdd(&a.hdr[HDR_OVF + a.par], 1);
         if (j < a.natoms) {
             a.ovf_cell[j] = c;
+            a.ovf_rank[j] = r - a.cap;
             a.pos1[j] = p;
             a.vel1[j] = v;
         } else {

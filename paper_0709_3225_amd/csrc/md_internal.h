@@ -13,8 +13,9 @@ namespace mdlj {
 // built for; kernels refuse a workspace whose record differs from their
 // arguments (its array offsets would not match).
 // HDR_OVF + p counts the overflow-list entries of a build binned with parity
-// p (p = 0, 1; the same alternation as the block histograms).
-enum : int { HDR_ERROR = 0, HDR_STATE = 1, HDR_N = 2, HDR_NC = 3, HDR_OVF = 4, HDR_WORDS = 64 };
+// p (p = 0, 1; the same alternation as the block histograms); HDR_OVFA + p
+// hands out index ranges of that list's per-cell index to the cell order.
+enum : int { HDR_ERROR = 0, HDR_STATE = 1, HDR_N = 2, HDR_NC = 3, HDR_OVF = 4, HDR_OVFA = 6, HDR_WORDS = 64 };
 
 // Workspace states. Distinctive values so that an uninitialised workspace is
 // never mistaken for a built one.
@@ -71,6 +72,8 @@ struct SimArgs {
     float4* bpos;    // ncells x cap bucket entries (w = user index bits)
     float4* bvel;
     int* ovf_cell;   // cell of overflow entry j, one entry per atom at most
+    int* ovf_rank;   // its rank among its cell's overflow entries (histogram rank - cap)
+    int* ovf_idx;    // the cell order's per-cell index of the overflow entries
     int* start;      // per-cell CSR offsets, ncells + 1 entries
     double* epart;   // per-block energy partials, 3 doubles per force block
     int nblocks, cap, natoms;  // natoms: all atoms of the workspace
@@ -114,7 +117,8 @@ struct Layout {
     float s, inv_s;
     int nblocks, cap;
     int nbstride;
-    size_t hdr, pos0, vel0, pos1, vel1, force, pos2, vel2, posref, plist, plist_n, counts, bstart, bcounts, bpos, bvel, ovf_cell, start, epart, total;
+    size_t hdr, pos0, vel0, pos1, vel1, force, pos2, vel2, posref, plist, plist_n, counts, bstart, bcounts, bpos, bvel,
+        ovf_cell, ovf_rank, ovf_idx, start, epart, total;
 };
 
 // Kernel launchers (each returns hipGetLastError() after its launch).
@@ -135,6 +139,8 @@ hipError_t launch_forces_skin(const SimArgs& a, bool energy, hipStream_t st);
 // lists; the drift bins for a rebuild (bin) or goes to pos2/vel2.
 hipError_t launch_forces_list(const SimArgs& a, bool energy, bool record, bool bin, int par, hipStream_t st);
 hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st);
+// out[0] = kcoef K + wcoef W from the partials of an energy pass.
+hipError_t launch_loss_final(const SimArgs& a, double kcoef, double wcoef, double* out, hipStream_t st);
 hipError_t launch_gather_user(const SimArgs& a, float4* pos_out, float4* vel_out, float4* force_out,
                               hipStream_t st);
 hipError_t launch_neighbors(const SimArgs& a, int* counts, int* idx, int max_per_atom,

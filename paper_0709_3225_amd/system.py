@@ -23,8 +23,9 @@ class LJSystem:
     """Cubic periodic LJ system of n particles in a box of side ``box``."""
 
     def __init__(self, n, box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_over_sigma=2.5, dt=0.005,
-                 cell_min=0.0, shift_mode=0, device="cuda"):
-        self.params = L.make_params(n, box, epsilon, sigma, mass, rc_over_sigma, dt, cell_min, shift_mode)
+                 cell_min=0.0, shift_mode=0, pair_lists=False, device="cuda"):
+        flags = L.MD_FLAG_PAIR_LISTS if pair_lists else 0
+        self.params = L.make_params(n, box, epsilon, sigma, mass, rc_over_sigma, dt, cell_min, shift_mode, flags)
         self.cells_per_dim, self.cell_side = L.md_cell_grid(self.params)  # raises on invalid params
         self.nbytes = L.md_workspace_bytes(self.params)
         self.device = torch.device(device)
@@ -65,7 +66,7 @@ class LJSystem:
 
     def step_list(self, nsteps: int, rebuild_every: int, thermo_every: int = 0):
         """md_step_list: as step_every, with pair lists recorded at each
-        rebuild and walked in between."""
+        rebuild and walked in between (needs ``pair_lists=True``)."""
         thermo = None
         if thermo_every > 0 and nsteps >= thermo_every:
             thermo = torch.empty((nsteps // thermo_every, 3), dtype=torch.float64, device=self.device)

@@ -69,6 +69,8 @@ def _time_probe(n, box, cell_min, p4, v4, copies, steps, warmup, repeats, shared
     pos = p4.repeat(copies, 1).contiguous()
     vel = v4.repeat(copies, 1).contiguous()
     events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(repeats)]
+    # the copies above (and the workspace) were made on the caller's stream
+    stream.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(stream):
         b.load(pos, vel)
         b.step(warmup)

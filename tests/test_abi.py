@@ -74,7 +74,7 @@ def test_cell_min_parameter():
     (dict(mass=float("inf")), _lib.MD_ERR_ARG),
     (dict(dt=-0.1), _lib.MD_ERR_ARG),
     (dict(shift_mode=2), _lib.MD_ERR_ARG),
-    (dict(flags=1), _lib.MD_ERR_ARG),
+    (dict(flags=2), _lib.MD_ERR_ARG),
     (dict(rc_over_sigma=float("nan")), _lib.MD_ERR_ARG),
 ])
 def test_invalid_params_rejected_on_host(kw, code):
@@ -114,6 +114,24 @@ def test_workspace_and_pointer_checks_on_host():
     assert lib.md_neighbors(ctypes.byref(p), fake, need, fake, fake, 0, None) == _lib.MD_ERR_ARG
     assert lib.md_check(None, 0, None, None) == _lib.MD_ERR_WORKSPACE
     assert b"workspace" in lib.md_last_error()
+    assert lib.md_loss(ctypes.byref(p), fake, need, None, None) == _lib.MD_ERR_ARG
+    assert lib.md_adjoint_seed(ctypes.byref(p), fake, need, ctypes.c_float(1.0), fake, fake, None, None) \
+        == _lib.MD_ERR_ARG  # the two adjoint vectors alias
+
+
+def test_pair_list_arrays_only_on_request():
+    """md_step_list's arrays are laid out only with MD_FLAG_PAIR_LISTS, and
+    md_step_list refuses a workspace without them (host check)."""
+    import ctypes
+
+    lib = _lib.lib()
+    plain = md.make_params(256000, 67.18385)
+    lists = md.make_params(256000, 67.18385, flags=_lib.MD_FLAG_PAIR_LISTS)
+    b0, b1 = md.md_workspace_bytes(plain), md.md_workspace_bytes(lists)
+    assert b1 - b0 > 4096 * 26 ** 3  # about 4.3 KB per cell of accept words
+    fake = ctypes.c_void_p(1 << 40)
+    assert lib.md_step_list(ctypes.byref(plain), fake, b0, 4, 2, 0, None, None) == _lib.MD_ERR_ARG
+    assert b"MD_FLAG_PAIR_LISTS" in lib.md_last_error()
 
 
 def test_status_names():
@@ -185,3 +203,4 @@ def test_grid_options_and_buckets():
     assert [nc for nc, _ in grid_options(256000, Ls)] == [54, 53, 26]
     assert bucket_key(4000, 7) == (7, 12)
     assert bucket_key(4000, 7) == bucket_key(4100, 7)
+

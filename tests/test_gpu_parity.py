@@ -4,10 +4,15 @@ Tolerances: forces within 1e-5 relative L2 (over all 3N components), energy
 and virial within 1e-6 relative, neighbour sets identical. Every case names
 itself on stdout before it touches the GPU.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
 import ljsynth
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 pytestmark = pytest.mark.gpu
 
@@ -113,6 +118,32 @@ def test_energy_shift_mode(mode, orc):
     assert rel_l2(f, fo) <= FORCE_TOL
     assert abs(e[0] - U) <= ENERGY_TOL * abs(U)
     assert abs(e[2] - W) <= ENERGY_TOL * abs(W)
+
+
+def test_energy_shift_mode_cutoff_sensitive_lj32k(orc):
+    """With the plain truncated force (shift_mode 1) every pair dropped or
+    added near r_c moves the force by |f_LJ(r_c)| = 0.039, far above the
+    1e-5 gate: the whole N = 32,000 system (mostly cells of 11..16 atoms,
+    screened on the matrix cores) against the oracle."""
+    pos4, vel4, box = ljsynth.make_state(ljsynth.WORKLOADS["lj32k_adjoint"], jitter_amp=0.05)
+    _say("shift_mode=1 lj32k whole system")
+    _, f, e = gpu_forces(pos4, box, shift_mode=1)
+    fo, U, W = orc.forces(orc.params(box, shift_mode=1), pos4)
+    assert rel_l2(f, fo) <= FORCE_TOL
+    assert abs(e[0] - U) <= ENERGY_TOL * abs(U)
+    assert abs(e[2] - W) <= ENERGY_TOL * abs(W)
+
+
+def test_energy_shift_mode_sampled_rows_lj256k(orc):
+    """shift_mode 1 at N = 256,000: 2,048 sampled rows against the oracle's
+    rows, each the full sum over all N atoms."""
+    w = ljsynth.WORKLOADS["lj256k"]
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05)
+    _say("shift_mode=1 lj256k sampled rows")
+    _, f, _ = gpu_forces(pos4, box, shift_mode=1)
+    sel = np.random.default_rng(18).choice(w.n, size=2048, replace=False)
+    fo, _, _ = orc.forces_rows(orc.params(box, shift_mode=1), pos4, sel)
+    assert rel_l2(f[sel], fo) <= FORCE_TOL
 
 
 @pytest.mark.parametrize("case", ["lj4k_jitter_shuffled", "lj256_two_cells", "fluid_rho0.4_ragged", "dense_clump"])
@@ -221,12 +252,69 @@ def test_bucket_overflow_build_and_steps(box, n_gas, orc):
     _check_cell_lists(p3, box)
 
 
-def test_fcc_lattice_energy_pin():
+@pytest.mark.parametrize("name", ["lj4k", "lj256k", "lj2m"])
+def _one_crowded_cell(seed=33):
+    """4,096 atoms in one cell: a 16^3 simple-cubic block of spacing 15/16
+    sigma, jittered by up to 0.09 sigma, filling the first of 27 cells of side
+    16 sigma (box 48, cell_min 15.9), plus a dilute gas around it. The bucket
+    capacity follows the mean occupancy (about 170 atoms per cell), so some
+    3,900 atoms of that cell go through the overflow list on every build."""
+    rng = np.random.default_rng(seed)
+    g = 0.5 + (15.0 / 16.0) * np.arange(16)
+    block = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    block = block + rng.uniform(-0.09, 0.09, block.shape)
+    gas = rng.uniform(17.0, 47.0, (600, 3))
+    keep = [q for i, q in enumerate(gas)
+            if (np.einsum("ij,ij->i", gas[:i] - q, gas[:i] - q) >= 1.0).all()]
+    pts = np.concatenate([block, np.asarray(keep)])
+    pos4 = np.zeros((len(pts), 4), np.float32)
+    pos4[:, :3] = pts
+    vel4 = np.zeros_like(pos4)
+    vel4[:, :3] = rng.normal(0.0, 0.3, (len(pts), 3))
+    return pos4, vel4, np.float32(48.0)
+
+
+def test_crowded_cell_builds_in_linear_time(orc):
+    """A cell holding 4,096 atoms: its members past the bucket capacity are
+    found through the per-cell overflow index, so a build, a force pass and
+    three rebuilding steps finish in well under 5 s (the search of the whole
+    overflow list for every member took minutes here); cell lists stay a
+    valid counting sort and forces match the oracle."""
+    import time
+
+    torch = _torch()
+    pos4, vel4, box = _one_crowded_cell()
+    _say(f"crowded cell n={len(pos4)} box={box}")
+    s = _system(len(pos4), box, cell_min=15.9, dt=1e-4)
+    assert s.cells_per_dim == 3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.load(_dev(pos4), _dev(vel4))
+    s.step(3)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    assert s.check() == 0
+    assert elapsed < 5.0, elapsed
+    pos, _ = s.state()
+    p3 = pos.cpu().numpy()
+    f = s.forces().cpu().numpy()[:, :3]
+    assert s.check() == 0
+    fo, _, _ = orc.forces(orc.params(box), p3)
+    assert rel_l2(f, fo) <= FORCE_TOL
+    start, order = s.cell_lists()
+    start = start.cpu().numpy()
+    assert np.diff(start).max() == 4096
+    assert np.array_equal(np.sort(order.cpu().numpy()), np.arange(len(pos4)))
+
+
+def test_fcc_lattice_energy_pin(name):
     """Perfect FCC at rho = 0.8442: U/N = -5.693278, W/N = -20.16527 from the
-    textbook shells, with no oracle in the loop."""
-    w = ljsynth.WORKLOADS["lj4k"]
+    textbook shells (12, 6, 24, 12 sites inside r_c), with no oracle in the
+    loop; every atom has the same environment, so the FP64 totals of the full
+    systems must give these per-atom values to 1e-6."""
+    w = ljsynth.WORKLOADS[name]
     pos4, vel4, box = ljsynth.make_state(w)
-    _say("fcc lattice pin lj4k")
+    _say(f"fcc lattice pin {name} n={w.n}")
     _, f, e = gpu_forces(pos4, box)
     assert e[0] / w.n == pytest.approx(-5.693278, rel=1e-6)
     assert e[2] / w.n == pytest.approx(-20.16527, rel=1e-6)
@@ -350,9 +438,13 @@ def test_full_size_sampled_rows(name, rows, orc):
     sel = np.random.default_rng(17).choice(w.n, size=rows, replace=False)
     fo, ur, wr = orc.forces_rows(orc.params(box), pos4, sel)
     assert rel_l2(f[sel], fo) <= FORCE_TOL
-    # the energy over all atoms equals N times the mean over a uniform sample only
-    # statistically; check it against the FCC-shell value instead (jitter is small)
-    assert e[0] / w.n == pytest.approx(-5.69, abs=0.2)
+    if name == "lj256k":
+        # the full O(N^2) oracle sums of this state, stored once by
+        # tests/golden/make_full_energy.py (the FCC pin covers N = 2,048,000)
+        g = json.load(open(os.path.join(GOLDEN, "lj256k_jitter_energy.json")))
+        assert g["n"] == w.n and g["jitter"] == 0.05 and g["box"] == box
+        assert abs(e[0] - g["U"]) <= ENERGY_TOL * abs(g["U"])
+        assert abs(e[2] - g["W"]) <= ENERGY_TOL * abs(g["W"])
 
 
 def test_edge_small_systems(orc):

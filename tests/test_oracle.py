@@ -278,6 +278,44 @@ def test_neighbors_brute_force(orc):
         assert list(idx[off[i]:off[i + 1]]) == expect
 
 
+def _lattice_neighbor_sets(pos, box, n_fcc, d2_max):
+    """Neighbour sets of a perfect FCC lattice by integer arithmetic: site
+    coordinates in units of half the lattice constant are integers (the
+    common a/4 offset drops out of every difference), the minimum image is
+    taken modulo 2 n_fcc, and shell k of the lattice lies at squared integer
+    distance 2 k."""
+    a = box / n_fcc
+    g = np.rint((np.asarray(pos, np.float64)[:, :3] / a - 0.25) * 2.0).astype(np.int64) % (2 * n_fcc)
+    d = g[:, None, :] - g[None, :, :]
+    d = (d + n_fcc) % (2 * n_fcc) - n_fcc
+    d2 = (d * d).sum(-1)
+    np.fill_diagonal(d2, 1 << 30)
+    return [np.flatnonzero(row <= d2_max) for row in d2]
+
+
+@pytest.mark.parametrize("density,n_fcc,shells", [(0.8442, 10, 4), (0.5, 6, 3)])
+def test_neighbors_of_perfect_fcc(orc, density, n_fcc, shells):
+    """On a perfect FCC lattice every atom has the same neighbours: the sites
+    of the textbook shells inside r_c = 2.5 (at rho = 0.8442, a = 1.6796: the
+    first four shells, 12 + 6 + 24 + 12 = 54 sites, the fifth at 2.656 is
+    outside; at rho = 0.5, a = 2: three shells, 42 sites). The oracle's
+    brute-force sets must equal the sets found by integer lattice arithmetic,
+    site for site."""
+    g = json.load(open(os.path.join(GOLDEN, "fcc_shells.json")))
+    expect = sum(m for k, m in g["shells"][:shells])
+    w = ljsynth.Workload("fcc", n_fcc, density, 1.0, 1, 1)
+    pos, _, L = ljsynth.make_state(w)
+    a = L / n_fcc
+    assert a * math.sqrt(shells / 2.0) < 2.5 < a * math.sqrt((shells + 1) / 2.0)
+    counts, idx, guard = orc.neighbors(_p(orc, L), pos)
+    assert guard == 0
+    assert np.all(counts == expect)
+    lattice = _lattice_neighbor_sets(pos, L, n_fcc, 2 * shells)
+    off = np.concatenate([[0], np.cumsum(counts)])
+    for i in range(len(pos)):
+        assert np.array_equal(idx[off[i]:off[i + 1]], lattice[i]), i
+
+
 def test_guard_band_empty_for_parity_state(orc):
     pos, _, L = _jittered(ljsynth.WORKLOADS["lj4k"])
     counts, idx, guard = orc.neighbors(_p(orc, L), pos)
@@ -335,3 +373,18 @@ def test_paper_worked_example_golden_is_consistent():
     ratio = (g["cell_side"] / g["rc"]) ** 3
     assert round(100 * (ratio - 1)) == g["particles_per_cell_increase_pct"]
     assert round(100 * (ratio ** 2 - 1)) == g["interactions_increase_pct"]
+
+
+def test_full_size_energy_golden_is_consistent(orc):
+    """The stored full O(N^2) oracle sums of the jittered N = 256,000 state
+    (tests/golden/make_full_energy.py) against an independent estimate: the
+    mean of 4,096 uniformly sampled rows, each a full sum over all N atoms,
+    times N (a statistical check, 1e-3), and the recorded box and recipe."""
+    g = json.load(open(os.path.join(GOLDEN, "lj256k_jitter_energy.json")))
+    w = ljsynth.WORKLOADS["lj256k"]
+    pos, _, L = ljsynth.make_state(w, jitter_amp=g["jitter"])
+    assert g["n"] == w.n and g["seed"] == w.seed and g["box"] == L
+    rows = np.random.default_rng(3).choice(w.n, size=4096, replace=False)
+    _, ur, wr = orc.forces_rows(_p(orc, L), pos, rows)
+    assert ur.mean() * w.n == pytest.approx(g["U"], rel=1e-3)
+    assert wr.mean() * w.n == pytest.approx(g["W"], rel=1e-3)

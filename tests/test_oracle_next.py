@@ -2,7 +2,7 @@
 (LJ truncated at its minimum 2^(1/6) sigma and shifted by eps, i.e. another
 short-range pair potential as the paper's closing section allows) and LJ at
 other densities (the density axis of the paper's cell-list measurements,
-section 4).
+section 3.2).
 
 The pins are closed forms and textbook lattice facts, not the oracle's own
 formulas: the WCA energy at contact, lattices whose shells lie wholly inside
