@@ -252,7 +252,6 @@ def test_bucket_overflow_build_and_steps(box, n_gas, orc):
     _check_cell_lists(p3, box)
 
 
-@pytest.mark.parametrize("name", ["lj4k", "lj256k", "lj2m"])
 def _one_crowded_cell(seed=33):
     """4,096 atoms in one cell: a 16^3 simple-cubic block of spacing 15/16
     sigma, jittered by up to 0.09 sigma, filling the first of 27 cells of side
@@ -307,6 +306,7 @@ def test_crowded_cell_builds_in_linear_time(orc):
     assert np.array_equal(np.sort(order.cpu().numpy()), np.arange(len(pos4)))
 
 
+@pytest.mark.parametrize("name", ["lj4k", "lj256k", "lj2m"])
 def test_fcc_lattice_energy_pin(name):
     """Perfect FCC at rho = 0.8442: U/N = -5.693278, W/N = -20.16527 from the
     textbook shells (12, 6, 24, 12 sites inside r_c), with no oracle in the
