@@ -203,6 +203,23 @@ md_status md_neighbors(const md_params* p, const void* ws, size_t ws_bytes, int3
                        int32_t* idx_dev, int32_t max_per_atom, hipStream_t stream);
 
 /*
+ * The same export through md_step_list's pair-list path (section 3: a list of
+ * partners within a radius beyond r_c, here the cell side). record = 1:
+ * screen the 27-cell neighbourhood against the list radius and keep every
+ * lane's accept words, as the force pass right after a rebuild of
+ * md_step_list does (this replaces the words md_step_list kept); record = 0:
+ * walk the words kept last instead of screening, as its passes between
+ * rebuilds do. Both export the pairs with r_ij^2 < r_c^2 that the walk
+ * accepts, so for the current positions both must equal md_neighbors. Needs
+ * a workspace laid out with MD_FLAG_PAIR_LISTS (MD_ERR_ARG otherwise);
+ * record = 0 is meaningful only while the kept words belong to the current
+ * cell lists (no rebuild since they were kept). Outputs and errors as for
+ * md_neighbors.
+ */
+md_status md_neighbors_lists(const md_params* p, void* ws, size_t ws_bytes, int32_t* counts_dev,
+                             int32_t* idx_dev, int32_t max_per_atom, int32_t record, hipStream_t stream);
+
+/*
  * Test export of the cell list: cell_start_dev int32 [n_c^3 + 1] (CSR offsets
  * of every cell into the sorted order) and order_dev int32 [n] (user index of
  * the atom at each sorted slot). Either pointer may be NULL.

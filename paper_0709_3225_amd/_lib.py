@@ -39,6 +39,7 @@ SYMBOLS = (
     "md_energy_virial",
     "md_get_state",
     "md_neighbors",
+    "md_neighbors_lists",
     "md_cell_lists",
     "md_adjoint_kick",
     "md_adjoint_drift",
@@ -128,6 +129,7 @@ def lib():
         L.md_energy_virial.argtypes = [P, vp, sz, vp, vp]
         L.md_get_state.argtypes = [P, vp, sz, vp, vp, vp]
         L.md_neighbors.argtypes = [P, vp, sz, vp, vp, i32, vp]
+        L.md_neighbors_lists.argtypes = [P, vp, sz, vp, vp, i32, i32, vp]
         L.md_cell_lists.argtypes = [P, vp, sz, vp, vp, vp]
         L.md_check.argtypes = [vp, sz, vp, ctypes.POINTER(i32)]
         L.md_adjoint_kick.argtypes = [P, vp, sz, vp, vp, vp, ctypes.c_float, vp]
@@ -148,7 +150,7 @@ def lib():
         L.md_graph_launch.argtypes = [vp, vp]
         L.md_graph_destroy.argtypes = [vp]
         for name in ("md_cell_grid", "md_build_cells", "md_forces", "md_step", "md_step_every", "md_step_list", "md_energy_virial",
-                     "md_get_state", "md_neighbors", "md_cell_lists", "md_check", "md_adjoint_kick",
+                     "md_get_state", "md_neighbors", "md_neighbors_lists", "md_cell_lists", "md_check", "md_adjoint_kick",
                      "md_adjoint_drift", "md_adjoint_segment", "md_loss_grad", "md_loss", "md_adjoint_seed",
                      "md_batch_build", "md_batch_forces", "md_batch_step",
                      "md_batch_energy_virial", "md_batch_get_state", "md_batch_graph_create", "md_graph_launch",
@@ -303,6 +305,15 @@ def md_neighbors(p: MDParams, ws, counts, idx, max_per_atom: int, stream=None):
     _check(lib().md_neighbors(ctypes.byref(p), wp, wn, _ptr(counts, "counts", torch.int32, (p.n,)),
                               _ptr(idx, "idx", torch.int32, (p.n * max_per_atom,)), int(max_per_atom),
                               _stream(stream)))
+
+
+def md_neighbors_lists(p: MDParams, ws, counts, idx, max_per_atom: int, record: bool, stream=None):
+    import torch
+
+    wp, wn = _ws(ws)
+    _check(lib().md_neighbors_lists(ctypes.byref(p), wp, wn, _ptr(counts, "counts", torch.int32, (p.n,)),
+                                    _ptr(idx, "idx", torch.int32, (p.n * max_per_atom,)), int(max_per_atom),
+                                    1 if record else 0, _stream(stream)))
 
 
 def md_cell_lists(p: MDParams, ws, cell_start=None, order=None, stream=None):

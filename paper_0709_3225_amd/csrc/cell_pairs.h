@@ -9,7 +9,6 @@
 namespace mdlj {
 namespace {
 
-constexpr int kTile = 1024;  // staged atoms per LDS pass of the neighbour export (16 KiB)
 
 // The 27-cell neighbourhood of a home cell as runs of memory-contiguous cells
 // that share one image shift ("segments"): the three cells of an x-row are
@@ -387,7 +386,10 @@ __device__ __forceinline__ bool row_hood(const SimArgs& a, int c, RowHood& r) {
 
 // Staging of a RowHood neighbourhood in one pass (total <= tile capacity), by
 // the same unmasked scheme as stage_whole (rows tile [0, total) in order).
-__device__ __forceinline__ void stage_rows(const SimArgs& a, const RowHood& r, float4* tile) {
+// RAW: the untranslated positions (w = user index) go to raw at the same
+// indices.
+template <bool RAW = false>
+__device__ __forceinline__ void stage_rows(const SimArgs& a, const RowHood& r, float4* tile, float4* raw = nullptr) {
     const int lane = threadIdx.x;
     const int last = a.natoms - 1;
     const char* pbase = reinterpret_cast<const char*>(a.pos0);
@@ -403,6 +405,7 @@ __device__ __forceinline__ void stage_rows(const SimArgs& a, const RowHood& r, f
         const float y = q[k].y - r.fy[k % 3];
         const float z = q[k].z - r.fz[k / 3];
         tile[r.pos[k] + lane] = make_float4(x, y, z, x * x + y * y + z * z);
+        if (RAW) raw[r.pos[k] + lane] = q[k];
         __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
@@ -414,6 +417,7 @@ __device__ __forceinline__ void stage_rows(const SimArgs& a, const RowHood& r, f
                     const float4 v = a.pos0[r.first[k] + off];
                     const float x = v.x - r.ox, y = v.y - r.fy[k % 3], z = v.z - r.fz[k / 3];
                     tile[r.pos[k] + off] = make_float4(x, y, z, x * x + y * y + z * z);
+                    if (RAW) raw[r.pos[k] + off] = v;
                 }
             }
         }

@@ -61,6 +61,37 @@ struct ForceOp {
     }
 };
 
+// Neighbour export from the force kernel's own staging, screen and walk: every
+// pair the walk visits and the exact FP32 cutoff test of pair_force accepts
+// appends the partner's user index to the home atom's row (row order follows
+// the atomics, so it is unspecified).
+struct ExportArgs {
+    int* counts;
+    int* idx;
+    int max_nb;
+};
+
+struct ExportOp {
+    const SimArgs& a;
+    const char* base;   // tile at the lane's span start
+    const char* rbase;  // untranslated positions (user index in w) at the same place
+    float xi, yi, zi;
+    int idi;
+    const ExportArgs& ex;
+    bool over = false;
+    __device__ __forceinline__ void operator()(uint32_t off, bool live) {
+        const float4 q = *reinterpret_cast<const float4*>(base + off);
+        const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
+        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        if (live && r2 < a.rc2) {
+            const int idj = __float_as_int(reinterpret_cast<const float4*>(rbase + off)->w);
+            const int slot = atomicAdd(&ex.counts[idi], 1);
+            if (slot < ex.max_nb) ex.idx[static_cast<size_t>(idi) * ex.max_nb + slot] = idj;
+            else over = true;
+        }
+    }
+};
+
 // Kept accept words (pair lists as bitmasks): span j of a lane is one 16-byte
 // record; spans past kListSpans are only counted (the cell then screens).
 __device__ __forceinline__ void keep_words(uint4* rows, int& n, const uint32_t (&wd)[kWords]) {
@@ -68,13 +99,21 @@ __device__ __forceinline__ void keep_words(uint4* rows, int& n, const uint32_t (
     ++n;
 }
 
-// Span j's kept words; span 0 was requested before the staging (w0).
-__device__ __forceinline__ void kept_words(const uint4* rows, const uint4& w0, int j, uint32_t (&wd)[kWords]) {
-    const uint4 v = j == 0 ? w0 : rows[j];
+// Span j's kept words; span 0 was requested before the staging (w0). Bits
+// past the span's groups candidates per lane are dropped, so a walk never
+// leaves the staged span, whatever the words hold.
+__device__ __forceinline__ void kept_words(const uint4* rows, const uint4& w0, int j, int groups,
+                                           uint32_t (&wd)[kWords]) {
+    const uint4 v = j == 0 ? w0 : (j < kListSpans ? rows[j] : make_uint4(0u, 0u, 0u, 0u));
     wd[0] = v.x;
     wd[1] = v.y;
     wd[2] = v.z;
     wd[3] = v.w;
+#pragma unroll
+    for (int w = 0; w < kWords; ++w) {
+        const int valid = groups - 32 * w;  // uniform
+        wd[w] &= valid >= 32 ? ~0u : (valid <= 0 ? 0u : ~0u << (32 - valid));
+    }
 }
 
 // Forces on the atoms of home cell c (local index of the system described by
@@ -96,9 +135,12 @@ __device__ __forceinline__ void kept_words(const uint4* rows, const uint4& w0, i
 // screening: the same candidates in the same order plus some beyond r_c,
 // which add exact zeros, so the sums are bitwise those of the screen. A cell
 // with more than kListSpans spans per lane, or more than one pass, screens as
-// usual.
-template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT, bool SKIN = false, int LIST = 0>
-__device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile, Neighbourhood& nb, float* red) {
+// usual (and with the plain bound).
+// EXPORT: no forces; the pairs the walk accepts go to the neighbour rows of
+// ex (raw: a second tile of untranslated positions).
+template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT, bool SKIN = false, int LIST = 0, bool EXPORT = false>
+__device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile, Neighbourhood& nb, float* red,
+                                           float4* raw = nullptr, const ExportArgs& ex = ExportArgs{}) {
     const int lane = threadIdx.x;
     float ox, oy, oz;
     // a cell away from the x faces whose neighbourhood and home atoms fit one
@@ -115,7 +157,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         home_first = rh.home_first;
         n_home = rh.n_home;
         home_pos = rh.home_pos;
-        stage_rows(a, rh, tile);
+        stage_rows<EXPORT>(a, rh, tile, raw);
     } else {
         load_neighbourhood(a, c, nb, ox, oy, oz);
         total = nb.total;
@@ -125,7 +167,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
     }
 
     double u_acc = 0.0, w_acc = 0.0, k_acc = 0.0;
-    bool bad = false, skin_out = false;
+    bool bad = false, skin_out = false, over = false;
     const size_t lrow = (static_cast<size_t>(a.cbase + c) * kWave + lane);  // this lane's kept words
     uint4* lwords = reinterpret_cast<uint4*>(a.plist) + lrow * kListSpans;
     const bool list_fits = total <= a.tile_cap && n_home <= kWave;          // uniform
@@ -159,7 +201,9 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         const float xi = pi.x - ox, yi = pi.y - oy, zi = pi.z - oz;
         const float ai = fmaf(zi, zi, fmaf(yi, yi, xi * xi));
         // idle lanes get a bound no candidate can meet (q.w - thr_i = +inf)
-        const float thr_i = act ? (LIST == 1 ? a.list_screen2 : a.screen2) - ai : -__builtin_huge_valf();
+        // (the list radius only where the words are kept: other cells sum as the plain screen does)
+        const float thr_i = act ? ((LIST == 1 && list_fits) ? a.list_screen2 : a.screen2) - ai
+                                : -__builtin_huge_valf();
         const float mx = -2.0f * xi, my = -2.0f * yi, mz = -2.0f * zi;
         // matrix-core operands: this lane's element of B (component s of
         // (-2 x_i, -2 y_i, -2 z_i, 1)) and of C (-bound + |x_i|^2; +inf idle)
@@ -170,32 +214,45 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
             const int tn = min(a.tile_cap, total - t0);
             if (!rows) {
                 __syncthreads();
-                stage_tile<false>(a, nb, tile, t0, tn);
+                if (EXPORT) stage_tile<false, true>(a, nb, tile, t0, tn, a.pos0, raw);
+                else stage_tile<false>(a, nb, tile, t0, tn);
             }
             for (int t = lane; t < kTilePad; t += kWave) tile[tn + t] = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
             __syncthreads();
             const int self_t = home_pos + h0 + h - t0;  // the home atom's own tile index (may be outside)
+            // the walk over one span's words; the lane's candidates are cand0,
+            // cand0 + ns_, cand0 + 2 ns_, ...
+            auto walk = [&](int ns_, int cand0, uint32_t (&wd)[kWords]) {
+                if (EXPORT) {
+                    ExportOp op{a, reinterpret_cast<const char*>(tile + cand0), reinterpret_cast<const char*>(raw + cand0),
+                                xi, yi, zi, __float_as_int(pi.w), ex};
+                    walk_bits(ns_, wd[0], wd[1], wd[2], wd[3], op);
+                    over = over || op.over;
+                } else {
+                    ForceOp<ENERGY> op{a, reinterpret_cast<const char*>(tile + cand0), xi, yi, zi, fx, fy, fz, u_loc,
+                                       w_loc};
+                    walk_bits(ns_, wd[0], wd[1], wd[2], wd[3], op);
+                    fx = op.fx;
+                    fy = op.fy;
+                    fz = op.fz;
+                    u_loc = op.u_loc;
+                    w_loc = op.w_loc;
+                }
+            };
             if (mf) {
                 const int nblk_all = (tn + 15) / 16;
                 for (int b0 = 0; b0 < nblk_all; b0 += 8 * kWords) {
                     const int nblk = min(8 * kWords, nblk_all - b0);
                     uint32_t wd[kWords];
                     if (LIST == 2 && use_list) {
-                        kept_words(lwords, lw0, b0 / (8 * kWords), wd);
+                        kept_words(lwords, lw0, b0 / (8 * kWords), 4 * nblk, wd);
                     } else {
                         screen_mfma(tile, 16 * b0, nblk, bval, cneg, wd);
                         if (act) clear_self(self_t - 16 * b0, s, 4, 4 * nblk, wd);
-                        if (LIST == 1) keep_words(lwords, n_rec, wd);
+                        if (LIST == 1 && list_fits) keep_words(lwords, n_rec, wd);
                     }
                     // the lane's candidates are tile + 16 b0 + s + 4 g, as for four VALU slices
-                    ForceOp<ENERGY> op{a, reinterpret_cast<const char*>(tile + 16 * b0 + s), xi, yi, zi, fx, fy, fz,
-                                       u_loc, w_loc};
-                    walk_bits<ForceOp<ENERGY>>(4, wd[0], wd[1], wd[2], wd[3], op);
-                    fx = op.fx;
-                    fy = op.fy;
-                    fz = op.fz;
-                    u_loc = op.u_loc;
-                    w_loc = op.w_loc;
+                    walk(4, 16 * b0 + s, wd);
                 }
                 continue;
             }
@@ -205,7 +262,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                 const int first = g0 * ns + (act ? s : 0);
                 uint32_t wd[kWords];
                 if (LIST == 2 && use_list) {
-                    kept_words(lwords, lw0, g0 / kGroups, wd);
+                    kept_words(lwords, lw0, g0 / kGroups, groups, wd);
                 } else {
                     switch (ns) {
                         case 2: screen_span<2>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
@@ -216,18 +273,12 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                         default: screen_span<0>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
                     }
                     if (act) clear_self(self_t, first, ns, groups, wd);
-                    if (LIST == 1) keep_words(lwords, n_rec, wd);
+                    if (LIST == 1 && list_fits) keep_words(lwords, n_rec, wd);
                 }
-                ForceOp<ENERGY> op{a, reinterpret_cast<const char*>(tile + first), xi, yi, zi, fx, fy, fz, u_loc,
-                                   w_loc};
-                walk_bits(ns, wd[0], wd[1], wd[2], wd[3], op);
-                fx = op.fx;
-                fy = op.fy;
-                fz = op.fz;
-                u_loc = op.u_loc;
-                w_loc = op.w_loc;
+                walk(ns, first, wd);
             }
         }
+        if (EXPORT) continue;
         // sum the slice partials of each home atom in slice order (red aliases the
         // tile: every lane has finished its walk at this barrier)
         __syncthreads();
@@ -295,6 +346,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         if (DRIFT && !SKIN) bin_atom(a, p_next, v_next, c_next);  // all lanes
     }
     if (LIST == 1) a.plist_n[lrow] = list_fits ? n_rec : kListSpans + 1;  // kept words of several passes are not used
+    if (EXPORT && over) atomicOr(&a.hdr[HDR_ERROR], DEV_NB_OVERFLOW);
     if (bad) atomicOr(&a.hdr[HDR_ERROR], DEV_NONFINITE);
     if (SKIN && skin_out) atomicOr(&a.hdr[HDR_ERROR], DEV_SKIN);
     if (ENERGY) {
@@ -456,51 +508,21 @@ __global__ void __launch_bounds__(kRedBlock)
     }
 }
 
-// Neighbour export: same staging and cutoff test as the force kernel.
-__global__ void __launch_bounds__(kWave) k_neighbors(SimArgs a, int* counts, int* idx, int max_nb) {
+// Neighbour export through the force kernel's own staging, screen and walk.
+// LIST 1 screens against the list radius and keeps the accept words, as the
+// force pass right after a rebuild of md_step_list does; LIST 2 walks the
+// words kept last, as its passes between rebuilds do.
+template <int LIST>
+__global__ void __launch_bounds__(kWave) k_neighbors(SimArgs a, ExportArgs ex) {
     if (!state_ok(a, false)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&a.hdr[HDR_ERROR], DEV_ORDER);
         return;
     }
-    __shared__ float4 tile[kTile + kWave];  // a one-pass staging writes up to 63 entries past the atoms
+    extern __shared__ float4 tile[];  // 2 x (tile_cap + kTilePad): frame positions, then untranslated ones
     __shared__ Neighbourhood nb;
-    const int lane = threadIdx.x;
-    const int c = blockIdx.x;
-    float ox, oy, oz;
-    load_neighbourhood(a, c, nb, ox, oy, oz);
-    const int total = nb.total;
-    const int home_first = nb.home_first;
-    const int n_home = nb.n_home;
-    bool overflow = false;
-    for (int h0 = 0; h0 < n_home; h0 += kWave) {
-        const int h = h0 + lane;
-        const bool act = h < n_home;
-        float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (act) pi = a.pos0[home_first + h];
-        const float xi = pi.x - ox, yi = pi.y - oy, zi = pi.z - oz;
-        const int idi = __float_as_int(pi.w);
-        int cnt = 0;
-        for (int t0 = 0; t0 < total; t0 += kTile) {
-            const int tn = min(kTile, total - t0);
-            __syncthreads();
-            stage_tile<true>(a, nb, tile, t0, tn);
-            __syncthreads();
-            if (act) {
-                for (int j = 0; j < tn; ++j) {
-                    const float4 q = tile[j];
-                    const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
-                    const float r2 = dx * dx + dy * dy + dz * dz;
-                    if (r2 < a.rc2 && __float_as_int(q.w) != idi) {
-                        if (cnt < max_nb) idx[static_cast<size_t>(idi) * max_nb + cnt] = __float_as_int(q.w);
-                        else overflow = true;
-                        ++cnt;
-                    }
-                }
-            }
-        }
-        if (act) counts[idi] = cnt;
-    }
-    if (overflow) atomicOr(&a.hdr[HDR_ERROR], DEV_NB_OVERFLOW);
+    force_cell<false, false, false, false, false, LIST, true>(a, xcd_block_order(blockIdx.x, a.ncells), tile, nb,
+                                                              reinterpret_cast<float*>(tile),
+                                                              tile + (a.tile_cap + kTilePad), ex);
 }
 
 }  // namespace
@@ -605,8 +627,14 @@ hipError_t launch_batch_energy_final(const SimArgs& base, const Replica* reps, i
     return hipGetLastError();
 }
 
-hipError_t launch_neighbors(const SimArgs& a, int* counts, int* idx, int max_per_atom, hipStream_t st) {
-    hipLaunchKernelGGL(k_neighbors, dim3(a.ncells), dim3(kWave), 0, st, a, counts, idx, max_per_atom);
+hipError_t launch_neighbors(const SimArgs& a, int* counts, int* idx, int max_per_atom, int list, hipStream_t st) {
+    hipError_t e = hipMemsetAsync(counts, 0, sizeof(int) * static_cast<size_t>(a.n), st);
+    if (e != hipSuccess) return e;
+    const ExportArgs ex{counts, idx, max_per_atom};
+    const size_t lds = 2 * sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
+    if (list == 1) hipLaunchKernelGGL(k_neighbors<1>, dim3(a.ncells), dim3(kWave), lds, st, a, ex);
+    else if (list == 2) hipLaunchKernelGGL(k_neighbors<2>, dim3(a.ncells), dim3(kWave), lds, st, a, ex);
+    else hipLaunchKernelGGL(k_neighbors<0>, dim3(a.ncells), dim3(kWave), lds, st, a, ex);
     return hipGetLastError();
 }
 

@@ -656,7 +656,23 @@ md_status md_neighbors(const md_params* p, const void* ws, size_t ws_bytes, int3
     if (!counts || !idx) return fail(MD_ERR_ARG, "neighbour outputs are NULL");
     if (max_per_atom < 1) return fail(MD_ERR_ARG, "max_per_atom must be >= 1");
     const SimArgs a = make_args(p, L, const_cast<void*>(ws));
-    MD_TRY_HIP(launch_neighbors(a, counts, idx, max_per_atom, stream), "neighbors");
+    MD_TRY_HIP(launch_neighbors(a, counts, idx, max_per_atom, 0, stream), "neighbors");
+    return MD_OK;
+}
+
+md_status md_neighbors_lists(const md_params* p, void* ws, size_t ws_bytes, int32_t* counts, int32_t* idx,
+                             int32_t max_per_atom, int32_t record, hipStream_t stream) {
+    Layout L{};
+    md_status s = make_layout(p, L);
+    if (s != MD_OK) return s;
+    if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
+    if (!(p->flags & MD_FLAG_PAIR_LISTS))
+        return fail(MD_ERR_ARG, "md_neighbors_lists needs a workspace laid out with MD_FLAG_PAIR_LISTS");
+    if (!counts || !idx) return fail(MD_ERR_ARG, "neighbour outputs are NULL");
+    if (max_per_atom < 1) return fail(MD_ERR_ARG, "max_per_atom must be >= 1");
+    if (record != 0 && record != 1) return fail(MD_ERR_ARG, "record must be 0 or 1");
+    const SimArgs a = make_args(p, L, ws);
+    MD_TRY_HIP(launch_neighbors(a, counts, idx, max_per_atom, record ? 1 : 2, stream), "neighbors");
     return MD_OK;
 }
 

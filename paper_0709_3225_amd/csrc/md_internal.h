@@ -143,7 +143,9 @@ hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st);
 hipError_t launch_loss_final(const SimArgs& a, double kcoef, double wcoef, double* out, hipStream_t st);
 hipError_t launch_gather_user(const SimArgs& a, float4* pos_out, float4* vel_out, float4* force_out,
                               hipStream_t st);
-hipError_t launch_neighbors(const SimArgs& a, int* counts, int* idx, int max_per_atom,
+// Neighbour export through the force kernel (list: 0 screen against r_c,
+// 1 screen against the list radius and keep the words, 2 walk the kept words).
+hipError_t launch_neighbors(const SimArgs& a, int* counts, int* idx, int max_per_atom, int list,
                             hipStream_t st);
 hipError_t launch_cell_lists(const SimArgs& a, int* cell_start, int* order, hipStream_t st);
 hipError_t launch_adjoint_kick(const SimArgs& a, const float4* w_user, float4* lam_r, double* theta, float coef,

@@ -84,10 +84,17 @@ class LJSystem:
         L.md_get_state(self.params, self.ws, pos, vel)
         return pos, vel
 
-    def neighbors(self, max_per_atom: int = 128):
+    def neighbors(self, max_per_atom: int = 128, lists: str | None = None):
+        """Neighbour rows as the force kernel's walk accepts them; ``lists``:
+        None screens against r_c (md_neighbors), "record" screens against the
+        list radius and keeps the words, "kept" walks the words kept last
+        (md_neighbors_lists)."""
         counts = torch.empty(self.n, dtype=torch.int32, device=self.device)
         idx = torch.full((self.n * max_per_atom,), -1, dtype=torch.int32, device=self.device)
-        L.md_neighbors(self.params, self.ws, counts, idx, max_per_atom)
+        if lists is None:
+            L.md_neighbors(self.params, self.ws, counts, idx, max_per_atom)
+        else:
+            L.md_neighbors_lists(self.params, self.ws, counts, idx, max_per_atom, lists == "record")
         return counts, idx.view(self.n, max_per_atom)
 
     def cell_lists(self):
