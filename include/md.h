@@ -123,6 +123,23 @@ md_status md_forces(const md_params* p, void* ws, size_t ws_bytes, float* force4
                     hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): md_build_cells on
+ * pos4_dev (zero velocities) followed by md_forces with output force4_dev,
+ * in a workspace the library keeps in a static device array of 16 MiB per
+ * GPU (held until the process ends) instead of a caller's. It allocates
+ * nothing. Parameters whose workspace (md_workspace_bytes) exceeds 16 MiB
+ * (about 60,000 atoms at liquid density) are refused with MD_ERR_WORKSPACE
+ * before any device call. The forces are those of md_forces on the same
+ * positions (same kernels, same layout). Calls on one GPU share its array,
+ * which keeps the last call's contents (every call rebuilds it from scratch):
+ * calls that overlap on one GPU, on any streams, race. Device-side error
+ * bits of the workspace are not reported (non-finite positions give
+ * non-finite forces).
+ */
+md_status md_forces_noalloc(const md_params* p, const float* pos4_dev, float* force4_dev, hipStream_t stream);
+
+/*
  * Advance nsteps velocity-Verlet steps (section 2). Each step: half kick
  * with the stored forces, drift, wrap into [0, L), cell-list rebuild
  * (histogram, scan, scatter, in-cell order), new forces, half kick.

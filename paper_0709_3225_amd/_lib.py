@@ -33,6 +33,7 @@ SYMBOLS = (
     "md_cell_grid",
     "md_build_cells",
     "md_forces",
+    "md_forces_noalloc",
     "md_step",
     "md_step_every",
     "md_step_list",
@@ -123,6 +124,7 @@ def lib():
         L.md_cell_grid.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
         L.md_build_cells.argtypes = [P, vp, sz, vp, vp, vp]
         L.md_forces.argtypes = [P, vp, sz, vp, vp]
+        L.md_forces_noalloc.argtypes = [P, vp, vp, vp]
         L.md_step.argtypes = [P, vp, sz, i32, i32, vp, vp]
         L.md_step_every.argtypes = [P, vp, sz, i32, i32, i32, vp, vp]
         L.md_step_list.argtypes = [P, vp, sz, i32, i32, i32, vp, vp]
@@ -149,7 +151,7 @@ def lib():
         L.md_batch_graph_create.argtypes = [P, R, i32, vp, sz, i32, i32, vp, vp, ctypes.POINTER(vp)]
         L.md_graph_launch.argtypes = [vp, vp]
         L.md_graph_destroy.argtypes = [vp]
-        for name in ("md_cell_grid", "md_build_cells", "md_forces", "md_step", "md_step_every", "md_step_list", "md_energy_virial",
+        for name in ("md_cell_grid", "md_build_cells", "md_forces", "md_forces_noalloc", "md_step", "md_step_every", "md_step_list", "md_energy_virial",
                      "md_get_state", "md_neighbors", "md_neighbors_lists", "md_cell_lists", "md_check", "md_adjoint_kick",
                      "md_adjoint_drift", "md_adjoint_segment", "md_loss_grad", "md_loss", "md_adjoint_seed",
                      "md_batch_build", "md_batch_forces", "md_batch_step",
@@ -237,6 +239,13 @@ def md_forces(p: MDParams, ws, force4=None, stream=None):
     wp, wn = _ws(ws)
     _check(lib().md_forces(ctypes.byref(p), wp, wn, _ptr(force4, "force4", torch.float32, (p.n, 4)),
                            _stream(stream)))
+
+
+def md_forces_noalloc(p: MDParams, pos4, force4, stream=None):
+    import torch
+
+    _check(lib().md_forces_noalloc(ctypes.byref(p), _ptr(pos4, "pos4", torch.float32, (p.n, 4)),
+                                   _ptr(force4, "force4", torch.float32, (p.n, 4)), _stream(stream)))
 
 
 def md_step(p: MDParams, ws, nsteps: int, thermo_every: int = 0, thermo=None, stream=None):

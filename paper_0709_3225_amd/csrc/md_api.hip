@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <utility>
 #include <vector>
@@ -270,6 +271,38 @@ md_status build_cells_impl(const SimArgs& a, const float4* pos4, const float4* v
     return MD_OK;
 }
 
+// ---- a workspace that needs no allocation (md_forces_noalloc) ----------------
+// A file-scope device array holds the workspace for callers that cannot
+// allocate device memory. Every GPU the library runs on holds its own copy
+// until the process ends. In host code the array's name stands for a
+// host-side symbol, not a device address: the device address of the current
+// GPU's copy comes from hipGetSymbolAddress on the first call on that device
+// and is kept per device; only that address is ever handed to a kernel.
+constexpr size_t kScratchBytes = size_t{16} << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+md_status scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kScratchDevices)
+        return fail(MD_ERR_ARG, "device %d is beyond the %d devices the static workspace serves", dev, kScratchDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(MD_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MD_OK;
+}
+
 // nsteps fused velocity-Verlet steps (md_step after validation).
 md_status steps_impl(const SimArgs& a, int32_t nsteps, int32_t thermo_every, double* thermo, hipStream_t stream) {
     // The force pass of every step but the last also performs the next step's
@@ -510,6 +543,24 @@ md_status md_forces(const md_params* p, void* ws, size_t ws_bytes, float* force4
     const SimArgs a = make_args(p, L, ws);
     MD_TRY_HIP(launch_forces(a, false, false, true, false, false, 0, stream), "forces");
     if (force4) MD_TRY_HIP(launch_gather_user(a, nullptr, nullptr, reinterpret_cast<float4*>(force4), stream), "gather");
+    return MD_OK;
+}
+
+md_status md_forces_noalloc(const md_params* p, const float* pos4, float* force4, hipStream_t stream) {
+    Layout L{};
+    md_status s = make_layout(p, L);
+    if (s != MD_OK) return s;
+    if (L.total > kScratchBytes)
+        return fail(MD_ERR_WORKSPACE, "these parameters need a %zu-byte workspace; the static one holds %zu bytes",
+                    L.total, kScratchBytes);
+    if (!pos4 || !force4) return fail(MD_ERR_ARG, "positions and forces must not be NULL");
+    if (!aligned16(pos4) || !aligned16(force4)) return fail(MD_ERR_ARG, "particle arrays must be 16-byte aligned");
+    void* ws = nullptr;
+    if ((s = scratch_address(&ws)) != MD_OK) return s;
+    const SimArgs a = make_args(p, L, ws);
+    if ((s = build_cells_impl(a, reinterpret_cast<const float4*>(pos4), nullptr, stream)) != MD_OK) return s;
+    MD_TRY_HIP(launch_forces(a, false, false, true, false, false, 0, stream), "forces");
+    MD_TRY_HIP(launch_gather_user(a, nullptr, nullptr, reinterpret_cast<float4*>(force4), stream), "gather");
     return MD_OK;
 }
 

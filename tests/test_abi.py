@@ -91,6 +91,7 @@ def test_invalid_params_rejected_on_host(kw, code):
 
     assert lib.md_build_cells(ctypes.byref(p), None, 0, None, None, None) == code
     assert lib.md_forces(ctypes.byref(p), None, 0, None, None) == code
+    assert lib.md_forces_noalloc(ctypes.byref(p), None, None, None) == code
     assert lib.md_step(ctypes.byref(p), None, 0, 1, 0, None, None) == code
     assert lib.md_energy_virial(ctypes.byref(p), None, 0, None, None) == code
 
@@ -112,6 +113,15 @@ def test_workspace_and_pointer_checks_on_host():
     assert lib.md_step(ctypes.byref(p), fake, need, -1, 0, None, None) == _lib.MD_ERR_ARG
     assert lib.md_step(ctypes.byref(p), fake, need, 4, 2, None, None) == _lib.MD_ERR_ARG
     assert lib.md_neighbors(ctypes.byref(p), fake, need, fake, fake, 0, None) == _lib.MD_ERR_ARG
+    # the static-workspace entry point: NULL or misaligned arrays, and a system
+    # whose workspace exceeds the 16 MiB static array, refused before any HIP call
+    assert lib.md_forces_noalloc(ctypes.byref(p), None, fake, None) == _lib.MD_ERR_ARG
+    assert lib.md_forces_noalloc(ctypes.byref(p), fake, ctypes.c_void_p((1 << 40) + 8), None) == _lib.MD_ERR_ARG
+    big = md.make_params(256000, 67.18385)
+    assert md.md_workspace_bytes(big) > (16 << 20)
+    assert lib.md_forces_noalloc(ctypes.byref(big), fake, fake, None) == _lib.MD_ERR_WORKSPACE
+    small = md.make_params(32000, 33.59192)
+    assert md.md_workspace_bytes(small) <= (16 << 20)
     assert lib.md_check(None, 0, None, None) == _lib.MD_ERR_WORKSPACE
     assert b"workspace" in lib.md_last_error()
     assert lib.md_loss(ctypes.byref(p), fake, need, None, None) == _lib.MD_ERR_ARG
