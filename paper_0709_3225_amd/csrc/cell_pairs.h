@@ -607,5 +607,142 @@ __device__ __forceinline__ void screen_mfma(const float4* tile, int first, int n
     }
 }
 
+// ---- neighbourhood of a cell on an x face as x-row pieces -------------------
+// The 27-cell neighbourhood is nine x-rows (dy, dz). In each row the cells
+// that need no image shift in x are consecutive in the sorted arrays (piece A:
+// three cells, or two for a home cell on an x face); on an x face the row's
+// third cell wraps around the box (piece B, one cell, shifted by -+L in x).
+// Interior cells take the scalar row table RowHood; this one, for the cells on
+// the x faces, stages them in one pass too instead of through the LDS segment
+// table of 27 single cells.
+// Pieces are staged in the order A0..A8, B0..B8, so the tile holds the
+// neighbourhood without gaps. The piece table is held one piece per lane
+// (lane k < 9: Ak, lane 9 + k: Bk); the rest is uniform.
+struct RowPieces {
+    int first = 0, pos = 0, len = 0;  // this lane's piece: sorted slot and tile index of its first atom, length
+    int total, home_first, n_home, home_pos;
+    float ox, oy, oz;   // home-cell origin
+    float fxb;          // frame offset in x of the B pieces
+    float fy[3], fz[3];  // frame offsets o - sh of rows with dy, dz = -1, 0, 1
+    bool face;
+};
+
+// Fill r for home cell c (local index, uniform). Lane k < 9 reads the CSR
+// offsets of row k's piece A (four consecutive entries: the start array has
+// four entries of padding after its end) and, on a face, of its piece B.
+__device__ __forceinline__ void row_pieces(const SimArgs& a, int c, RowPieces& r) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x;
+    const int nc = a.nc;
+    const int nn = nc * nc;
+    const int iz = c / nn;
+    const int rem = c - iz * nn;
+    const int iy = rem / nc;
+    const int ix = rem - iy * nc;
+    r.face = ix == 0 || ix == nc - 1;
+    r.ox = static_cast<float>(ix) * a.s;
+    r.oy = static_cast<float>(iy) * a.s;
+    r.oz = static_cast<float>(iz) * a.s;
+    r.fy[0] = iy == 0 ? r.oy + a.box : r.oy;
+    r.fy[1] = r.oy;
+    r.fy[2] = iy == nc - 1 ? r.oy - a.box : r.oy;
+    r.fz[0] = iz == 0 ? r.oz + a.box : r.oz;
+    r.fz[1] = r.oz;
+    r.fz[2] = iz == nc - 1 ? r.oz - a.box : r.oz;
+    r.fxb = ix == 0 ? r.ox + a.box : r.ox - a.box;
+    // first cell of piece A; the home cell is cell hoff of it (0 or 1)
+    const int a0 = ix == 0 ? 0 : (ix == nc - 1 ? nc - 2 : ix - 1);
+    const int hoff = ix - a0;
+    const int bcell = ix == 0 ? nc - 1 : 0;
+    Int4u row = {0, 0, 0, 0};
+    int b0 = 0, b1 = 0;
+    if (lane < 9) {
+        int jy = iy + lane % 3 - 1, jz = iz + lane / 3 - 1;
+        jy = jy < 0 ? jy + nc : (jy >= nc ? jy - nc : jy);
+        jz = jz < 0 ? jz + nc : (jz >= nc ? jz - nc : jz);
+        const int* rs = a.start + a.cbase + nc * (jy + nc * jz);
+        row = *reinterpret_cast<const Int4u*>(rs + a0);
+        if (r.face) {
+            b0 = rs[bcell];
+            b1 = rs[bcell + 1];
+        }
+    }
+    const int aend = r.face ? row.z : row.w;
+    if (lane < 9) {
+        r.first = row.x;
+        r.len = aend - row.x;
+    }
+    if (r.face) {  // B pieces to lanes 9..17
+        const int src = lane >= 9 && lane < 18 ? lane - 9 : 0;
+        const int bf = __shfl(b0, src), bl = __shfl(b1 - b0, src);
+        if (lane >= 9 && lane < 18) {
+            r.first = bf;
+            r.len = bl;
+        }
+    }
+    const int incl = wave_incl_scan(r.len);
+    r.pos = incl - r.len;
+    r.total = __builtin_amdgcn_readlane(incl, 17);
+    const int hb = hoff == 0 ? row.x : row.y, he = hoff == 0 ? row.y : row.z;
+    r.home_first = __builtin_amdgcn_readlane(hb, 4);
+    r.n_home = __builtin_amdgcn_readlane(he, 4) - r.home_first;
+    r.home_pos = __builtin_amdgcn_readlane(r.pos, 4) + (r.home_first - __builtin_amdgcn_readlane(r.first, 4));
+}
+
+// Staging of nine pieces (table lanes k0 .. k0 + 8) in one pass by the
+// unmasked scheme of stage_whole: every lane loads and stores entry
+// pos + lane of each piece; pieces are written in order, so a piece's surplus
+// entries are overwritten by a later piece or fall into the padding after the
+// total. Atoms 64 and up of a longer piece follow, masked. RAW: the
+// untranslated positions (w = user index) go to raw at the same indices.
+template <int K0, bool RAW>
+__device__ __forceinline__ void stage_nine(const SimArgs& a, const RowPieces& r, float fx, float4* tile,
+                                           float4* raw) {
+    const int lane = threadIdx.x;
+    const int last = a.natoms - 1;
+    const char* pbase = reinterpret_cast<const char*>(a.pos0);
+    float4 q[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const uint32_t off = static_cast<uint32_t>(min(__builtin_amdgcn_readlane(r.first, K0 + k) + lane, last)) << 4;
+        q[k] = *reinterpret_cast<const float4*>(pbase + off);
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const float x = q[k].x - fx;
+        const float y = q[k].y - r.fy[k % 3];
+        const float z = q[k].z - r.fz[k / 3];
+        const int p = __builtin_amdgcn_readlane(r.pos, K0 + k);
+        tile[p + lane] = make_float4(x, y, z, x * x + y * y + z * z);
+        if (RAW) raw[p + lane] = q[k];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (__any(lane >= K0 && lane < K0 + 9 && r.len > kWave)) {  // rare
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const int len = __builtin_amdgcn_readlane(r.len, K0 + k);
+            if (len > kWave) {
+                const int f = __builtin_amdgcn_readlane(r.first, K0 + k), p = __builtin_amdgcn_readlane(r.pos, K0 + k);
+                for (int off = kWave + lane; off - lane < len; off += kWave) {
+                    if (off < len) {
+                        const float4 v = a.pos0[f + off];
+                        const float x = v.x - fx, y = v.y - r.fy[k % 3], z = v.z - r.fz[k / 3];
+                        tile[p + off] = make_float4(x, y, z, x * x + y * y + z * z);
+                        if (RAW) raw[p + off] = v;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// The whole neighbourhood of r in one pass (total <= tile capacity; the tile
+// needs room for total + 63 entries).
+template <bool RAW>
+__device__ __forceinline__ void stage_pieces(const SimArgs& a, const RowPieces& r, float4* tile, float4* raw) {
+    stage_nine<0, RAW>(a, r, r.ox, tile, raw);
+    if (r.face) stage_nine<9, RAW>(a, r, r.fxb, tile, raw);
+}
+
 }  // namespace
 }  // namespace mdlj

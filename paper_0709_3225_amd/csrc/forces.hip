@@ -147,7 +147,8 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
     // pass is staged here, from a table in scalar registers; others take the
     // LDS table and stage in the pass loop below
     RowHood rh;
-    const bool rows = row_hood(a, c, rh) && rh.pos[9] <= a.tile_cap && rh.n_home <= kWave;
+    const bool interior = row_hood(a, c, rh);  // uniform
+    bool rows = interior && rh.pos[9] <= a.tile_cap && rh.n_home <= kWave;
     int total, home_first, n_home, home_pos;
     if (rows) {
         ox = rh.ox;
@@ -158,7 +159,22 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         n_home = rh.n_home;
         home_pos = rh.home_pos;
         stage_rows<EXPORT>(a, rh, tile, raw);
-    } else {
+    }
+    // a cell on an x face: the same one-pass staging from a table of row pieces
+    RowPieces rp;
+    if (!interior) row_pieces(a, c, rp);
+    if (!interior && rp.total <= a.tile_cap && rp.n_home <= kWave) {
+        rows = true;
+        ox = rp.ox;
+        oy = rp.oy;
+        oz = rp.oz;
+        total = rp.total;
+        home_first = rp.home_first;
+        n_home = rp.n_home;
+        home_pos = rp.home_pos;
+        stage_pieces<EXPORT>(a, rp, tile, raw);
+    }
+    if (!rows) {
         load_neighbourhood(a, c, nb, ox, oy, oz);
         total = nb.total;
         home_first = nb.home_first;
