@@ -73,6 +73,15 @@ typedef struct md_params {
     int32_t shift_mode;    /* 0: force shifted to zero at r_c (section 2);
                               1: plain truncated force, energy shifted */
     int32_t flags;         /* MD_FLAG_* bits; 0 for a plain workspace */
+    int32_t waves_per_cell; /* wavefronts per home cell in the force pass:
+                              1, 2 or 4, sharing one staged neighbourhood and
+                              splitting its candidates (0 selects 1). More
+                              than one pays only on grids with too few cells
+                              to fill the GPU. The pairs are the same for
+                              every choice; only the order of the FP32 force
+                              sums differs (bitwise reproducible for a fixed
+                              choice). The pair-list and neighbour-export
+                              passes always take one. */
 } md_params;
 
 /* md_params.flags: lay the workspace out with md_step_list's pair-list
@@ -180,7 +189,8 @@ md_status md_step_every(const md_params* p, void* ws, size_t ws_bytes, int32_t n
  * candidates); until the next rebuild the force pass walks the kept words
  * instead of screening. They hold the same candidates in the same order as
  * the screen plus some beyond r_c that add exact zeros, so the trajectory is
- * bitwise that of md_step_every with the same arguments. MD_DEV_SKIN is set
+ * bitwise that of md_step_every with the same arguments and one wavefront
+ * per cell (these passes always take one). MD_DEV_SKIN is set
  * if an atom moves more than (cell side - r_c) / 2 from where it was when the
  * words were kept. Cells that need more than one LDS pass, or more than four
  * 128-candidate spans per lane, screen as usual. Arguments and return values
@@ -329,7 +339,8 @@ md_status md_adjoint_seed(const md_params* p, void* ws, size_t ws_bytes, float s
  * captures a whole multi-step run into one graph that md_graph_launch starts
  * with a single call. Each replica follows exactly the arithmetic of md_step
  * on that system alone (same cell grid, LDS pass length and summation order),
- * so its results are bitwise those of a solo run.
+ * so its results are bitwise those of a solo run with the same
+ * waves_per_cell (taken from p for the whole batch).
  *
  * Shared parameters (epsilon, sigma, mass, rc_over_sigma, dt, shift_mode)
  * come from p; p->n and p->box are ignored. The minimum cell side is the

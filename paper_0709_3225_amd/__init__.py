@@ -26,6 +26,6 @@ from ._lib import (  # noqa: F401
 from .system import LJSystem, occupancy_cell_min  # noqa: F401
 from .adjoint import LJTrajectory, trajectory_gradients  # noqa: F401
 from .batch import BatchedLJ  # noqa: F401
-from .tune import grid_options, tune_batch, tune_cell_min  # noqa: F401
+from .tune import grid_options, tune_batch, tune_cell_min, tune_system  # noqa: F401
 
 lib()

@@ -81,6 +81,7 @@ class MDParams(ctypes.Structure):
         ("cell_min", ctypes.c_float),
         ("shift_mode", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("waves_per_cell", ctypes.c_int32),
     ]
 
 
@@ -100,9 +101,9 @@ def replica_table(reps):
 
 
 def make_params(n, box, epsilon=1.0, sigma=1.0, mass=1.0, rc_over_sigma=2.5, dt=0.005, cell_min=0.0,
-                shift_mode=0, flags=0) -> MDParams:
+                shift_mode=0, flags=0, waves_per_cell=0) -> MDParams:
     return MDParams(int(n), float(box), float(epsilon), float(sigma), float(mass), float(rc_over_sigma),
-                    float(dt), float(cell_min), int(shift_mode), int(flags))
+                    float(dt), float(cell_min), int(shift_mode), int(flags), int(waves_per_cell))
 
 
 _lib = None

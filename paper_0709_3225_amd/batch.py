@@ -18,13 +18,14 @@ from . import _lib as L
 
 class BatchedLJ:
     def __init__(self, replicas, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_over_sigma=2.5, dt=0.005, cell_min=0.0,
-                 shift_mode=0, device="cuda"):
+                 shift_mode=0, waves_per_cell=0, device="cuda"):
         """replicas: sequence of (n, box) or (n, box, cell_min); a replica's
         nonzero cell_min replaces the shared one (tune.tune_batch picks them)."""
         self.replicas = [(int(r[0]), float(r[1]), float(r[2]) if len(r) > 2 else 0.0) for r in replicas]
         self.count = len(self.replicas)
         self.table = L.replica_table(self.replicas)
-        self.params = L.make_params(1, 1.0, epsilon, sigma, mass, rc_over_sigma, dt, cell_min, shift_mode)
+        self.params = L.make_params(1, 1.0, epsilon, sigma, mass, rc_over_sigma, dt, cell_min, shift_mode, 0,
+                                    waves_per_cell)
         self.nbytes = int(L.lib().md_batch_workspace_bytes(ctypes.byref(self.params), self.table, self.count))
         if self.nbytes == 0:
             # reproduce the validation error with its message

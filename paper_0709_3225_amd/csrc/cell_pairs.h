@@ -73,7 +73,7 @@ struct HoodSegs {
 // waits for them here.
 __device__ __forceinline__ void hood_issue(const SimArgs& a, int c, HoodLoads& h) {
 #pragma clang fp contract(off)
-    const int lane = threadIdx.x;
+    const int lane = __lane_id();
     const int nc = a.nc;
     const int ix = c % nc, iy = (c / nc) % nc, iz = c / (nc * nc);
     float ox, oy, oz;
@@ -101,7 +101,7 @@ __device__ __forceinline__ float lane_value(float v, int l) {
 
 // Segments of a neighbourhood from its CSR ranges (waits for hood_issue's loads).
 __device__ __forceinline__ void hood_segments(const SimArgs& a, const HoodLoads& h, HoodSegs& g) {
-    const int lane = threadIdx.x;
+    const int lane = __lane_id();
     const int cnt = lane < 27 ? h.next - h.first : 0;
     const int incl = wave_incl_scan(cnt);
     const int pos = incl - cnt;
@@ -136,7 +136,7 @@ __device__ __forceinline__ void hood_segments(const SimArgs& a, const HoodLoads&
 
 // Write the table to LDS (the caller synchronises before it is read).
 __device__ __forceinline__ void hood_store(const HoodSegs& g, Neighbourhood& nb) {
-    const int lane = threadIdx.x;
+    const int lane = __lane_id();
     if (lane < g.nseg()) {
         nb.seg_pos[lane] = g.pos;
         nb.seg_first[lane] = g.first;
@@ -155,7 +155,7 @@ __device__ __forceinline__ void hood_store(const HoodSegs& g, Neighbourhood& nb)
 
 // The segment table of nb back in registers (lane l holds segment l).
 __device__ __forceinline__ HoodSegs hood_from_lds(const Neighbourhood& nb) {
-    const int lane = threadIdx.x;
+    const int lane = __lane_id();
     HoodSegs g;
     const int nseg = nb.nseg;
     g.meta = lane == 0 ? nb.total : lane == 1 ? nb.home_pos : lane == 2 ? nb.home_first : lane == 3 ? nb.n_home : nseg;
@@ -178,7 +178,7 @@ __device__ __forceinline__ void load_neighbourhood(const SimArgs& a, int c, Neig
     hood_issue(a, c, h);
     HoodSegs g;
     hood_segments(a, h, g);
-    hood_store(g, nb);
+    if (threadIdx.x < kWave) hood_store(g, nb);  // every wavefront holds the same table
     cell_origin(a, c, ox, oy, oz);
     __syncthreads();
 }
@@ -232,7 +232,7 @@ __device__ __forceinline__ void stage_chunk(const HoodSegs& h, StageCursor& cur,
 template <int B, bool WITH_VEC>
 __device__ __forceinline__ void stage_issue(const SimArgs& a, const HoodSegs& h, StageCursor& cur, int t1,
                                             StageBatch<B, WITH_VEC>& b, const float4* vec) {
-    const int lane = threadIdx.x;
+    const int lane = __lane_id();
 #pragma unroll
     for (int u = 0; u < B; ++u) {
         int slot = 0;  // lanes without an atom load slot 0 (always valid) and store nothing
@@ -250,7 +250,7 @@ __device__ __forceinline__ void stage_issue(const SimArgs& a, const HoodSegs& h,
 template <int B, bool ID_IN_W, bool WITH_VEC>
 __device__ __forceinline__ void stage_commit(const HoodSegs& h, const StageBatch<B, WITH_VEC>& b, StageCursor& cur,
                                              int t0, int t1, float4* tile, float4* vtile) {
-    const int lane = threadIdx.x;
+    const int lane = __lane_id();
 #pragma unroll
     for (int u = 0; u < B; ++u) {
         if (stage_more(h, cur, t1)) {
@@ -280,7 +280,7 @@ __device__ __forceinline__ void stage_commit(const HoodSegs& h, const StageBatch
 // j < k). The tile needs room for total + 63 entries.
 template <bool ID_IN_W>
 __device__ __forceinline__ void stage_whole(const SimArgs& a, const HoodSegs& h, float4* tile) {
-    const int lane = threadIdx.x;
+    const int lane = __lane_id();
     const int nseg = h.nseg();  // 9 or 27
     const int last = a.natoms - 1;
     // 32-bit byte offsets from the array base (scalar base + vector offset loads)
@@ -341,7 +341,7 @@ typedef int Int4u __attribute__((ext_vector_type(4), aligned(4)));
 
 __device__ __forceinline__ bool row_hood(const SimArgs& a, int c, RowHood& r) {
 #pragma clang fp contract(off)
-    const int lane = threadIdx.x;
+    const int lane = __lane_id();
     const int nc = a.nc;
     const int ix = __builtin_amdgcn_readfirstlane(c % nc);
     const int iy = __builtin_amdgcn_readfirstlane((c / nc) % nc);
@@ -390,7 +390,7 @@ __device__ __forceinline__ bool row_hood(const SimArgs& a, int c, RowHood& r) {
 // indices.
 template <bool RAW = false>
 __device__ __forceinline__ void stage_rows(const SimArgs& a, const RowHood& r, float4* tile, float4* raw = nullptr) {
-    const int lane = threadIdx.x;
+    const int lane = __lane_id();
     const int last = a.natoms - 1;
     const char* pbase = reinterpret_cast<const char*>(a.pos0);
     float4 q[9];
@@ -468,6 +468,13 @@ constexpr int kGroups = 32 * kWords;   // candidates per lane per span
 constexpr int kMaxSlices = 16;
 constexpr int kScreenUnroll = 4;
 constexpr int kTilePad = kMaxSlices * (kScreenUnroll + 1);  // far-away entries after the staged atoms
+constexpr int kMaxCellWaves = 4;                            // wavefronts per force workgroup
+
+// LDS entries (float4) of a force workgroup: the tile and its padding, which
+// the reduction reuses (five floats per lane and wavefront)
+__host__ __device__ constexpr size_t cell_lds_entries(int tile_cap, int waves) {
+    return static_cast<size_t>(tile_cap + kTilePad > 80 * waves ? tile_cap + kTilePad : 80 * waves);
+}
 
 // Screen of one span: word w, bit 31 - k holds the verdict on the lane's
 // candidate 32 w + k, i.e. tile entry first + (32 w + k) * ns. groups is the
@@ -580,7 +587,7 @@ typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 // candidate first + 4 (32 w + k) + s. bval: this lane's B element; cneg: C.
 __device__ __forceinline__ void screen_mfma(const float4* tile, int first, int nblk, float bval, float cneg,
                                             uint32_t (&wd)[kWords]) {
-    const int lane = threadIdx.x;
+    const int lane = __lane_id();
     const int row = lane & 15;  // A row: candidate 4 (row % 4) + row / 4 of each block
     const float* base = reinterpret_cast<const float*>(tile + first) + (4 * (row & 3) + (row >> 2)) * 4 + (lane >> 4);
     const mfma_f4 c = {cneg, cneg, cneg, cneg};
@@ -632,7 +639,7 @@ struct RowPieces {
 // four entries of padding after its end) and, on a face, of its piece B.
 __device__ __forceinline__ void row_pieces(const SimArgs& a, int c, RowPieces& r) {
 #pragma clang fp contract(off)
-    const int lane = threadIdx.x;
+    const int lane = __lane_id();
     const int nc = a.nc;
     const int nn = nc * nc;
     const int iz = c / nn;
@@ -698,7 +705,7 @@ __device__ __forceinline__ void row_pieces(const SimArgs& a, int c, RowPieces& r
 template <int K0, bool RAW>
 __device__ __forceinline__ void stage_nine(const SimArgs& a, const RowPieces& r, float fx, float4* tile,
                                            float4* raw) {
-    const int lane = threadIdx.x;
+    const int lane = __lane_id();
     const int last = a.natoms - 1;
     const char* pbase = reinterpret_cast<const char*>(a.pos0);
     float4 q[9];

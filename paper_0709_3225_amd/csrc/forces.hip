@@ -138,10 +138,18 @@ __device__ __forceinline__ void kept_words(const uint4* rows, const uint4& w0, i
 // usual (and with the plain bound).
 // EXPORT: no forces; the pairs the walk accepts go to the neighbour rows of
 // ex (raw: a second tile of untranslated positions).
-template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT, bool SKIN = false, int LIST = 0, bool EXPORT = false>
+template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT, bool SKIN = false, int LIST = 0, bool EXPORT = false,
+          int MW = 1>
 __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile, Neighbourhood& nb, float* red,
                                            float4* raw = nullptr, const ExportArgs& ex = ExportArgs{}) {
-    const int lane = threadIdx.x;
+    // The workgroup holds nw <= MW wavefronts (1, 2 or 4). All of them compute
+    // the neighbourhood table; wavefront 0 stages the tile they share, each
+    // screens and walks its own contiguous range of every pass's candidates,
+    // and wavefront 0 adds their partials (waves in order, then slices) and
+    // runs the epilogue. MW = 1 compiles the one-wavefront kernel.
+    const int lane = __lane_id();
+    const int wv = MW == 1 ? 0 : static_cast<int>(threadIdx.x) >> 6;  // uniform per wavefront
+    const int nw = MW == 1 ? 1 : static_cast<int>(blockDim.x) >> 6;
     float ox, oy, oz;
     // a cell away from the x faces whose neighbourhood and home atoms fit one
     // pass is staged here, from a table in scalar registers; others take the
@@ -158,7 +166,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         home_first = rh.home_first;
         n_home = rh.n_home;
         home_pos = rh.home_pos;
-        stage_rows<EXPORT>(a, rh, tile, raw);
+        if (wv == 0) stage_rows<EXPORT>(a, rh, tile, raw);
     }
     // a cell on an x face: the same one-pass staging from a table of row pieces
     RowPieces rp;
@@ -172,7 +180,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         home_first = rp.home_first;
         n_home = rp.n_home;
         home_pos = rp.home_pos;
-        stage_pieces<EXPORT>(a, rp, tile, raw);
+        if (wv == 0) stage_pieces<EXPORT>(a, rp, tile, raw);
     }
     if (!rows) {
         load_neighbourhood(a, c, nb, ox, oy, oz);
@@ -204,9 +212,9 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         const int hstride = mf ? 16 : nh;  // lanes of one home atom: h, h + hstride, ...
         const int h = lane % hstride, s = lane / hstride;
         const bool act = mf ? h < nh : s < ns;
-        // the lane that finishes home atom h; in the matrix-core layout lanes
-        // nh..15 have s == 0 but no atom
-        const bool lead = act && s == 0;
+        // the lane that finishes home atom h (in wavefront 0); in the
+        // matrix-core layout lanes nh..15 have s == 0 but no atom
+        const bool lead = act && s == 0 && wv == 0;
         float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
         if (act) pi = a.pos0[home_first + h0 + h];
         float4 vel = make_float4(0.f, 0.f, 0.f, 0.f);  // fetched now, used by the epilogue
@@ -230,10 +238,13 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
             const int tn = min(a.tile_cap, total - t0);
             if (!rows) {
                 __syncthreads();
-                if (EXPORT) stage_tile<false, true>(a, nb, tile, t0, tn, a.pos0, raw);
-                else stage_tile<false>(a, nb, tile, t0, tn);
+                if (wv == 0) {
+                    if (EXPORT) stage_tile<false, true>(a, nb, tile, t0, tn, a.pos0, raw);
+                    else stage_tile<false>(a, nb, tile, t0, tn);
+                }
             }
-            for (int t = lane; t < kTilePad; t += kWave) tile[tn + t] = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
+            if (wv == 0)
+                for (int t = lane; t < kTilePad; t += kWave) tile[tn + t] = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
             __syncthreads();
             const int self_t = home_pos + h0 + h - t0;  // the home atom's own tile index (may be outside)
             // the walk over one span's words; the lane's candidates are cand0,
@@ -256,9 +267,13 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                 }
             };
             if (mf) {
+                // this wavefront's blocks [b_lo, b_hi), split at multiples of four
+                // blocks (the screen's step), so no verdict is taken twice
                 const int nblk_all = (tn + 15) / 16;
-                for (int b0 = 0; b0 < nblk_all; b0 += 8 * kWords) {
-                    const int nblk = min(8 * kWords, nblk_all - b0);
+                const int q4 = (nblk_all + 3) >> 2;
+                const int b_lo = 4 * ((q4 * wv) / nw), b_hi = min(nblk_all, 4 * ((q4 * (wv + 1)) / nw));
+                for (int b0 = b_lo; b0 < b_hi; b0 += 8 * kWords) {
+                    const int nblk = min(8 * kWords, b_hi - b0);
                     uint32_t wd[kWords];
                     if (LIST == 2 && use_list) {
                         kept_words(lwords, lw0, b0 / (8 * kWords), 4 * nblk, wd);
@@ -273,8 +288,12 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                 continue;
             }
             const int groups_all = (tn + ns - 1) / ns;  // candidates of the largest slice
-            for (int g0 = 0; g0 < groups_all; g0 += kGroups) {
-                const int groups = min(kGroups, groups_all - g0);
+            // this wavefront's groups [g_lo, g_hi), split at multiples of the screen's step
+            const int q4 = (groups_all + kScreenUnroll - 1) / kScreenUnroll;
+            const int g_lo = kScreenUnroll * ((q4 * wv) / nw);
+            const int g_hi = min(groups_all, kScreenUnroll * ((q4 * (wv + 1)) / nw));
+            for (int g0 = g_lo; g0 < g_hi; g0 += kGroups) {
+                const int groups = min(kGroups, g_hi - g0);
                 const int first = g0 * ns + (act ? s : 0);
                 uint32_t wd[kWords];
                 if (LIST == 2 && use_list) {
@@ -298,12 +317,13 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         // sum the slice partials of each home atom in slice order (red aliases the
         // tile: every lane has finished its walk at this barrier)
         __syncthreads();
-        red[0 * kWave + lane] = fx;
-        red[1 * kWave + lane] = fy;
-        red[2 * kWave + lane] = fz;
+        float* mine = red + 5 * kWave * wv;  // this wavefront's partials
+        mine[0 * kWave + lane] = fx;
+        mine[1 * kWave + lane] = fy;
+        mine[2 * kWave + lane] = fz;
         if (ENERGY) {
-            red[3 * kWave + lane] = u_loc;
-            red[4 * kWave + lane] = w_loc;
+            mine[3 * kWave + lane] = u_loc;
+            mine[4 * kWave + lane] = w_loc;
         }
         __syncthreads();
         const int k = home_first + h0 + h;
@@ -311,14 +331,17 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         float4 p_next = pi, v_next = make_float4(0.f, 0.f, 0.f, 0.f);
         if (lead) {
             float gx = 0.f, gy = 0.f, gz = 0.f, gu = 0.f, gw = 0.f;
-            for (int q = 0; q < ns; ++q) {
-                const int l = h + q * hstride;
-                gx += red[0 * kWave + l];
-                gy += red[1 * kWave + l];
-                gz += red[2 * kWave + l];
-                if (ENERGY) {
-                    gu += red[3 * kWave + l];
-                    gw += red[4 * kWave + l];
+            for (int w = 0; w < nw; ++w) {
+                const float* part = red + 5 * kWave * w;
+                for (int q = 0; q < ns; ++q) {
+                    const int l = h + q * hstride;
+                    gx += part[0 * kWave + l];
+                    gy += part[1 * kWave + l];
+                    gz += part[2 * kWave + l];
+                    if (ENERGY) {
+                        gu += part[3 * kWave + l];
+                        gw += part[4 * kWave + l];
+                    }
                 }
             }
             if (!finite3(gx, gy, gz)) bad = true;
@@ -359,7 +382,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                 }
             }
         }
-        if (DRIFT && !SKIN) bin_atom(a, p_next, v_next, c_next);  // all lanes
+        if (DRIFT && !SKIN && wv == 0) bin_atom(a, p_next, v_next, c_next);  // all lanes of wavefront 0
     }
     if (LIST == 1) a.plist_n[lrow] = list_fits ? n_rec : kListSpans + 1;  // kept words of several passes are not used
     if (EXPORT && over) atomicOr(&a.hdr[HDR_ERROR], DEV_NB_OVERFLOW);
@@ -369,7 +392,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         u_acc = wave_sum(u_acc);
         w_acc = wave_sum(w_acc);
         k_acc = wave_sum(k_acc);
-        if (lane == 0) {
+        if (threadIdx.x == 0) {
             double* e = a.epart + 3 * static_cast<size_t>(a.cbase + c);
             e[0] = u_acc;
             e[1] = w_acc;
@@ -378,31 +401,31 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
     }
 }
 
-template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT>
-__global__ void __launch_bounds__(kWave) k_forces(SimArgs a, bool from_step) {
+template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT, int MW>
+__global__ void __launch_bounds__(MW * kWave) k_forces(SimArgs a, bool from_step) {
     if (from_step) {
         if (a.hdr[HDR_ERROR] & DEV_ORDER) return;
     } else if (!state_ok(a, false)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&a.hdr[HDR_ERROR], DEV_ORDER);
         return;
     }
-    extern __shared__ float4 tile[];  // a.tile_cap + kTilePad entries
+    extern __shared__ float4 tile[];  // cell_lds_entries(a.tile_cap, a.waves) entries
     __shared__ Neighbourhood nb;
-    // the slice reduction reuses the tile (at least kTilePad = 80 entries, 320 floats)
-    force_cell<KICK, ENERGY, WRITE, DRIFT>(a, xcd_block_order(blockIdx.x, a.ncells), tile, nb,
-                                           reinterpret_cast<float*>(tile));
+    // the slice reduction reuses the tile (320 floats per wavefront)
+    force_cell<KICK, ENERGY, WRITE, DRIFT, false, 0, false, MW>(a, xcd_block_order(blockIdx.x, a.ncells), tile, nb,
+                                                                reinterpret_cast<float*>(tile));
     if (WRITE && blockIdx.x == 0 && threadIdx.x == 0) a.hdr[HDR_STATE] = STATE_FORCES;
 }
 
 // A step between rebuilds (md_step_every): forces, kick, and the next step's
 // half kick and drift into pos2/vel2.
-template <bool ENERGY>
-__global__ void __launch_bounds__(kWave) k_forces_skin(SimArgs a) {
+template <bool ENERGY, int MW>
+__global__ void __launch_bounds__(MW * kWave) k_forces_skin(SimArgs a) {
     if (a.hdr[HDR_ERROR] & DEV_ORDER) return;
     extern __shared__ float4 tile[];
     __shared__ Neighbourhood nb;
-    force_cell<true, ENERGY, false, true, true>(a, xcd_block_order(blockIdx.x, a.ncells), tile, nb,
-                                                reinterpret_cast<float*>(tile));
+    force_cell<true, ENERGY, false, true, true, 0, false, MW>(a, xcd_block_order(blockIdx.x, a.ncells), tile, nb,
+                                                              reinterpret_cast<float*>(tile));
 }
 
 // Pair-list steps: RECORD right after a rebuild, else walk the recorded lists;
@@ -419,17 +442,17 @@ __global__ void __launch_bounds__(kWave) k_forces_list(SimArgs a) {
 // Batched forces: one workgroup per listed cell (global cell indices of the
 // replicas of one tile class, XCD-ordered); the replica's own geometry comes
 // from its descriptor.
-template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT>
-__global__ void __launch_bounds__(kWave)
+template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT, int MW>
+__global__ void __launch_bounds__(MW * kWave)
     k_batch_forces(SimArgs base, const Replica* __restrict__ reps, const int* __restrict__ cell_rep,
                    const int* __restrict__ cells, int ncl) {
     if (base.hdr[HDR_ERROR] & DEV_ORDER) return;
-    extern __shared__ float4 tile[];  // the class's largest tile_cap + kTilePad entries
+    extern __shared__ float4 tile[];  // cell_lds_entries of the class's largest tile_cap
     __shared__ Neighbourhood nb;
     float* red = reinterpret_cast<float*>(tile);  // slice reduction, as in k_forces
     const int gc = cells[xcd_block_order(blockIdx.x, ncl)];
     const SimArgs a = replica_view(base, reps[cell_rep[gc]]);
-    force_cell<KICK, ENERGY, WRITE, DRIFT>(a, gc - a.cbase, tile, nb, red);
+    force_cell<KICK, ENERGY, WRITE, DRIFT, false, 0, false, MW>(a, gc - a.cbase, tile, nb, red);
     if (WRITE && blockIdx.x == 0 && threadIdx.x == 0) base.hdr[HDR_STATE] = STATE_FORCES;
 }
 
@@ -547,9 +570,13 @@ hipError_t launch_forces(const SimArgs& a_in, bool kick, bool energy, bool write
                          int par, hipStream_t st) {
     SimArgs a = a_in;
     a.par = par;
-    const dim3 g(a.ncells), b(kWave);
-    const size_t lds = sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
-#define MD_FORCES(K, E, W, D) hipLaunchKernelGGL((k_forces<K, E, W, D>), g, b, lds, st, a, from_step)
+    const dim3 g(a.ncells), b(kWave * a.waves);
+    const size_t lds = sizeof(float4) * cell_lds_entries(a.tile_cap, a.waves);
+#define MD_FORCES(K, E, W, D)                                                                          \
+    do {                                                                                               \
+        if (a.waves == 1) hipLaunchKernelGGL((k_forces<K, E, W, D, 1>), g, b, lds, st, a, from_step);  \
+        else hipLaunchKernelGGL((k_forces<K, E, W, D, kMaxCellWaves>), g, b, lds, st, a, from_step);   \
+    } while (0)
     if (kick && drift && !write_force) {
         if (energy) MD_FORCES(true, true, false, true);
         else MD_FORCES(true, false, false, true);
@@ -568,16 +595,22 @@ hipError_t launch_forces(const SimArgs& a_in, bool kick, bool energy, bool write
 }
 
 hipError_t launch_forces_skin(const SimArgs& a, bool energy, hipStream_t st) {
-    const dim3 g(a.ncells), b(kWave);
-    const size_t lds = sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
-    if (energy) hipLaunchKernelGGL(k_forces_skin<true>, g, b, lds, st, a);
-    else hipLaunchKernelGGL(k_forces_skin<false>, g, b, lds, st, a);
+    const dim3 g(a.ncells), b(kWave * a.waves);
+    const size_t lds = sizeof(float4) * cell_lds_entries(a.tile_cap, a.waves);
+    if (a.waves == 1) {
+        if (energy) hipLaunchKernelGGL((k_forces_skin<true, 1>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((k_forces_skin<false, 1>), g, b, lds, st, a);
+    } else {
+        if (energy) hipLaunchKernelGGL((k_forces_skin<true, kMaxCellWaves>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((k_forces_skin<false, kMaxCellWaves>), g, b, lds, st, a);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_forces_list(const SimArgs& a_in, bool energy, bool record, bool bin, int par, hipStream_t st) {
     SimArgs a = a_in;
     a.par = par;
+    a.waves = 1;  // the kept words are per lane of one wavefront
     const dim3 g(a.ncells), b(kWave);
     const size_t lds = sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
 #define MD_LIST(E, R, B) hipLaunchKernelGGL((k_forces_list<E, R, B>), g, b, lds, st, a)
@@ -617,10 +650,16 @@ hipError_t launch_batch_forces(const SimArgs& base_in, const Replica* reps, cons
                                hipStream_t st) {
     SimArgs base = base_in;
     base.par = par;
-    const dim3 g(ncl), b(kWave);
-    const size_t lds = sizeof(float4) * static_cast<size_t>(tile_cap + kTilePad);
-#define MD_FORCES(K, E, W, D) \
-    hipLaunchKernelGGL((k_batch_forces<K, E, W, D>), g, b, lds, st, base, reps, cell_rep, cells, ncl)
+    const dim3 g(ncl), b(kWave * base.waves);
+    const size_t lds = sizeof(float4) * cell_lds_entries(tile_cap, base.waves);
+#define MD_FORCES(K, E, W, D)                                                                                      \
+    do {                                                                                                           \
+        if (base.waves == 1)                                                                                       \
+            hipLaunchKernelGGL((k_batch_forces<K, E, W, D, 1>), g, b, lds, st, base, reps, cell_rep, cells, ncl);  \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_batch_forces<K, E, W, D, kMaxCellWaves>), g, b, lds, st, base, reps, cell_rep,   \
+                               cells, ncl);                                                                        \
+    } while (0)
     if (kick && drift && !write_force) {
         if (energy) MD_FORCES(true, true, false, true);
         else MD_FORCES(true, false, false, true);

@@ -57,6 +57,8 @@ md_status validate(const md_params* p) {
         return fail(MD_ERR_ARG, "cell_min must be finite and >= 0");
     if (p->shift_mode != 0 && p->shift_mode != 1) return fail(MD_ERR_ARG, "shift_mode must be 0 or 1");
     if ((p->flags & ~MD_FLAG_PAIR_LISTS) != 0) return fail(MD_ERR_ARG, "flags hold unknown bits 0x%x", p->flags);
+    if (p->waves_per_cell != 0 && p->waves_per_cell != 1 && p->waves_per_cell != 2 && p->waves_per_cell != 4)
+        return fail(MD_ERR_ARG, "waves_per_cell must be 0, 1, 2 or 4 (got %d)", p->waves_per_cell);
     const float rc = cutoff(p);
     if (!(rc > 0.f) || !std::isfinite(rc)) return fail(MD_ERR_ARG, "cutoff must be finite and > 0");
     if (!(p->box >= 2.0f * rc)) return fail(MD_ERR_BOX, "box %g is shorter than two cutoffs (2 * %g)", p->box, rc);
@@ -168,6 +170,10 @@ int tile_capacity(int n, int ncells) {
     return std::min(2048, std::max(128, cap));
 }
 
+// Wavefronts per force workgroup: the caller's choice, else one (which is
+// as fast or faster from about 2,000 cells up).
+int waves_per_cell(const md_params* p) { return p->waves_per_cell != 0 ? p->waves_per_cell : 1; }
+
 SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     char* b = static_cast<char*>(ws);
     SimArgs a{};
@@ -231,6 +237,7 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     a.list_screen2 = screen_bound(static_cast<double>(L.s), L.s);
     a.disp_half = a.skin_half;
     a.tile_cap = tile_capacity(p->n, L.ncells);
+    a.waves = waves_per_cell(p);
     a.dt = p->dt;
     a.hdt_m = static_cast<float>(0.5 * p->dt / p->mass);
     a.half_m = static_cast<float>(0.5 * p->mass);

@@ -97,6 +97,7 @@ struct SimArgs {
     float uc;        // u_LJ(r_c)
     float screen2;   // conservative bound on r^2 for the dot-product screen
     int tile_cap;    // staged atoms per LDS pass of the force kernel
+    int waves;       // wavefronts per force workgroup (1, 2 or 4), sharing one staged tile
 
     float dt;
     float hdt_m;     // dt / (2 m)

@@ -4,7 +4,10 @@ The only geometric choice the method leaves open is the cell side: section 3
 asks for cells of side at least r_c, and section 3.2 takes the finest such
 grid, n_c = int(L / r_c). Coarser grids stage more candidates per home cell
 but fill more lanes of the one-wavefront-per-cell kernel; which wins depends
-on the occupancy of the cells, so it is measured, not modelled.
+on the occupancy of the cells, so it is measured, not modelled. The force
+pass may also split a cell's candidates over two or four wavefronts
+(md_params.waves_per_cell), which pays only where the grid has too few cells
+to fill the GPU; tune_system measures both knobs on one system.
 
 Replicas are grouped into size buckets (their default grid and its mean
 occupancy). For each bucket the tuner times batched steps of a probe made of
@@ -139,3 +142,45 @@ def tune_cell_min(n: int, box: float, pos4: torch.Tensor, vel4: torch.Tensor, **
     """The tuner on one system (for LJSystem): returns (cell_min, report)."""
     cms, report = tune_batch([(n, box)], pos4, vel4, **kw)
     return cms[0], report
+
+
+def tune_system(n: int, box: float, pos4: torch.Tensor, vel4: torch.Tensor, *, epsilon=1.0, sigma=1.0, mass=1.0,
+                rc_over_sigma=2.5, dt=0.005, shift_mode=0, extra=1, waves=(1, 2, 4), steps=20, warmup=3, repeats=3,
+                min_gain=0.03):
+    """Pick the cell grid and the wavefronts per cell of one system by timing
+    md_step on the system itself (not on copies: a small system's grid holds
+    too few cells to fill the GPU with one wavefront each, which is where
+    several wavefronts per cell pay). Candidates are grid_options x waves; a
+    candidate replaces the default (default grid, one wavefront) only if it
+    is faster per step by at least ``min_gain``. Returns
+    (cell_min, waves_per_cell, report)."""
+    from .system import LJSystem
+
+    shared = dict(epsilon=epsilon, sigma=sigma, mass=mass, rc_over_sigma=rc_over_sigma, dt=dt, shift_mode=shift_mode)
+    t_start = time.perf_counter()
+    stream = torch.cuda.Stream()
+    tried = []
+    for nc, cm in grid_options(n, box, rc_over_sigma=rc_over_sigma, sigma=sigma, extra=extra):
+        for wv in waves:
+            s = LJSystem(n, box, cell_min=cm, waves_per_cell=wv, **shared)
+            events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                      for _ in range(repeats)]
+            # the workspace was allocated on the caller's stream
+            stream.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(stream):
+                s.load(pos4, vel4)
+                s.step(warmup)
+                for e0, e1 in events:
+                    e0.record(stream)
+                    s.step(steps)
+                    e1.record(stream)
+            stream.synchronize()
+            s.check()
+            best_t = min(e0.elapsed_time(e1) for e0, e1 in events) / 1e3 / steps
+            tried.append({"cells_per_dim": nc, "cell_min": cm, "waves_per_cell": wv, "s_per_step": best_t})
+    best = min(tried, key=lambda t: t["s_per_step"])
+    if best["s_per_step"] >= tried[0]["s_per_step"] * (1.0 - min_gain):
+        best = tried[0]
+    report = {"tried": tried, "chosen": {k: best[k] for k in ("cells_per_dim", "cell_min", "waves_per_cell")},
+              "seconds": time.perf_counter() - t_start}
+    return best["cell_min"], best["waves_per_cell"], report

@@ -75,6 +75,9 @@ def test_cell_min_parameter():
     (dict(dt=-0.1), _lib.MD_ERR_ARG),
     (dict(shift_mode=2), _lib.MD_ERR_ARG),
     (dict(flags=2), _lib.MD_ERR_ARG),
+    (dict(waves_per_cell=3), _lib.MD_ERR_ARG),
+    (dict(waves_per_cell=-1), _lib.MD_ERR_ARG),
+    (dict(waves_per_cell=8), _lib.MD_ERR_ARG),
     (dict(rc_over_sigma=float("nan")), _lib.MD_ERR_ARG),
 ])
 def test_invalid_params_rejected_on_host(kw, code):

@@ -228,7 +228,9 @@ def _run_modes(pos4, vel4, box, n, cell_min, nsteps, every, modes, dt=0.005):
 
     out = {}
     for mode in modes:
-        s = LJSystem(n, box, dt=dt, cell_min=cell_min, pair_lists=(mode == "list"))
+        # the pair-list passes take one wavefront per cell; so does the
+        # screening run they are compared with
+        s = LJSystem(n, box, dt=dt, cell_min=cell_min, pair_lists=(mode == "list"), waves_per_cell=1)
         s.load(_dev(pos4), None if vel4 is None else _dev(vel4))
         run = {"every": s.step_every, "list": s.step_list}[mode]
         th = run(nsteps, every, thermo_every=1)

@@ -485,6 +485,106 @@ def test_full_size_sampled_rows(name, rows, orc):
         assert abs(e[2] - g["W"]) <= ENERGY_TOL * abs(g["W"])
 
 
+WAVE_CASES = ["lj4k_jitter_shuffled", "lj256_two_cells", "lj32k_jitter", "fcc_rho1.2_jitter", "sparse_gas_rho0.05",
+              "fluid_rho0.4_ragged", "dense_clump"]
+
+
+@pytest.mark.parametrize("waves", [2, 4])
+@pytest.mark.parametrize("case", WAVE_CASES)
+def test_waves_per_cell_match_oracle(case, waves, orc):
+    """Two or four wavefronts per home cell split each pass's candidates
+    (matrix-core blocks or VALU groups, at multiples of the screen's step) and
+    add their partials in wavefront order: forces and energies against the
+    oracle at the same bar as one wavefront; the cases span the matrix-core
+    and VALU screens, face and interior cells, several passes (dense_clump)
+    and ranges that leave a wavefront no candidates (sparse gas)."""
+    pos4, box = CASES[case]()
+    _say(f"waves {waves} {case} n={len(pos4)}")
+    vel4 = np.zeros_like(pos4)
+    vel4[:, :3] = np.random.default_rng(5).normal(size=(len(pos4), 3))
+    _, f, e = gpu_forces(pos4, box, vel4, waves_per_cell=waves)
+    _, f1, e1 = gpu_forces(pos4, box, vel4, waves_per_cell=1)
+    p = orc.params(box)
+    fo, U, W = orc.forces(p, pos4)
+    K = orc.kinetic(p, vel4)
+    assert rel_l2(f, fo) <= FORCE_TOL
+    assert abs(e[0] - U) <= ENERGY_TOL * abs(U)
+    assert abs(e[1] - K) <= ENERGY_TOL * abs(K)
+    assert abs(e[2] - W) <= ENERGY_TOL * abs(W)
+    # the same pairs as one wavefront: only the order of the FP32 sums differs
+    assert rel_l2(f, f1) <= 1e-6
+    assert e[1] == e1[1]
+
+
+@pytest.mark.parametrize("waves", [2, 4])
+def test_waves_per_cell_steps(waves, orc):
+    """md_step with several wavefronts per cell: one step against the oracle's
+    step, a 20-step run bitwise repeatable, and the no-rebuild and batched
+    paths (which share the force pass) on the same state."""
+    w = ljsynth.WORKLOADS["lj4k"]
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05, shuffle=True)
+    _say(f"waves {waves} steps lj4k")
+    s = _system(w.n, box, dt=w.dt, waves_per_cell=waves)
+    s.load(_dev(pos4), _dev(vel4))
+    s.step(1)
+    pos, vel = s.state()
+    assert s.check() == 0
+    x, v, _ = orc.run(orc.params(box, dt=w.dt), pos4, vel4, 1)
+    d = pos.cpu().numpy()[:, :3] - x
+    d -= box * np.round(d / box)
+    assert np.abs(d).max() < 2e-5
+    assert rel_l2(vel.cpu().numpy()[:, :3], v) < 1e-5
+    outs = []
+    for _ in range(2):
+        s = _system(w.n, box, dt=w.dt, waves_per_cell=waves)
+        s.load(_dev(pos4), _dev(vel4))
+        th = s.step(20, thermo_every=10)
+        pos, vel = s.state()
+        assert s.check() == 0
+        outs.append([t.cpu().numpy() for t in (pos, vel, th)])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    # the 20-step energies of one wavefront, to FP32 round-off of the trajectory
+    s1 = _system(w.n, box, dt=w.dt, waves_per_cell=1)
+    s1.load(_dev(pos4), _dev(vel4))
+    th1 = s1.step(20, thermo_every=10).cpu().numpy()
+    e_w = outs[0][2][:, 0] + outs[0][2][:, 1]
+    e_1 = th1[:, 0] + th1[:, 1]
+    assert np.abs(e_w - e_1).max() / abs(e_1[0]) < 1e-5
+    # steps between rebuilds (md_step_every, skin 0.86) take the same force pass
+    se = _system(w.n, box, dt=w.dt, cell_min=2.9, waves_per_cell=waves)
+    se.load(_dev(pos4), _dev(vel4))
+    te = se.step_every(20, 5, thermo_every=10).cpu().numpy()
+    assert se.check() == 0
+    _, _, tho = orc.run(orc.params(box, dt=w.dt), pos4, vel4, 20)
+    eo = tho[:, 0] + tho[:, 1]
+    assert np.abs(te[:, 0] + te[:, 1] - eo[[10, 20]]).max() / abs(eo[0]) < 1e-5
+
+
+def test_waves_per_cell_batched(orc):
+    """A batch of replicas with four wavefronts per cell: each replica's
+    forces against the oracle."""
+    from paper_0709_3225_amd.batch import BatchedLJ
+
+    torch = _torch()
+    w = ljsynth.WORKLOADS["lj4k"]
+    states = [ljsynth.make_state(w, jitter_amp=0.05), ljsynth.make_state(ljsynth.WORKLOADS["lj256_check"],
+                                                                        jitter_amp=0.05)]
+    _say("waves 4 batched lj4k + lj256")
+    b = BatchedLJ([(len(p), box) for p, _, box in states], waves_per_cell=4)
+    pos = torch.cat([_dev(p) for p, _, _ in states])
+    vel = torch.cat([_dev(v) for _, v, _ in states])
+    b.load(pos, vel)
+    out = torch.empty((len(pos), 4), dtype=torch.float32, device="cuda")
+    f = b.forces(out).cpu().numpy()[:, :3].astype(np.float64)
+    b.check()
+    off = 0
+    for p4, _, box in states:
+        fo, _, _ = orc.forces(orc.params(box), p4)
+        assert rel_l2(f[off:off + len(p4)], fo) <= FORCE_TOL
+        off += len(p4)
+
+
 def test_edge_small_systems(orc):
     _say("edge: one atom, two atoms across the boundary")
     s, f, e = gpu_forces(np.array([[1.0, 2.0, 3.0, 0.0]], np.float32), 6.0)
