@@ -24,8 +24,15 @@ if ROOT not in sys.path:
 
 METRIC = "atom-steps/s LJ cell-list FP32 + % FP32 peak; batched & adjoint vs plain"
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X: 256 CUs x 2.4 GHz x 256 FP32 flop/clk
+FP32_MATRIX_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix-core peak
 FLOP_PER_CANDIDATE = 8           # displacement (3) + r^2 (5)
 FLOP_PER_ACCEPTED = 17           # rsqrt, powers, shifted magnitude, 3 accumulating FMAs
+# Hessian-vector product pass of the adjoint, per accepted pair: powers and
+# phi/r (12), phi' and B = (phi' - g)/r^2 (6), dphi/dsigma / r (7), w_i - w_j (3),
+# d.(w_i - w_j) (5), B times it (1), J accumulation (12), force for d/d eps (6),
+# d.w_i and the sigma term (7)
+FLOP_PER_ACCEPTED_HVP = 59
+MFMA_MIN_HOME, MFMA_MAX_HOME = 11, 16  # home-atom chunks screened on the matrix cores
 
 
 def parse():
@@ -143,6 +150,7 @@ def adjoint_leg(torch):
     s.check()
     adj = w.n * w.steps / t_adj
     plain = w.n * w.steps / t_plain
+    hvp = hvp_roofline(s, torch)
     # the same gradient at the headline size (N = 256,000), where the grid
     # fills the chip: context for how the ratio depends on the size
     wl = ljsynth.WORKLOADS["lj256k"]
@@ -160,7 +168,47 @@ def adjoint_leg(torch):
         "value": adj, "unit": "atom-steps/s (forward + backward)", "plain_value": plain,
         "ratio_vs_plain": adj / plain, "loss": loss, "dL_deps": ge, "dL_dsigma": gs,
         "value_at_256k": adj_l,
+        "hvp_roofline": hvp,
+        "hvp_roofline_at_256k": hvp_roofline(_loaded(torch, wl), torch),
     }
+
+
+def _loaded(torch, w):
+    import ljsynth
+    from paper_0709_3225_amd import LJSystem
+
+    pos4, vel4, box = ljsynth.make_state(w)
+    s = LJSystem(w.n, box, dt=w.dt)
+    s.load(torch.from_numpy(pos4).cuda(), torch.from_numpy(vel4).cuda())
+    s.step(20)
+    return s
+
+
+def hvp_roofline(s, torch, reps=100):
+    """The Hessian-vector product pass of the adjoint (k_pair_pass<OP_ADJ>,
+    one md_adjoint_kick: the pair pass plus a gather of the vector into cell
+    order) on the system's current cells: HIP events over reps calls on the
+    launch stream, algorithmic flops split as for the force kernel (59 per
+    accepted pair)."""
+    from paper_0709_3225_amd import _lib as L
+
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    w4 = torch.randn((s.n, 4), generator=g, device="cuda", dtype=torch.float32)
+    lam = torch.zeros((s.n, 4), device="cuda", dtype=torch.float32)
+    stream = torch.cuda.current_stream()
+    L.md_adjoint_kick(s.params, s.ws, w4, lam, None, 1.0)  # warm
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        L.md_adjoint_kick(s.params, s.ws, w4, lam, None, 1.0)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    s.check()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    return {"kernel": "k_pair_pass<OP_ADJ> (md_adjoint_kick: pair pass + gather of n float4)", "n": s.n,
+            **alu_roofline(pair_counts(s, torch), FLOP_PER_ACCEPTED_HVP, us)}
 
 
 def _timed_steps(s, nsteps, torch, every=0):
@@ -328,9 +376,11 @@ def pair_list_leg(torch, nsteps=100, warm=20):
             "value": best["value"] if best else None}
 
 
-def algorithmic_force_flops(sys_, torch):
-    """8 flops per candidate pair the 27-cell method tests plus 17 more per
-    accepted ordered pair, counted on the current state."""
+def pair_counts(sys_, torch):
+    """Candidate pairs the 27-cell method tests on the current state, split
+    into those screened on the VALU and those screened on the matrix cores
+    (home-atom chunks of 11..16 atoms: a cell's atoms in chunks of 64, each
+    chunk against the whole neighbourhood), and the accepted ordered pairs."""
     import numpy as np
 
     start, _ = sys_.cell_lists()
@@ -343,10 +393,43 @@ def algorithmic_force_flops(sys_, torch):
             for dx in (-1, 0, 1):
                 hood += np.roll(grid, shift=(dz, dy, dx), axis=(0, 1, 2))
     candidates = int((grid * hood).sum())
+    last = grid % 64  # the last chunk; full chunks of 64 take the VALU screen
+    mfma_home = np.where((last >= MFMA_MIN_HOME) & (last <= MFMA_MAX_HOME), last, 0)
+    mfma = int((mfma_home * hood).sum())
     counts, _ = sys_.neighbors(max_per_atom=1)  # counts only; rows truncate (flag cleared below)
     accepted = int(counts.sum().item())
     sys_.check(raise_on_error=False)
-    return candidates, accepted, FLOP_PER_CANDIDATE * candidates + FLOP_PER_ACCEPTED * accepted
+    return {"candidates": candidates, "valu_candidates": candidates - mfma, "mfma_candidates": mfma,
+            "accepted_pairs": accepted}
+
+
+def alu_roofline(pc, per_accepted, kernel_us):
+    """Algorithmic flops of one cell-pair launch split by the unit that runs
+    them: the VALU takes the screen of VALU-screened candidates (8 each) and
+    every accepted pair's interaction; the matrix cores take the screen of the
+    other candidates (8 each, as dot products). Each part over the launch's
+    duration against its own FP32 peak."""
+    t = kernel_us * 1e-6
+    vec = FLOP_PER_CANDIDATE * pc["valu_candidates"] + per_accepted * pc["accepted_pairs"]
+    mat = FLOP_PER_CANDIDATE * pc["mfma_candidates"]
+    vec_tf = vec / t / 1e12
+    mat_tf = mat / t / 1e12
+    return {
+        "bound": "alu",
+        "achieved": vec_tf,
+        "peak": FP32_VECTOR_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": vec_tf / FP32_VECTOR_PEAK_TFLOPS,
+        "kernel_us": kernel_us,
+        "vector_flops_per_launch": vec,
+        "matrix": {"achieved": mat_tf, "peak": FP32_MATRIX_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": mat_tf / FP32_MATRIX_PEAK_TFLOPS, "flops_per_launch": mat},
+        "all_flops_tflops": (vec + mat) / t / 1e12,
+        **pc,
+        # the interaction-only count: the candidate test and interaction of the
+        # accepted pairs alone, the floor of any exact method, over the same time
+        "interaction_only_tflops": (FLOP_PER_CANDIDATE + per_accepted) * pc["accepted_pairs"] / t / 1e12,
+    }
 
 
 FORCE_SOURCES = ("paper_0709_3225_amd/csrc/forces.hip", "paper_0709_3225_amd/csrc/cell_pairs.h",
@@ -476,13 +559,34 @@ def main():
         s.step(args.warmup)
     s.check()
 
-    # ---- timed region: K whole steps
     stream = torch.cuda.current_stream()
+
+    # ---- force kernel alone (md_forces without output = one kernel launch) on
+    # the state the timed region starts from; recomputing its forces leaves
+    # the state bitwise as it was
+    from paper_0709_3225_amd import md_forces
+
+    reps = args.force_reps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.forces()  # warm
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        md_forces(s.params, s.ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    force_us = e0.elapsed_time(e1) * 1e3 / reps
+    s.check()
+    roof = alu_roofline(pair_counts(s, torch), FLOP_PER_ACCEPTED, force_us)
+
+    # ---- timed region: K whole steps, at least one of them with the FP64
+    # energy/virial/kinetic reduction
+    thermo_every = min(args.thermo_every, args.steps) if args.thermo_every > 0 else 0
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
-    thermo = s.step(args.steps, thermo_every=args.thermo_every)
+    thermo = s.step(args.steps, thermo_every=thermo_every)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -490,23 +594,6 @@ def main():
     s.check()
     elapsed = max(wall, gpu_s)
     value = w.n * args.steps / elapsed
-
-    # ---- force kernel alone (md_forces without output = one kernel launch)
-    reps = args.force_reps
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    s.forces()  # warm
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(reps):
-        from paper_0709_3225_amd import md_forces
-
-        md_forces(s.params, s.ws)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    force_us = e0.elapsed_time(e1) * 1e3 / reps
-    s.check()
-    candidates, accepted, flops = algorithmic_force_flops(s, torch)
-    achieved_tflops = flops / (force_us * 1e-6) / 1e12
 
     e_th = None
     if thermo is not None:
@@ -530,30 +617,21 @@ def main():
         "config": {
             "workload": f"{w.name}: LJ fluid N={w.n} ({w.n_fcc}^3 FCC start), rho={w.density}, T*={w.temperature}, "
                         f"rc=2.5 sigma force-shifted, dt={w.dt}, NVE, cell list rebuilt every step, "
-                        f"FP64 U/K/W every {args.thermo_every} steps",
+                        f"FP64 U/K/W every {thermo_every} steps",
             "n": w.n,
             "box": box,
             "cells_per_dim": s.cells_per_dim,
-            "thermo_every": args.thermo_every,
+            "thermo_every": thermo_every,
         },
         "roofline": {
-            "kernel": "k_forces<false,false,true> (md_forces)",
-            "bound": "alu",
-            "achieved": achieved_tflops,
-            "peak": FP32_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS,
+            "kernel": "k_forces<false,false,true,false,1> (md_forces)",
+            "state": f"after the {args.warmup} warm-up steps",
+            **roof,
             "traffic": recorded_traffic(args.workload),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "kernel_us": force_us,
-            "flops_per_launch": flops,
-            "candidates": candidates,
-            "accepted_pairs": accepted,
-            # the interaction-only count: 25 flop per accepted ordered pair,
-            # the floor of any exact method, over the same kernel time
-            "interaction_only_tflops": (FLOP_PER_CANDIDATE + FLOP_PER_ACCEPTED) * accepted / (force_us * 1e-6) / 1e12,
         },
         "thermo_last": e_th,
+        "timed_region": {"hip_events_ms": gpu_s * 1e3, "wall_ms": wall * 1e3},
     }
     if args.copy_calibration_mib > 0:
         # one plain copy of known size: FETCH_SIZE/WRITE_SIZE of this dispatch give the
