@@ -23,31 +23,50 @@ namespace {
 
 enum { OP_ADJ = 0, OP_VGRAD = 1 };
 
-// One pair of the Hessian-vector product, plus the force (for d/d eps) and the
-// sigma derivative projected on w_i.
+// Pair constants of the passes below. With ir2 = 1/r^2, ir6 = ir2^3,
+// ir8 = ir2 ir6, c12 = 48 eps sigma^12 and c6 = 24 eps sigma^6 (so that
+// f_LJ(r)/r = ir8 (c12 ir6 - c6)) and fc = f_LJ(r_c):
+//   g = phi / r                    = ir8 (c12 ir6 - c6) - fc / r
+//   B = (phi' - g) / r^2           = ir2 [ir8 (8 c6 - 14 c12 ir6) + fc / r]
+//   phi / r + phi'                 = ir8 (6 c6 - 12 c12 ir6) - fc / r
+//   sigma (d phi / d sigma) / r    = ir8 (12 c12 ir6 - 6 c6) + fc / r
+// (phi' = ir8 (7 c6 - 13 c12 ir6); the sigma derivative is taken at fixed
+// r_c / sigma, so the shift contributes fc / r). Sums of the last line are
+// divided by sigma once per atom.
+struct PairConsts {
+    float rc2, fc, c12, c6;
+    float b12, b6;  // -14 c12, 8 c6
+    float v12, v6;  // -12 c12, 6 c6
+    float s12, s6;  // 12 c12, -6 c6
+};
+
+__device__ __forceinline__ PairConsts pair_consts(const SimArgs& a) {
+    return PairConsts{a.rc2,          a.fc,          a.c12,         a.c6,          -14.0f * a.c12,
+                      8.0f * a.c6,    -12.0f * a.c12, 6.0f * a.c6,  12.0f * a.c12, -6.0f * a.c6};
+}
+
+// One pair of the Hessian-vector product, plus the force (for d/d eps) and
+// sigma times the sigma derivative projected on w_i.
 struct AdjOp {
-    const SimArgs& a;
+    const PairConsts& k;
     const char* base;   // position tile at the lane's span start
     const char* wbase;  // adjoint-vector tile at the lane's span start
     float xi, yi, zi, wx, wy, wz;
     float jx = 0.f, jy = 0.f, jz = 0.f, fx = 0.f, fy = 0.f, fz = 0.f, sg = 0.f;
-    float inv_sig;
     __device__ __forceinline__ void operator()(uint32_t off, bool live) {
         const float4 q = *reinterpret_cast<const float4*>(base + off);
         const float4 wj = *reinterpret_cast<const float4*>(wbase + off);
         const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const bool ok = live && (r2 < a.rc2);
+        const bool ok = live && (r2 < k.rc2);
         const float rinv = __builtin_amdgcn_rsqf(r2);
         const float ir2 = rinv * rinv;
-        const float s2 = a.sig2 * ir2;
-        const float s6 = s2 * s2 * s2;
-        const float s12 = s6 * s6;
-        const float e_ir2 = a.eps24 * ir2;
-        float g = fmaf(e_ir2, fmaf(2.0f, s12, -s6), -a.fc * rinv);            // phi / r
-        const float phip = e_ir2 * fmaf(7.0f, s6, -26.0f * s12);                 // phi'
-        float bb = (phip - g) * ir2;                                             // (phi' - g) / r^2
-        float dps = fmaf(e_ir2 * inv_sig, fmaf(24.0f, s12, -6.0f * s6), a.fc * inv_sig * rinv);  // (dphi/dsigma)/r
+        const float ir6 = ir2 * ir2 * ir2;
+        const float ir8 = ir2 * ir6;
+        const float fcr = k.fc * rinv;
+        float g = fmaf(ir8, fmaf(k.c12, ir6, -k.c6), -fcr);         // phi / r
+        float bb = ir2 * fmaf(ir8, fmaf(k.b12, ir6, k.b6), fcr);    // (phi' - g) / r^2
+        float dps = fmaf(ir8, fmaf(k.s12, ir6, k.s6), fcr);          // sigma (dphi/dsigma) / r
         g = ok ? g : 0.f;
         bb = ok ? bb : 0.f;
         dps = ok ? dps : 0.f;
@@ -65,36 +84,41 @@ struct AdjOp {
 };
 
 // One pair of the virial gradient: grad_i W = sum_j (phi + r phi') d / r,
-// plus W and r dphi/dsigma for the parameter derivatives.
+// plus W and sigma r dphi/dsigma for the parameter derivatives.
 struct VGradOp {
-    const SimArgs& a;
+    const PairConsts& k;
     const char* base;
     float xi, yi, zi;
     float gx = 0.f, gy = 0.f, gz = 0.f, wsum = 0.f, wsig = 0.f;
-    float inv_sig;
     __device__ __forceinline__ void operator()(uint32_t off, bool live) {
         const float4 q = *reinterpret_cast<const float4*>(base + off);
         const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const bool ok = live && (r2 < a.rc2);
+        const bool ok = live && (r2 < k.rc2);
         const float rinv = __builtin_amdgcn_rsqf(r2);
         const float ir2 = rinv * rinv;
-        const float s2 = a.sig2 * ir2;
-        const float s6 = s2 * s2 * s2;
-        const float s12 = s6 * s6;
-        const float e_ir2 = a.eps24 * ir2;
-        const float g = fmaf(e_ir2, fmaf(2.0f, s12, -s6), -a.fc * rinv);  // phi / r
-        const float phip = e_ir2 * fmaf(7.0f, s6, -26.0f * s12);
-        const float dps = fmaf(e_ir2 * inv_sig, fmaf(24.0f, s12, -6.0f * s6), a.fc * inv_sig * rinv);
-        const float sc = ok ? g + phip : 0.f;  // (phi + r phi') / r
-        gx = fmaf(sc, dx, gx);
-        gy = fmaf(sc, dy, gy);
-        gz = fmaf(sc, dz, gz);
+        const float ir6 = ir2 * ir2 * ir2;
+        const float ir8 = ir2 * ir6;
+        const float fcr = k.fc * rinv;
+        const float g = fmaf(ir8, fmaf(k.c12, ir6, -k.c6), -fcr);    // phi / r
+        const float sc = fmaf(ir8, fmaf(k.v12, ir6, k.v6), -fcr);    // phi / r + phi'
+        const float dps = fmaf(ir8, fmaf(k.s12, ir6, k.s6), fcr);    // sigma (dphi/dsigma) / r
+        const float scm = ok ? sc : 0.f;
+        gx = fmaf(scm, dx, gx);
+        gy = fmaf(scm, dy, gy);
+        gz = fmaf(scm, dz, gz);
         wsum += ok ? g * r2 : 0.f;     // r phi
-        wsig += ok ? dps * r2 : 0.f;   // r dphi/dsigma
+        wsig += ok ? dps * r2 : 0.f;   // sigma r dphi/dsigma
     }
 };
 
+// One pass over the pairs of every home cell: the Hessian-vector product
+// (ADJ) or the virial gradient (VGRAD). Staging as in the force kernel: a
+// neighbourhood that fits one tile is staged in one pass from the row table
+// (cells away from the x faces) or the row-piece table (cells on an x face),
+// with the adjoint vector (ADJ) in a second tile at the same indices; other
+// cells take the LDS segment table and stage in the pass loop. The slice
+// reduction reuses the position tile.
 template <int OP>
 __global__ void __launch_bounds__(kWave)
     k_pair_pass(SimArgs a, const float4* __restrict__ wvec, float4* __restrict__ out_r, float4* __restrict__ out_v,
@@ -104,17 +128,49 @@ __global__ void __launch_bounds__(kWave)
         return;
     }
     constexpr bool ADJ = (OP == OP_ADJ);
+    constexpr int NRED = ADJ ? 7 : 5;  // partials per lane
     extern __shared__ float4 tile[];  // positions, then (ADJ) the adjoint vector: 2 x (tile_cap + kTilePad)
     __shared__ Neighbourhood nb;
-    __shared__ float red[7 * kWave];
     float4* wtile = tile + (a.tile_cap + kTilePad);
-    const int lane = threadIdx.x;
+    float* red = reinterpret_cast<float*>(tile);  // NRED x 64 floats, after the walk
+    const int lane = __lane_id();
     const int c = xcd_block_order(blockIdx.x, a.ncells);
+    const PairConsts kc = pair_consts(a);
     float ox, oy, oz;
-    load_neighbourhood(a, c, nb, ox, oy, oz);
-    const int total = nb.total;
-    const int home_first = nb.home_first;
-    const int n_home = nb.n_home;
+    RowHood rh;
+    const bool interior = row_hood(a, c, rh);  // uniform
+    bool rows = interior && rh.pos[9] <= a.tile_cap && rh.n_home <= kWave;
+    int total, home_first, n_home, home_pos;
+    if (rows) {
+        ox = rh.ox;
+        oy = rh.oy;
+        oz = rh.oz;
+        total = rh.pos[9];
+        home_first = rh.home_first;
+        n_home = rh.n_home;
+        home_pos = rh.home_pos;
+        stage_rows<ADJ ? SECOND_VEC : SECOND_NONE>(a, rh, tile, wtile, wvec);
+    }
+    RowPieces rp;
+    if (!interior) row_pieces(a, c, rp);
+    if (!interior && rp.total <= a.tile_cap && rp.n_home <= kWave) {
+        rows = true;
+        ox = rp.ox;
+        oy = rp.oy;
+        oz = rp.oz;
+        total = rp.total;
+        home_first = rp.home_first;
+        n_home = rp.n_home;
+        home_pos = rp.home_pos;
+        stage_pieces<ADJ ? SECOND_VEC : SECOND_NONE>(a, rp, tile, wtile, wvec);
+    }
+    if (!rows) {
+        load_neighbourhood(a, c, nb, ox, oy, oz);
+        total = nb.total;
+        home_first = nb.home_first;
+        n_home = nb.n_home;
+        home_pos = nb.home_pos;
+    }
     const float inv_sig = 1.0f / sqrtf(a.sig2);
     const float inv_eps = 24.0f / a.eps24;
 
@@ -142,14 +198,16 @@ __global__ void __launch_bounds__(kWave)
         float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f, v4 = 0.f, v5 = 0.f, v6 = 0.f;
         for (int t0 = 0; t0 < total; t0 += a.tile_cap) {
             const int tn = min(a.tile_cap, total - t0);
-            __syncthreads();
-            stage_tile<false, ADJ>(a, nb, tile, t0, tn, wvec, wtile);
+            if (!rows) {
+                __syncthreads();
+                stage_tile<false, ADJ>(a, nb, tile, t0, tn, wvec, wtile);
+            }
             for (int t = lane; t < kTilePad; t += kWave) {
                 tile[tn + t] = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
                 if (ADJ) wtile[tn + t] = make_float4(0.f, 0.f, 0.f, 0.f);
             }
             __syncthreads();
-            const int self_t = nb.home_pos + h0 + h - t0;
+            const int self_t = home_pos + h0 + h - t0;
             // spans: 128 candidates per lane (32 blocks of 16 with the matrix cores)
             const int groups_all = mf ? 4 * ((tn + 15) / 16) : (tn + ns - 1) / ns;
             for (int g0 = 0; g0 < groups_all; g0 += kGroups) {
@@ -169,22 +227,22 @@ __global__ void __launch_bounds__(kWave)
                 }
                 if (act) clear_self(self_t, first, ns, groups, wd);
                 if (ADJ) {
-                    AdjOp op{a, reinterpret_cast<const char*>(tile + first), reinterpret_cast<const char*>(wtile + first),
+                    AdjOp op{kc, reinterpret_cast<const char*>(tile + first), reinterpret_cast<const char*>(wtile + first),
                              xi, yi, zi, wi.x, wi.y, wi.z};
-                    op.inv_sig = inv_sig;
                     op.jx = v0; op.jy = v1; op.jz = v2; op.fx = v3; op.fy = v4; op.fz = v5; op.sg = v6;
                     walk_bits(ns, wd[0], wd[1], wd[2], wd[3], op);
                     v0 = op.jx; v1 = op.jy; v2 = op.jz; v3 = op.fx; v4 = op.fy; v5 = op.fz; v6 = op.sg;
                 } else {
-                    VGradOp op{a, reinterpret_cast<const char*>(tile + first), xi, yi, zi};
-                    op.inv_sig = inv_sig;
+                    VGradOp op{kc, reinterpret_cast<const char*>(tile + first), xi, yi, zi};
                     op.gx = v0; op.gy = v1; op.gz = v2; op.wsum = v3; op.wsig = v4;
                     walk_bits(ns, wd[0], wd[1], wd[2], wd[3], op);
                     v0 = op.gx; v1 = op.gy; v2 = op.gz; v3 = op.wsum; v4 = op.wsig;
                 }
             }
         }
-        // slice partials of each home atom, summed in slice order
+        // slice partials of each home atom, summed in slice order (red aliases
+        // the position tile: every lane has finished its walk at this barrier;
+        // a cell of several home chunks restages in the next chunk's pass)
         __syncthreads();
         red[0 * kWave + lane] = v0;
         red[1 * kWave + lane] = v1;
@@ -201,8 +259,7 @@ __global__ void __launch_bounds__(kWave)
             for (int q = 0; q < ns; ++q) {
                 const int l = h + q * hstride;
 #pragma unroll
-                for (int k = 0; k < 7; ++k)
-                    if (ADJ || k < 5) r[k] += red[k * kWave + l];
+                for (int k = 0; k < NRED; ++k) r[k] += red[k * kWave + l];
             }
             const int slot = home_first + h0 + h;
             const int id = __float_as_int(pi.w);
@@ -217,7 +274,7 @@ __global__ void __launch_bounds__(kWave)
                 acc0 += static_cast<double>(inv_eps) *
                         (static_cast<double>(wi.x) * r[3] + static_cast<double>(wi.y) * r[4] +
                          static_cast<double>(wi.z) * r[5]);
-                acc1 += static_cast<double>(r[6]);
+                acc1 += static_cast<double>(inv_sig) * static_cast<double>(r[6]);
             } else {
                 out_r[id] = make_float4(coef * r[0], coef * r[1], coef * r[2], 0.f);
                 const float4 v = a.vel0[slot];
@@ -225,7 +282,7 @@ __global__ void __launch_bounds__(kWave)
                 out_v[id] = make_float4(km * v.x, km * v.y, km * v.z, 0.f);
                 // W = 1/2 sum over ordered pairs of r phi, dW/d eps = W / eps
                 acc0 += 0.5 * static_cast<double>(inv_eps) * static_cast<double>(r[3]);
-                acc1 += 0.5 * static_cast<double>(r[4]);
+                acc1 += 0.5 * static_cast<double>(inv_sig) * static_cast<double>(r[4]);
             }
         }
     }

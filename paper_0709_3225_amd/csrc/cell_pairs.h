@@ -384,20 +384,26 @@ __device__ __forceinline__ bool row_hood(const SimArgs& a, int c, RowHood& r) {
     return true;
 }
 
+// Second tile of the staging functions below (SECOND): none; the untranslated
+// positions (w = user index); or the entries of vsrc, a per-atom vector in
+// sorted order. Either goes to raw at the same indices as the positions.
+enum { SECOND_NONE = 0, SECOND_RAW = 1, SECOND_VEC = 2 };
+
 // Staging of a RowHood neighbourhood in one pass (total <= tile capacity), by
 // the same unmasked scheme as stage_whole (rows tile [0, total) in order).
-// RAW: the untranslated positions (w = user index) go to raw at the same
-// indices.
-template <bool RAW = false>
-__device__ __forceinline__ void stage_rows(const SimArgs& a, const RowHood& r, float4* tile, float4* raw = nullptr) {
+template <int SECOND = SECOND_NONE>
+__device__ __forceinline__ void stage_rows(const SimArgs& a, const RowHood& r, float4* tile, float4* raw = nullptr,
+                                           const float4* vsrc = nullptr) {
     const int lane = __lane_id();
     const int last = a.natoms - 1;
     const char* pbase = reinterpret_cast<const char*>(a.pos0);
-    float4 q[9];
+    const char* vbase = reinterpret_cast<const char*>(vsrc);
+    float4 q[9], v[SECOND == SECOND_VEC ? 9 : 1];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const uint32_t off = static_cast<uint32_t>(min(r.first[k] + lane, last)) << 4;
         q[k] = *reinterpret_cast<const float4*>(pbase + off);
+        if (SECOND == SECOND_VEC) v[k] = *reinterpret_cast<const float4*>(vbase + off);
     }
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -405,7 +411,8 @@ __device__ __forceinline__ void stage_rows(const SimArgs& a, const RowHood& r, f
         const float y = q[k].y - r.fy[k % 3];
         const float z = q[k].z - r.fz[k / 3];
         tile[r.pos[k] + lane] = make_float4(x, y, z, x * x + y * y + z * z);
-        if (RAW) raw[r.pos[k] + lane] = q[k];
+        if (SECOND == SECOND_RAW) raw[r.pos[k] + lane] = q[k];
+        if (SECOND == SECOND_VEC) raw[r.pos[k] + lane] = v[k];
         __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
@@ -414,10 +421,11 @@ __device__ __forceinline__ void stage_rows(const SimArgs& a, const RowHood& r, f
         if (len > kWave) {  // uniform; rare
             for (int off = kWave + lane; off - lane < len; off += kWave) {
                 if (off < len) {
-                    const float4 v = a.pos0[r.first[k] + off];
-                    const float x = v.x - r.ox, y = v.y - r.fy[k % 3], z = v.z - r.fz[k / 3];
+                    const float4 u = a.pos0[r.first[k] + off];
+                    const float x = u.x - r.ox, y = u.y - r.fy[k % 3], z = u.z - r.fz[k / 3];
                     tile[r.pos[k] + off] = make_float4(x, y, z, x * x + y * y + z * z);
-                    if (RAW) raw[r.pos[k] + off] = v;
+                    if (SECOND == SECOND_RAW) raw[r.pos[k] + off] = u;
+                    if (SECOND == SECOND_VEC) raw[r.pos[k] + off] = vsrc[r.first[k] + off];
                 }
             }
         }
@@ -700,19 +708,21 @@ __device__ __forceinline__ void row_pieces(const SimArgs& a, int c, RowPieces& r
 // unmasked scheme of stage_whole: every lane loads and stores entry
 // pos + lane of each piece; pieces are written in order, so a piece's surplus
 // entries are overwritten by a later piece or fall into the padding after the
-// total. Atoms 64 and up of a longer piece follow, masked. RAW: the
-// untranslated positions (w = user index) go to raw at the same indices.
-template <int K0, bool RAW>
+// total. Atoms 64 and up of a longer piece follow, masked. SECOND as for
+// stage_rows.
+template <int K0, int SECOND>
 __device__ __forceinline__ void stage_nine(const SimArgs& a, const RowPieces& r, float fx, float4* tile,
-                                           float4* raw) {
+                                           float4* raw, const float4* vsrc) {
     const int lane = __lane_id();
     const int last = a.natoms - 1;
     const char* pbase = reinterpret_cast<const char*>(a.pos0);
-    float4 q[9];
+    const char* vbase = reinterpret_cast<const char*>(vsrc);
+    float4 q[9], v[SECOND == SECOND_VEC ? 9 : 1];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const uint32_t off = static_cast<uint32_t>(min(__builtin_amdgcn_readlane(r.first, K0 + k) + lane, last)) << 4;
         q[k] = *reinterpret_cast<const float4*>(pbase + off);
+        if (SECOND == SECOND_VEC) v[k] = *reinterpret_cast<const float4*>(vbase + off);
     }
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -721,7 +731,8 @@ __device__ __forceinline__ void stage_nine(const SimArgs& a, const RowPieces& r,
         const float z = q[k].z - r.fz[k / 3];
         const int p = __builtin_amdgcn_readlane(r.pos, K0 + k);
         tile[p + lane] = make_float4(x, y, z, x * x + y * y + z * z);
-        if (RAW) raw[p + lane] = q[k];
+        if (SECOND == SECOND_RAW) raw[p + lane] = q[k];
+        if (SECOND == SECOND_VEC) raw[p + lane] = v[k];
         __builtin_amdgcn_sched_barrier(0);
     }
     if (__any(lane >= K0 && lane < K0 + 9 && r.len > kWave)) {  // rare
@@ -732,10 +743,11 @@ __device__ __forceinline__ void stage_nine(const SimArgs& a, const RowPieces& r,
                 const int f = __builtin_amdgcn_readlane(r.first, K0 + k), p = __builtin_amdgcn_readlane(r.pos, K0 + k);
                 for (int off = kWave + lane; off - lane < len; off += kWave) {
                     if (off < len) {
-                        const float4 v = a.pos0[f + off];
-                        const float x = v.x - fx, y = v.y - r.fy[k % 3], z = v.z - r.fz[k / 3];
+                        const float4 u = a.pos0[f + off];
+                        const float x = u.x - fx, y = u.y - r.fy[k % 3], z = u.z - r.fz[k / 3];
                         tile[p + off] = make_float4(x, y, z, x * x + y * y + z * z);
-                        if (RAW) raw[p + off] = v;
+                        if (SECOND == SECOND_RAW) raw[p + off] = u;
+                        if (SECOND == SECOND_VEC) raw[p + off] = vsrc[f + off];
                     }
                 }
             }
@@ -745,10 +757,11 @@ __device__ __forceinline__ void stage_nine(const SimArgs& a, const RowPieces& r,
 
 // The whole neighbourhood of r in one pass (total <= tile capacity; the tile
 // needs room for total + 63 entries).
-template <bool RAW>
-__device__ __forceinline__ void stage_pieces(const SimArgs& a, const RowPieces& r, float4* tile, float4* raw) {
-    stage_nine<0, RAW>(a, r, r.ox, tile, raw);
-    if (r.face) stage_nine<9, RAW>(a, r, r.fxb, tile, raw);
+template <int SECOND = SECOND_NONE>
+__device__ __forceinline__ void stage_pieces(const SimArgs& a, const RowPieces& r, float4* tile, float4* raw = nullptr,
+                                             const float4* vsrc = nullptr) {
+    stage_nine<0, SECOND>(a, r, r.ox, tile, raw, vsrc);
+    if (r.face) stage_nine<9, SECOND>(a, r, r.fxb, tile, raw, vsrc);
 }
 
 }  // namespace

@@ -166,7 +166,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         home_first = rh.home_first;
         n_home = rh.n_home;
         home_pos = rh.home_pos;
-        if (wv == 0) stage_rows<EXPORT>(a, rh, tile, raw);
+        if (wv == 0) stage_rows<EXPORT ? SECOND_RAW : SECOND_NONE>(a, rh, tile, raw);
     }
     // a cell on an x face: the same one-pass staging from a table of row pieces
     RowPieces rp;
@@ -180,7 +180,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         home_first = rp.home_first;
         n_home = rp.n_home;
         home_pos = rp.home_pos;
-        if (wv == 0) stage_pieces<EXPORT>(a, rp, tile, raw);
+        if (wv == 0) stage_pieces<EXPORT ? SECOND_RAW : SECOND_NONE>(a, rp, tile, raw);
     }
     if (!rows) {
         load_neighbourhood(a, c, nb, ox, oy, oz);
