@@ -118,9 +118,12 @@ struct VGradOp {
 // (cells away from the x faces) or the row-piece table (cells on an x face),
 // with the adjoint vector (ADJ) in a second tile at the same indices; other
 // cells take the LDS segment table and stage in the pass loop. The slice
-// reduction reuses the position tile.
-template <int OP>
-__global__ void __launch_bounds__(kWave)
+// reduction reuses the tiles. With nw = blockDim / 64 <= MW wavefronts per
+// cell, wavefront 0 stages, each screens and walks its own contiguous range
+// of every pass's candidates, and wavefront 0 adds the partials (wavefronts
+// in order, then slices) and finishes the atoms.
+template <int OP, int MW>
+__global__ void __launch_bounds__(MW * kWave)
     k_pair_pass(SimArgs a, const float4* __restrict__ wvec, float4* __restrict__ out_r, float4* __restrict__ out_v,
                 float coef, float kcoef, double pcoef, bool accumulate) {
     if (!state_ok(a, false)) {
@@ -132,8 +135,10 @@ __global__ void __launch_bounds__(kWave)
     extern __shared__ float4 tile[];  // positions, then (ADJ) the adjoint vector: 2 x (tile_cap + kTilePad)
     __shared__ Neighbourhood nb;
     float4* wtile = tile + (a.tile_cap + kTilePad);
-    float* red = reinterpret_cast<float*>(tile);  // NRED x 64 floats, after the walk
+    float* red = reinterpret_cast<float*>(tile);  // NRED x 64 floats per wavefront, after the walk
     const int lane = __lane_id();
+    const int wv = MW == 1 ? 0 : static_cast<int>(threadIdx.x) >> 6;  // uniform per wavefront
+    const int nw = MW == 1 ? 1 : static_cast<int>(blockDim.x) >> 6;
     const int c = xcd_block_order(blockIdx.x, a.ncells);
     const PairConsts kc = pair_consts(a);
     float ox, oy, oz;
@@ -149,7 +154,7 @@ __global__ void __launch_bounds__(kWave)
         home_first = rh.home_first;
         n_home = rh.n_home;
         home_pos = rh.home_pos;
-        stage_rows<ADJ ? SECOND_VEC : SECOND_NONE>(a, rh, tile, wtile, wvec);
+        if (wv == 0) stage_rows<ADJ ? SECOND_VEC : SECOND_NONE>(a, rh, tile, wtile, wvec);
     }
     RowPieces rp;
     if (!interior) row_pieces(a, c, rp);
@@ -162,7 +167,7 @@ __global__ void __launch_bounds__(kWave)
         home_first = rp.home_first;
         n_home = rp.n_home;
         home_pos = rp.home_pos;
-        stage_pieces<ADJ ? SECOND_VEC : SECOND_NONE>(a, rp, tile, wtile, wvec);
+        if (wv == 0) stage_pieces<ADJ ? SECOND_VEC : SECOND_NONE>(a, rp, tile, wtile, wvec);
     }
     if (!rows) {
         load_neighbourhood(a, c, nb, ox, oy, oz);
@@ -200,18 +205,25 @@ __global__ void __launch_bounds__(kWave)
             const int tn = min(a.tile_cap, total - t0);
             if (!rows) {
                 __syncthreads();
-                stage_tile<false, ADJ>(a, nb, tile, t0, tn, wvec, wtile);
+                if (wv == 0) stage_tile<false, ADJ>(a, nb, tile, t0, tn, wvec, wtile);
             }
-            for (int t = lane; t < kTilePad; t += kWave) {
-                tile[tn + t] = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
-                if (ADJ) wtile[tn + t] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (wv == 0) {
+                for (int t = lane; t < kTilePad; t += kWave) {
+                    tile[tn + t] = make_float4(0.f, 0.f, 0.f, __builtin_huge_valf());
+                    if (ADJ) wtile[tn + t] = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
             }
             __syncthreads();
             const int self_t = home_pos + h0 + h - t0;
-            // spans: 128 candidates per lane (32 blocks of 16 with the matrix cores)
+            // spans: 128 candidates per lane (32 blocks of 16 with the matrix cores);
+            // this wavefront's groups [g_lo, g_hi), split at multiples of the
+            // screen's step (four blocks, or four VALU groups)
             const int groups_all = mf ? 4 * ((tn + 15) / 16) : (tn + ns - 1) / ns;
-            for (int g0 = 0; g0 < groups_all; g0 += kGroups) {
-                const int groups = min(kGroups, groups_all - g0);
+            const int unit = mf ? 16 : kScreenUnroll;
+            const int nu = (groups_all + unit - 1) / unit;
+            const int g_lo = unit * ((nu * wv) / nw), g_hi = min(groups_all, unit * ((nu * (wv + 1)) / nw));
+            for (int g0 = g_lo; g0 < g_hi; g0 += kGroups) {
+                const int groups = min(kGroups, g_hi - g0);
                 const int first = mf ? 4 * g0 + s : g0 * ns + (act ? s : 0);
                 uint32_t wd[kWords];
                 if (mf) {
@@ -240,26 +252,31 @@ __global__ void __launch_bounds__(kWave)
                 }
             }
         }
-        // slice partials of each home atom, summed in slice order (red aliases
-        // the position tile: every lane has finished its walk at this barrier;
-        // a cell of several home chunks restages in the next chunk's pass)
+        // partials of each home atom, summed over wavefronts in order and
+        // slices in order (red aliases the tiles: every lane has finished its
+        // walk at this barrier; a cell of several home chunks restages in the
+        // next chunk's pass)
         __syncthreads();
-        red[0 * kWave + lane] = v0;
-        red[1 * kWave + lane] = v1;
-        red[2 * kWave + lane] = v2;
-        red[3 * kWave + lane] = v3;
-        red[4 * kWave + lane] = v4;
+        float* mine = red + NRED * kWave * wv;
+        mine[0 * kWave + lane] = v0;
+        mine[1 * kWave + lane] = v1;
+        mine[2 * kWave + lane] = v2;
+        mine[3 * kWave + lane] = v3;
+        mine[4 * kWave + lane] = v4;
         if (ADJ) {
-            red[5 * kWave + lane] = v5;
-            red[6 * kWave + lane] = v6;
+            mine[5 * kWave + lane] = v5;
+            mine[6 * kWave + lane] = v6;
         }
         __syncthreads();
-        if (act && s == 0) {
+        if (act && s == 0 && wv == 0) {
             float r[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-            for (int q = 0; q < ns; ++q) {
-                const int l = h + q * hstride;
+            for (int w = 0; w < nw; ++w) {
+                const float* part = red + NRED * kWave * w;
+                for (int q = 0; q < ns; ++q) {
+                    const int l = h + q * hstride;
 #pragma unroll
-                for (int k = 0; k < NRED; ++k) r[k] += red[k * kWave + l];
+                    for (int k = 0; k < NRED; ++k) r[k] += part[k * kWave + l];
+                }
             }
             const int slot = home_first + h0 + h;
             const int id = __float_as_int(pi.w);
@@ -290,7 +307,7 @@ __global__ void __launch_bounds__(kWave)
     acc1 = wave_sum(acc1);
     // the cell's parameter partials, scaled by pcoef; accumulate adds them to
     // the cell's running sums (the passes of one segment), else replaces them
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
         double* e = a.epart + 3 * static_cast<size_t>(blockIdx.x);
         e[0] = (accumulate ? e[0] : 0.0) + pcoef * acc0;
         e[1] = (accumulate ? e[1] : 0.0) + pcoef * acc1;
@@ -376,14 +393,28 @@ __global__ void __launch_bounds__(256) k_adjoint_drift(int n, float dt, const fl
     lam_v[i] = v;
 }
 
+// One pair pass over all cells with a.waves wavefronts per cell: LDS for the
+// position tile (and the vector tile with ADJ), at least the reduction's
+// partials of every wavefront.
+template <int OP, class... Args>
+void launch_pair(const SimArgs& a, hipStream_t st, Args... args) {
+    constexpr size_t nred = OP == OP_ADJ ? 7 : 5;
+    const size_t tiles = (OP == OP_ADJ ? 2 : 1) * static_cast<size_t>(a.tile_cap + kTilePad);
+    const size_t lds = sizeof(float4) * std::max(tiles, nred * 16 * static_cast<size_t>(a.waves));
+    if (a.waves == 1)
+        hipLaunchKernelGGL((k_pair_pass<OP, 1>), dim3(a.ncells), dim3(kWave), lds, st, a, args...);
+    else
+        hipLaunchKernelGGL((k_pair_pass<OP, kMaxCellWaves>), dim3(a.ncells), dim3(kWave * a.waves), lds, st, a,
+                           args...);
+}
+
 }  // namespace
 
 hipError_t launch_adjoint_kick(const SimArgs& a, const float4* w_user, float4* lam_r, double* theta, float coef,
                                hipStream_t st) {
     hipLaunchKernelGGL(k_gather_vec, dim3((a.n + 255) / 256), dim3(256), 0, st, a, w_user);
-    const size_t lds = 2 * sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
-    hipLaunchKernelGGL((k_pair_pass<OP_ADJ>), dim3(a.ncells), dim3(kWave), lds, st, a,
-                       static_cast<const float4*>(a.vel1), lam_r, static_cast<float4*>(nullptr), coef, 0.f, 1.0, false);
+    launch_pair<OP_ADJ>(a, st, static_cast<const float4*>(a.vel1), lam_r, static_cast<float4*>(nullptr), coef, 0.f, 1.0,
+                        false);
     if (theta) hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(kRedBlock), 0, st, a, theta, static_cast<double>(coef));
     return hipGetLastError();
 }
@@ -392,10 +423,8 @@ hipError_t launch_adjoint_drift_kick(const SimArgs& a, float dt, float4* lam_r, 
                                      bool accumulate, hipStream_t st) {
     hipLaunchKernelGGL(k_drift_gather, dim3((a.n + 255) / 256), dim3(256), 0, st, a, dt,
                        static_cast<const float4*>(lam_r), lam_v);
-    const size_t lds = 2 * sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
-    hipLaunchKernelGGL((k_pair_pass<OP_ADJ>), dim3(a.ncells), dim3(kWave), lds, st, a,
-                       static_cast<const float4*>(a.vel1), lam_r, static_cast<float4*>(nullptr), coef, 0.f,
-                       static_cast<double>(coef), accumulate);
+    launch_pair<OP_ADJ>(a, st, static_cast<const float4*>(a.vel1), lam_r, static_cast<float4*>(nullptr), coef, 0.f,
+                        static_cast<double>(coef), accumulate);
     return hipGetLastError();
 }
 
@@ -406,9 +435,7 @@ hipError_t launch_theta_final(const SimArgs& a, double* theta, double coef, hipS
 
 hipError_t launch_loss_grad(const SimArgs& a, float kcoef, float wcoef, float4* g_r, float4* g_v, double* theta,
                             hipStream_t st) {
-    const size_t lds = sizeof(float4) * static_cast<size_t>(a.tile_cap + kTilePad);
-    hipLaunchKernelGGL((k_pair_pass<OP_VGRAD>), dim3(a.ncells), dim3(kWave), lds, st, a,
-                       static_cast<const float4*>(nullptr), g_r, g_v, wcoef, kcoef, 1.0, false);
+    launch_pair<OP_VGRAD>(a, st, static_cast<const float4*>(nullptr), g_r, g_v, wcoef, kcoef, 1.0, false);
     if (theta) hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(kRedBlock), 0, st, a, theta, static_cast<double>(wcoef));
     return hipGetLastError();
 }
