@@ -38,10 +38,10 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def _loaded(pos4, box, vel4=None):
+def _loaded(pos4, box, vel4=None, waves=0):
     from paper_0709_3225_amd import LJSystem
 
-    s = LJSystem(len(pos4), box)
+    s = LJSystem(len(pos4), box, waves_per_cell=waves)
     s.load(_dev(pos4), None if vel4 is None else _dev(vel4), forces=False)
     return s
 
@@ -55,16 +55,19 @@ HVP_CASES = {
 }
 
 
+@pytest.mark.parametrize("waves", [1, 2, 4])
 @pytest.mark.parametrize("name", list(HVP_CASES))
-def test_hvp_and_force_parameter_derivatives(name, orc):
+def test_hvp_and_force_parameter_derivatives(name, waves, orc):
+    """The pair pass with one, two or four wavefronts per cell (each
+    wavefront screens and walks its own range of the candidates)."""
     torch = _torch()
     from paper_0709_3225_amd import _lib as L
 
     pos4, vel4, box = ljsynth.make_state(HVP_CASES[name](), jitter_amp=0.05, shuffle=True)
-    _say(f"hvp {name} n={len(pos4)}")
+    _say(f"hvp {name} n={len(pos4)} waves={waves}")
     w = np.zeros_like(pos4)
     w[:, :3] = np.random.default_rng(7).normal(size=(len(pos4), 3))
-    s = _loaded(pos4, box)
+    s = _loaded(pos4, box, waves=waves)
     lam = torch.zeros((len(pos4), 4), dtype=torch.float32, device="cuda")
     theta = torch.zeros(2, dtype=torch.float64, device="cuda")
     L.md_adjoint_kick(s.params, s.ws, _dev(w), lam, theta, 1.0)
@@ -119,15 +122,16 @@ def test_hvp_symmetry_and_translation():
     assert s.check() == 0
 
 
+@pytest.mark.parametrize("waves", [1, 4])
 @pytest.mark.parametrize("name", ["lj256_check", "lj4k", "rho0.1_32k"])
-def test_loss_gradient(name, orc):
+def test_loss_gradient(name, waves, orc):
     torch = _torch()
     from paper_0709_3225_amd import _lib as L
 
     pos4, vel4, box = ljsynth.make_state(HVP_CASES[name](), jitter_amp=0.05)
-    _say(f"loss gradient {name}")
+    _say(f"loss gradient {name} waves={waves}")
     n = len(pos4)
-    s = _loaded(pos4, box, vel4)
+    s = _loaded(pos4, box, vel4, waves=waves)
     gr = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
     gv = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
     theta = torch.zeros(2, dtype=torch.float64, device="cuda")
