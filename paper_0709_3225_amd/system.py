@@ -49,10 +49,15 @@ class LJSystem:
         L.md_forces(self.params, self.ws, out)
         return out
 
-    def step(self, nsteps: int, thermo_every: int = 0):
+    def step(self, nsteps: int, thermo_every: int = 0, thermo_out: torch.Tensor | None = None):
+        """md_step; with thermo_every > 0, (U, K, W) of every thermo_every-th
+        step in FP64, into thermo_out if given (at least nsteps //
+        thermo_every rows of 3 doubles) or a new tensor."""
         thermo = None
         if thermo_every > 0 and nsteps >= thermo_every:
-            thermo = torch.empty((nsteps // thermo_every, 3), dtype=torch.float64, device=self.device)
+            thermo = thermo_out
+            if thermo is None:
+                thermo = torch.empty((nsteps // thermo_every, 3), dtype=torch.float64, device=self.device)
         L.md_step(self.params, self.ws, nsteps, thermo_every if thermo is not None else 0, thermo)
         return thermo
 
