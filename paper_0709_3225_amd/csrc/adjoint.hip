@@ -314,21 +314,36 @@ __global__ void __launch_bounds__(MW * kWave)
     }
 }
 
-// theta[0..1] += coef * (fixed-order sums of the per-block partials).
-constexpr int kRedBlock = 256;
-__global__ void __launch_bounds__(kRedBlock) k_theta_final(SimArgs a, double* theta, double coef) {
+// theta[0..1] += coef * (fixed-order sums of the per-block partials): lane t
+// sums blocks t, t + kThetaBlock, ... in that order (the loads of kThetaUnroll
+// blocks issued before their sums), then a fixed tree over the lanes.
+constexpr int kThetaBlock = 1024;
+constexpr int kThetaUnroll = 8;
+__global__ void __launch_bounds__(kThetaBlock) k_theta_final(SimArgs a, double* theta, double coef) {
     if (!state_ok(a, false)) return;
-    __shared__ double s0[kRedBlock], s1[kRedBlock];
+    __shared__ double s0[kThetaBlock], s1[kThetaBlock];
     const int t = threadIdx.x;
     double x0 = 0.0, x1 = 0.0;
-    for (int b = t; b < a.ncells; b += kRedBlock) {
-        x0 += a.epart[3 * b + 0];
-        x1 += a.epart[3 * b + 1];
+    for (int b0 = t; b0 < a.ncells; b0 += kThetaBlock * kThetaUnroll) {
+        double p0[kThetaUnroll], p1[kThetaUnroll];
+#pragma unroll
+        for (int q = 0; q < kThetaUnroll; ++q) {
+            const int b = b0 + q * kThetaBlock;
+            p0[q] = b < a.ncells ? a.epart[3 * b + 0] : 0.0;
+            p1[q] = b < a.ncells ? a.epart[3 * b + 1] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kThetaUnroll; ++q) {
+            if (b0 + q * kThetaBlock < a.ncells) {
+                x0 += p0[q];
+                x1 += p1[q];
+            }
+        }
     }
     s0[t] = x0;
     s1[t] = x1;
     __syncthreads();
-    for (int off = kRedBlock / 2; off > 0; off >>= 1) {
+    for (int off = kThetaBlock / 2; off > 0; off >>= 1) {
         if (t < off) {
             s0[t] += s0[t + off];
             s1[t] += s1[t + off];
@@ -415,7 +430,7 @@ hipError_t launch_adjoint_kick(const SimArgs& a, const float4* w_user, float4* l
     hipLaunchKernelGGL(k_gather_vec, dim3((a.n + 255) / 256), dim3(256), 0, st, a, w_user);
     launch_pair<OP_ADJ>(a, st, static_cast<const float4*>(a.vel1), lam_r, static_cast<float4*>(nullptr), coef, 0.f, 1.0,
                         false);
-    if (theta) hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(kRedBlock), 0, st, a, theta, static_cast<double>(coef));
+    if (theta) hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(kThetaBlock), 0, st, a, theta, static_cast<double>(coef));
     return hipGetLastError();
 }
 
@@ -429,14 +444,14 @@ hipError_t launch_adjoint_drift_kick(const SimArgs& a, float dt, float4* lam_r, 
 }
 
 hipError_t launch_theta_final(const SimArgs& a, double* theta, double coef, hipStream_t st) {
-    hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(kRedBlock), 0, st, a, theta, coef);
+    hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(kThetaBlock), 0, st, a, theta, coef);
     return hipGetLastError();
 }
 
 hipError_t launch_loss_grad(const SimArgs& a, float kcoef, float wcoef, float4* g_r, float4* g_v, double* theta,
                             hipStream_t st) {
     launch_pair<OP_VGRAD>(a, st, static_cast<const float4*>(nullptr), g_r, g_v, wcoef, kcoef, 1.0, false);
-    if (theta) hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(kRedBlock), 0, st, a, theta, static_cast<double>(wcoef));
+    if (theta) hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(kThetaBlock), 0, st, a, theta, static_cast<double>(wcoef));
     return hipGetLastError();
 }
 

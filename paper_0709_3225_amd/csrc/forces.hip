@@ -458,19 +458,22 @@ __global__ void __launch_bounds__(MW * kWave)
 
 // Fixed-order final sum of the per-block partials: U = 1/2 sum, W = 1/2 sum
 // (every pair is visited from both sides), K as is.
-constexpr int kRedBlock = 256;
+constexpr int kRedBlock = 256;    // batched finals: one workgroup per replica
+constexpr int kFinalBlock = 1024; // the single system's final sum
 constexpr int kRedUnroll = 8;
 
-// Lane t's running sums of the (U, W, K) partials of blocks t, t + kRedBlock,
-// t + 2 kRedBlock, ... in that order; the loads of kRedUnroll blocks are
-// issued before their sums, so the sequential order costs no round trips.
+// Lane t's running sums of the (U, W, K) partials of blocks t, t + BLOCK,
+// t + 2 BLOCK, ... in that order; the loads of kRedUnroll blocks are issued
+// before their sums, so the sequential order costs one round trip per
+// BLOCK * kRedUnroll blocks.
+template <int BLOCK>
 __device__ __forceinline__ void sum_partials(const double* __restrict__ e, int n, int t, double& u, double& w,
                                              double& k) {
-    for (int b0 = t; b0 < n; b0 += kRedBlock * kRedUnroll) {
+    for (int b0 = t; b0 < n; b0 += BLOCK * kRedUnroll) {
         double pu[kRedUnroll], pw[kRedUnroll], pk[kRedUnroll];
 #pragma unroll
         for (int q = 0; q < kRedUnroll; ++q) {
-            const int b = b0 + q * kRedBlock;
+            const int b = b0 + q * BLOCK;
             const bool ok = b < n;
             pu[q] = ok ? e[3 * b + 0] : 0.0;
             pw[q] = ok ? e[3 * b + 1] : 0.0;
@@ -478,7 +481,7 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ e, int n
         }
 #pragma unroll
         for (int q = 0; q < kRedUnroll; ++q) {
-            if (b0 + q * kRedBlock < n) {
+            if (b0 + q * BLOCK < n) {
                 u += pu[q];
                 w += pw[q];
                 k += pk[q];
@@ -488,18 +491,18 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ e, int n
 }
 // LOSS: out3[0] = kcoef K + wcoef W instead of (U, K, W).
 template <bool LOSS>
-__global__ void __launch_bounds__(kRedBlock) k_energy_final(SimArgs a, double* out3, bool from_step, double kcoef,
-                                                            double wcoef) {
+__global__ void __launch_bounds__(kFinalBlock) k_energy_final(SimArgs a, double* out3, bool from_step, double kcoef,
+                                                              double wcoef) {
     if (from_step && (a.hdr[HDR_ERROR] & DEV_ORDER)) return;
-    __shared__ double su[kRedBlock], sw[kRedBlock], sk[kRedBlock];
+    __shared__ double su[kFinalBlock], sw[kFinalBlock], sk[kFinalBlock];
     const int t = threadIdx.x;
     double u = 0.0, w = 0.0, k = 0.0;
-    sum_partials(a.epart, a.ncells, t, u, w, k);
+    sum_partials<kFinalBlock>(a.epart, a.ncells, t, u, w, k);
     su[t] = u;
     sw[t] = w;
     sk[t] = k;
     __syncthreads();
-    for (int off = kRedBlock / 2; off > 0; off >>= 1) {
+    for (int off = kFinalBlock / 2; off > 0; off >>= 1) {
         if (t < off) {
             su[t] += su[t + off];
             sw[t] += sw[t + off];
@@ -527,7 +530,7 @@ __global__ void __launch_bounds__(kRedBlock)
     const Replica r = reps[blockIdx.x];
     const int t = threadIdx.x;
     double u = 0.0, w = 0.0, k = 0.0;
-    sum_partials(base.epart + 3 * static_cast<size_t>(r.cbase), r.ncells, t, u, w, k);
+    sum_partials<kRedBlock>(base.epart + 3 * static_cast<size_t>(r.cbase), r.ncells, t, u, w, k);
     su[t] = u;
     sw[t] = w;
     sk[t] = k;
@@ -636,12 +639,12 @@ hipError_t launch_forces_list(const SimArgs& a_in, bool energy, bool record, boo
 }
 
 hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st) {
-    hipLaunchKernelGGL(k_energy_final<false>, dim3(1), dim3(kRedBlock), 0, st, a, out3, true, 0.0, 0.0);
+    hipLaunchKernelGGL(k_energy_final<false>, dim3(1), dim3(kFinalBlock), 0, st, a, out3, true, 0.0, 0.0);
     return hipGetLastError();
 }
 
 hipError_t launch_loss_final(const SimArgs& a, double kcoef, double wcoef, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_energy_final<true>, dim3(1), dim3(kRedBlock), 0, st, a, out, true, kcoef, wcoef);
+    hipLaunchKernelGGL(k_energy_final<true>, dim3(1), dim3(kFinalBlock), 0, st, a, out, true, kcoef, wcoef);
     return hipGetLastError();
 }
 

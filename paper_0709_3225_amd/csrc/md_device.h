@@ -67,7 +67,8 @@ __device__ __forceinline__ int half_kick_drift(const SimArgs& a, float4& p, floa
 // the same cell in a contiguous run share one atomicAdd of the run length on
 // the histogram; input that is already cell-sorted (every step after the
 // first) turns most per-atom atomics into one per run. bcount (nullable)
-// receives the run length per block of 16 cells too. Atomics on one address
+// receives the count per block of 16 cells too, one atomic per run of lanes
+// in the same block. Atomics on one address
 // serialise (about 0.15 us each here), so nothing coarser than 16 cells is
 // counted atomically. Must be called by all 64 lanes of the wave.
 __device__ __forceinline__ int histogram_rank(int* count, int* bcount, int c) {
@@ -80,9 +81,17 @@ __device__ __forceinline__ int histogram_rank(int* count, int* bcount, int c) {
     const int next_head = above ? (__ffsll(static_cast<unsigned long long>(above)) - 1) : kWave;
     const int my_head = 63 - __clzll(static_cast<long long>(heads & upto));
     int base = 0;
-    if (head && c >= 0) {
-        base = atomicAdd(&count[c], next_head - lane);
-        if (bcount) atomicAdd(&bcount[c >> kBlockShift], next_head - lane);
+    if (head && c >= 0) base = atomicAdd(&count[c], next_head - lane);
+    if (bcount) {
+        // the block counts, one atomic per run of lanes in the same block of
+        // cells (several cells of a run share a block counter)
+        const int bk = c >= 0 ? (c >> kBlockShift) : -1;
+        const int prevb = __shfl_up(bk, 1);
+        const bool bhead = (lane == 0) || (prevb != bk);
+        const uint64_t bheads = __ballot(bhead);
+        const uint64_t babove = bheads & ~upto;
+        const int next_bhead = babove ? (__ffsll(static_cast<unsigned long long>(babove)) - 1) : kWave;
+        if (bhead && bk >= 0) atomicAdd(&bcount[bk], next_bhead - lane);
     }
     base = __shfl(base, my_head);
     return base + (lane - my_head);
