@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint throughput leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-replica throughput leg")
     ap.add_argument("--no-widened", action="store_true", help="skip the density-axis, WCA and skin legs")
-    ap.add_argument("--only", choices=("adjoint", "batched"),
+    ap.add_argument("--only", choices=("adjoint", "batched", "neighbor_list"),
                     help="run only this leg and print its JSON (for kernel traces of one leg)")
     return ap.parse_args()
 
@@ -308,7 +308,46 @@ def wca_leg(torch, nsteps=100, warm=20):
     best = max(points, key=lambda p: p["value"])
     return {"workload": f"{w.name}: WCA N={w.n} (40^3 FCC start), rho={w.density}, T*={w.temperature}, "
                         f"rc=2^(1/6) sigma energy-shifted, dt={w.dt}, {nsteps} steps after {warm}",
-            "unit": "atom-steps/s", "points": points, "best": best["cells"], "value": best["value"]}
+            "unit": "atom-steps/s", "points": points, "best": best["cells"], "value": best["value"],
+            "neighbor_list": wca_list_points(torch, w, box, nsteps, warm)}
+
+
+def wca_list_points(torch, w, box, nsteps, warm):
+    """The WCA workload with per-atom Verlet lists (md_step_nlist) of radius
+    r_V = r_c + skin on the occupancy-sized cells: the lists hold about 15
+    partners per atom against the 27 cells' 390 candidates. A point is valid
+    without MD_DEV_SKIN (an atom moved by more than skin / 2 between
+    rebuilds) or MD_DEV_NB_OVERFLOW."""
+    from paper_0709_3225_amd import LJSystem, occupancy_cell_min
+    import ljsynth
+
+    pos4, vel4, _ = ljsynth.make_state(w)
+    cm = occupancy_cell_min(w.n, box, w.rc_over_sigma)
+    points = []
+    for skin, every in ((0.3, 5), (0.3, 8), (0.5, 10), (0.5, 15)):
+        s = LJSystem(w.n, box, rc_over_sigma=w.rc_over_sigma, shift_mode=w.shift_mode, dt=w.dt, cell_min=cm,
+                     list_radius=w.rc_over_sigma + skin, atom_lists=True)
+        s.load(torch.from_numpy(pos4).cuda(), torch.from_numpy(vel4).cuda())
+        s.step(warm)
+        s.step_nlist(every + 1, every)  # every kernel of the timed run once
+        s.check(raise_on_error=False)
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        s.step_nlist(nsteps, every)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = max(time.perf_counter() - t0, e0.elapsed_time(e1) / 1e3)
+        flags = s.check(raise_on_error=False)
+        points.append({"list_radius": round(w.rc_over_sigma + skin, 4), "cells_per_dim": s.cells_per_dim,
+                       "rebuild_every": every, "value": w.n * nsteps / t, "us_per_step": t * 1e6 / nsteps,
+                       "valid": flags == 0})
+    valid = [p for p in points if p["valid"]]
+    best = max(valid, key=lambda p: p["value"]) if valid else None
+    return {"points": points, "best": {k: best[k] for k in ("list_radius", "rebuild_every")} if best else None,
+            "value": best["value"] if best else None}
 
 
 def skin_leg(torch, nsteps=100, warm=20):
@@ -338,12 +377,14 @@ def skin_leg(torch, nsteps=100, warm=20):
             "value": best["value"]}
 
 
-def pair_list_leg(torch, nsteps=100, warm=20):
+def pair_list_leg(torch, nsteps=100, warm=20, atom_lists=False):
     """The headline workload with pair lists (md_step_list): the force pass
     after each cell rebuild records every lane's candidates within the cell
     side, the passes in between walk them; the skin is the grid's margin over
-    r_c. A point is valid when no atom moved by half the skin since the lists
-    were recorded (no MD_DEV_SKIN)."""
+    r_c. With atom_lists, md_step_nlist: the pass after each rebuild writes
+    every atom's neighbour list, one lane per atom walks it in between. A
+    point is valid when no atom moved by half the skin since the lists were
+    recorded and no list overflowed (no MD_DEV_SKIN, MD_DEV_NB_OVERFLOW)."""
     import ljsynth
     from paper_0709_3225_amd import LJSystem
 
@@ -351,15 +392,18 @@ def pair_list_leg(torch, nsteps=100, warm=20):
     pos4, vel4, box = ljsynth.make_state(w)
     points = []
     for cm, every in ((0.0, 2), (0.0, 3), (0.0, 4), (2.7, 6), (2.7, 10), (2.9, 10), (2.9, 15)):
-        s = LJSystem(w.n, box, dt=w.dt, cell_min=cm, pair_lists=True)
+        s = LJSystem(w.n, box, dt=w.dt, cell_min=cm, pair_lists=not atom_lists, atom_lists=atom_lists)
         s.load(torch.from_numpy(pos4).cuda(), torch.from_numpy(vel4).cuda())
         s.step(warm)
+        run = s.step_nlist if atom_lists else s.step_list
+        run(every + 1, every)  # every kernel of the timed run once
+        s.check(raise_on_error=False)
         stream = torch.cuda.current_stream()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         e0.record(stream)
-        s.step_list(nsteps, every)
+        run(nsteps, every)
         e1.record(stream)
         torch.cuda.synchronize()
         t = max(time.perf_counter() - t0, e0.elapsed_time(e1) / 1e3)
@@ -369,8 +413,9 @@ def pair_list_leg(torch, nsteps=100, warm=20):
                        "valid": flags == 0})
     valid = [p for p in points if p["valid"]]
     best = max(valid, key=lambda p: p["value"]) if valid else None
+    kind = "per-atom neighbour lists written" if atom_lists else "pair lists recorded"
     return {"workload": f"{w.name}: LJ N={w.n}, rho={w.density}, T*={w.temperature}, {nsteps} steps after {warm}, "
-                        "pair lists recorded at each cell rebuild (every k steps)",
+                        f"{kind} at each cell rebuild (every k steps)",
             "unit": "atom-steps/s", "points": points,
             "best": {k: best[k] for k in ("skin", "rebuild_every")} if best else None,
             "value": best["value"] if best else None}
@@ -548,7 +593,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.only:
-        leg = adjoint_leg(torch) if args.only == "adjoint" else batched_leg(torch)
+        legs = {"adjoint": adjoint_leg, "batched": batched_leg,
+                "neighbor_list": lambda t: pair_list_leg(t, atom_lists=True)}
+        leg = legs[args.only](torch)
         print(json.dumps({args.only: leg}), flush=True)
         return
     w = ljsynth.WORKLOADS[args.workload]
@@ -661,6 +708,7 @@ def main():
         out["wca"] = wca_leg(torch)
         out["skin"] = skin_leg(torch)
         out["pair_list"] = pair_list_leg(torch)
+        out["neighbor_list"] = pair_list_leg(torch, atom_lists=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s.state()[0].cpu().numpy(), box, args.cpu_seconds)
         sp, sv = s.state()

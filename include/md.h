@@ -54,7 +54,9 @@ typedef enum md_status {
 #define MD_DEV_NONFINITE 1 /* a coordinate, velocity or force was not finite */
 #define MD_DEV_ORDER 2     /* md_forces before md_build_cells, or md_step
                               before md_forces: the call did nothing */
-#define MD_DEV_NB_OVERFLOW 4 /* md_neighbors: a row exceeded max_per_atom */
+#define MD_DEV_NB_OVERFLOW 4 /* md_neighbors: a row exceeded max_per_atom;
+                              md_step_nlist: an atom had more partners
+                              within the list radius than its list holds */
 #define MD_DEV_SKIN 8      /* md_step_every: between rebuilds an atom left its
                               cell by more than half the skin; that run may
                               have missed pairs near r_c */
@@ -82,12 +84,23 @@ typedef struct md_params {
                               sums differs (bitwise reproducible for a fixed
                               choice). The pair-list and neighbour-export
                               passes always take one. */
+    float list_radius;     /* md_step_list / md_step_nlist: radius r_V of the
+                              pair and neighbour lists (section 3: r_c plus a
+                              skin), r_c < r_V <= cell side; 0 selects the cell
+                              side. The lists stay valid while no atom has
+                              moved by more than (r_V - r_c) / 2. */
 } md_params;
 
 /* md_params.flags: lay the workspace out with md_step_list's pair-list
  * arrays (about 4.3 KB per cell and 16 B per atom more); md_step_list
  * refuses a workspace without them. */
 #define MD_FLAG_PAIR_LISTS 1
+/* md_params.flags: lay the workspace out with md_step_nlist's per-atom
+ * neighbour lists (about 4 B x the list capacity + 20 B per atom; the
+ * capacity is 1.5 x the mean number of atoms within the cell side of an atom
+ * plus 32, rounded up to a multiple of 32); md_step_nlist refuses a
+ * workspace without them. */
+#define MD_FLAG_ATOM_LISTS 2
 
 /*
  * Bytes of device workspace for these parameters (0 if they are invalid).
@@ -200,6 +213,27 @@ md_status md_step_every(const md_params* p, void* ws, size_t ws_bytes, int32_t n
 md_status md_step_list(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps,
                        int32_t rebuild_every, int32_t thermo_every, double* thermo_dev,
                        hipStream_t stream);
+
+/*
+ * md_step_every with per-atom Verlet neighbour lists (section 3: partners
+ * within a radius larger than r_c, valid until a particle has moved by more
+ * than half the difference). The force pass right after each cell rebuild
+ * screens the 27-cell neighbourhood against the cell side and writes, for
+ * every atom, the sorted slot and periodic image of every partner it finds;
+ * until the next rebuild, one lane per atom walks its own list: no cell
+ * staging and no screen. Thermo steps between rebuilds screen the cells
+ * instead, and the last step of a call is an ordinary md_step force pass. An
+ * atom with more partners than the list holds sets MD_DEV_NB_OVERFLOW (the
+ * ones past the capacity are missed until the next rebuild); MD_DEV_SKIN is
+ * set if an atom moves more than (cell side - r_c) / 2 from where it was when
+ * the lists were written. The forces are those of md_step_every summed in
+ * another order, so trajectories agree to FP32 rounding, not bitwise.
+ * Arguments and return values as for md_step_every; the workspace must have
+ * been sized with MD_FLAG_ATOM_LISTS in p->flags (MD_ERR_ARG otherwise).
+ */
+md_status md_step_nlist(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps,
+                        int32_t rebuild_every, int32_t thermo_every, double* thermo_dev,
+                        hipStream_t stream);
 
 /*
  * Potential energy U, kinetic energy K = m/2 sum v^2 and virial

@@ -26,6 +26,7 @@ MD_DEV_NB_OVERFLOW = 4
 MD_DEV_SKIN = 8
 
 MD_FLAG_PAIR_LISTS = 1
+MD_FLAG_ATOM_LISTS = 2
 
 # Symbols declared in include/md.h, in declaration order.
 SYMBOLS = (
@@ -37,6 +38,7 @@ SYMBOLS = (
     "md_step",
     "md_step_every",
     "md_step_list",
+    "md_step_nlist",
     "md_energy_virial",
     "md_get_state",
     "md_neighbors",
@@ -82,6 +84,7 @@ class MDParams(ctypes.Structure):
         ("shift_mode", ctypes.c_int32),
         ("flags", ctypes.c_int32),
         ("waves_per_cell", ctypes.c_int32),
+        ("list_radius", ctypes.c_float),
     ]
 
 
@@ -101,9 +104,9 @@ def replica_table(reps):
 
 
 def make_params(n, box, epsilon=1.0, sigma=1.0, mass=1.0, rc_over_sigma=2.5, dt=0.005, cell_min=0.0,
-                shift_mode=0, flags=0, waves_per_cell=0) -> MDParams:
+                shift_mode=0, flags=0, waves_per_cell=0, list_radius=0.0) -> MDParams:
     return MDParams(int(n), float(box), float(epsilon), float(sigma), float(mass), float(rc_over_sigma),
-                    float(dt), float(cell_min), int(shift_mode), int(flags), int(waves_per_cell))
+                    float(dt), float(cell_min), int(shift_mode), int(flags), int(waves_per_cell), float(list_radius))
 
 
 _lib = None
@@ -129,6 +132,7 @@ def lib():
         L.md_step.argtypes = [P, vp, sz, i32, i32, vp, vp]
         L.md_step_every.argtypes = [P, vp, sz, i32, i32, i32, vp, vp]
         L.md_step_list.argtypes = [P, vp, sz, i32, i32, i32, vp, vp]
+        L.md_step_nlist.argtypes = [P, vp, sz, i32, i32, i32, vp, vp]
         L.md_energy_virial.argtypes = [P, vp, sz, vp, vp]
         L.md_get_state.argtypes = [P, vp, sz, vp, vp, vp]
         L.md_neighbors.argtypes = [P, vp, sz, vp, vp, i32, vp]
@@ -290,6 +294,21 @@ def md_step_list(p: MDParams, ws, nsteps: int, rebuild_every: int, thermo_every:
         tp = _ptr(thermo, "thermo", torch.float64)
     _check(lib().md_step_list(ctypes.byref(p), wp, wn, int(nsteps), int(rebuild_every), int(thermo_every), tp,
                               _stream(stream)))
+
+
+def md_step_nlist(p: MDParams, ws, nsteps: int, rebuild_every: int, thermo_every: int = 0, thermo=None,
+                  stream=None):
+    import torch
+
+    wp, wn = _ws(ws)
+    tp = None
+    if thermo is not None:
+        rows = nsteps // thermo_every if thermo_every > 0 else 0
+        if thermo.numel() < 3 * rows:
+            raise ValueError(f"thermo needs {3 * rows} doubles")
+        tp = _ptr(thermo, "thermo", torch.float64)
+    _check(lib().md_step_nlist(ctypes.byref(p), wp, wn, int(nsteps), int(rebuild_every), int(thermo_every), tp,
+                               _stream(stream)))
 
 
 def md_energy_virial(p: MDParams, ws, out3, stream=None):

@@ -385,9 +385,24 @@ __device__ __forceinline__ bool row_hood(const SimArgs& a, int c, RowHood& r) {
 }
 
 // Second tile of the staging functions below (SECOND): none; the untranslated
-// positions (w = user index); or the entries of vsrc, a per-atom vector in
-// sorted order. Either goes to raw at the same indices as the positions.
-enum { SECOND_NONE = 0, SECOND_RAW = 1, SECOND_VEC = 2 };
+// positions (w = user index); the entries of vsrc, a per-atom vector in
+// sorted order; or (SECOND_CODE, 32-bit entries) each atom's neighbour-list
+// entry: its sorted slot with the code of the periodic image the frame
+// translation applied. Any of them goes to raw at the same indices as the
+// positions.
+enum { SECOND_NONE = 0, SECOND_RAW = 1, SECOND_VEC = 2, SECOND_CODE = 3 };
+
+// Image shift along one axis of a neighbour whose atoms are staged at
+// x - f in the frame of origin o: the partner of the home atom is x + s L
+// with s L = o - f, i.e. s = -1, 0 or +1.
+__device__ __forceinline__ int image_shift(float o, float f, float box) {
+    const float d = o - f;
+    return d > 0.5f * box ? 1 : (d < -0.5f * box ? -1 : 0);
+}
+
+__device__ __forceinline__ uint32_t list_entry(int slot, int sx, int sy, int sz) {
+    return static_cast<uint32_t>(slot) | (static_cast<uint32_t>((sx + 1) + 3 * (sy + 1) + 9 * (sz + 1)) << kSlotBits);
+}
 
 // Staging of a RowHood neighbourhood in one pass (total <= tile capacity), by
 // the same unmasked scheme as stage_whole (rows tile [0, total) in order).
@@ -398,13 +413,13 @@ __device__ __forceinline__ void stage_rows(const SimArgs& a, const RowHood& r, f
     const int last = a.natoms - 1;
     const char* pbase = reinterpret_cast<const char*>(a.pos0);
     const char* vbase = reinterpret_cast<const char*>(vsrc);
-    float4 q[9], v[SECOND == SECOND_VEC ? 9 : 1];
+    float4 q[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const uint32_t off = static_cast<uint32_t>(min(r.first[k] + lane, last)) << 4;
         q[k] = *reinterpret_cast<const float4*>(pbase + off);
-        if (SECOND == SECOND_VEC) v[k] = *reinterpret_cast<const float4*>(vbase + off);
     }
+    uint32_t* codes = reinterpret_cast<uint32_t*>(raw);
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const float x = q[k].x - r.ox;
@@ -412,8 +427,22 @@ __device__ __forceinline__ void stage_rows(const SimArgs& a, const RowHood& r, f
         const float z = q[k].z - r.fz[k / 3];
         tile[r.pos[k] + lane] = make_float4(x, y, z, x * x + y * y + z * z);
         if (SECOND == SECOND_RAW) raw[r.pos[k] + lane] = q[k];
-        if (SECOND == SECOND_VEC) raw[r.pos[k] + lane] = v[k];
+        if (SECOND == SECOND_CODE)
+            codes[r.pos[k] + lane] = list_entry(r.first[k] + lane, 0, image_shift(r.oy, r.fy[k % 3], a.box),
+                                                image_shift(r.oz, r.fz[k / 3], a.box));
         __builtin_amdgcn_sched_barrier(0);
+    }
+    if (SECOND == SECOND_VEC) {  // a second round (the positions' registers are free again)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const uint32_t off = static_cast<uint32_t>(min(r.first[k] + lane, last)) << 4;
+            q[k] = *reinterpret_cast<const float4*>(vbase + off);
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            raw[r.pos[k] + lane] = q[k];
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -426,6 +455,9 @@ __device__ __forceinline__ void stage_rows(const SimArgs& a, const RowHood& r, f
                     tile[r.pos[k] + off] = make_float4(x, y, z, x * x + y * y + z * z);
                     if (SECOND == SECOND_RAW) raw[r.pos[k] + off] = u;
                     if (SECOND == SECOND_VEC) raw[r.pos[k] + off] = vsrc[r.first[k] + off];
+                    if (SECOND == SECOND_CODE)
+                        codes[r.pos[k] + off] = list_entry(r.first[k] + off, 0, image_shift(r.oy, r.fy[k % 3], a.box),
+                                                           image_shift(r.oz, r.fz[k / 3], a.box));
                 }
             }
         }
@@ -451,6 +483,24 @@ __device__ __forceinline__ void stage_tile(const SimArgs& a, const Neighbourhood
         StageCursor issue = cur;
         stage_issue(a, h, issue, t1, b, vec);
         stage_commit<B, ID_IN_W, WITH_VEC>(h, b, cur, t0, t1, tile, vtile);
+    }
+}
+
+// Neighbour-list entries (list_entry) of neighbourhood atoms [t0, t0 + tn) of
+// the table in nb, into codes[0, tn): the companion of stage_tile for the
+// pass that writes the neighbour lists.
+__device__ __forceinline__ void stage_codes(const SimArgs& a, const Neighbourhood& nb, uint32_t* codes, int t0,
+                                            int tn) {
+    const int lane = __lane_id();
+    const int t1 = t0 + tn;
+    const int nseg = nb.nseg;
+    for (int k = 0; k < nseg; ++k) {  // uniform
+        const int p = nb.seg_pos[k], len = nb.seg_len[k], first = nb.seg_first[k];
+        const int lo = max(p, t0), hi = min(p + len, t1);
+        const int sx = image_shift(nb.origin[0], nb.sx[k], a.box);
+        const int sy = image_shift(nb.origin[1], nb.sy[k], a.box);
+        const int sz = image_shift(nb.origin[2], nb.sz[k], a.box);
+        for (int t = lo + lane; t < hi; t += kWave) codes[t - t0] = list_entry(first + (t - p), sx, sy, sz);
     }
 }
 
@@ -717,13 +767,14 @@ __device__ __forceinline__ void stage_nine(const SimArgs& a, const RowPieces& r,
     const int last = a.natoms - 1;
     const char* pbase = reinterpret_cast<const char*>(a.pos0);
     const char* vbase = reinterpret_cast<const char*>(vsrc);
-    float4 q[9], v[SECOND == SECOND_VEC ? 9 : 1];
+    float4 q[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const uint32_t off = static_cast<uint32_t>(min(__builtin_amdgcn_readlane(r.first, K0 + k) + lane, last)) << 4;
         q[k] = *reinterpret_cast<const float4*>(pbase + off);
-        if (SECOND == SECOND_VEC) v[k] = *reinterpret_cast<const float4*>(vbase + off);
     }
+    uint32_t* codes = reinterpret_cast<uint32_t*>(raw);
+    const int sx = SECOND == SECOND_CODE ? image_shift(r.ox, fx, a.box) : 0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const float x = q[k].x - fx;
@@ -732,8 +783,23 @@ __device__ __forceinline__ void stage_nine(const SimArgs& a, const RowPieces& r,
         const int p = __builtin_amdgcn_readlane(r.pos, K0 + k);
         tile[p + lane] = make_float4(x, y, z, x * x + y * y + z * z);
         if (SECOND == SECOND_RAW) raw[p + lane] = q[k];
-        if (SECOND == SECOND_VEC) raw[p + lane] = v[k];
+        if (SECOND == SECOND_CODE)
+            codes[p + lane] = list_entry(__builtin_amdgcn_readlane(r.first, K0 + k) + lane, sx,
+                                         image_shift(r.oy, r.fy[k % 3], a.box), image_shift(r.oz, r.fz[k / 3], a.box));
         __builtin_amdgcn_sched_barrier(0);
+    }
+    if (SECOND == SECOND_VEC) {  // a second round (the positions' registers are free again)
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const uint32_t off = static_cast<uint32_t>(min(__builtin_amdgcn_readlane(r.first, K0 + k) + lane, last))
+                                 << 4;
+            q[k] = *reinterpret_cast<const float4*>(vbase + off);
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            raw[__builtin_amdgcn_readlane(r.pos, K0 + k) + lane] = q[k];
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
     if (__any(lane >= K0 && lane < K0 + 9 && r.len > kWave)) {  // rare
 #pragma unroll
@@ -748,6 +814,9 @@ __device__ __forceinline__ void stage_nine(const SimArgs& a, const RowPieces& r,
                         tile[p + off] = make_float4(x, y, z, x * x + y * y + z * z);
                         if (SECOND == SECOND_RAW) raw[p + off] = u;
                         if (SECOND == SECOND_VEC) raw[p + off] = vsrc[f + off];
+                        if (SECOND == SECOND_CODE)
+                            codes[p + off] = list_entry(f + off, sx, image_shift(r.oy, r.fy[k % 3], a.box),
+                                                        image_shift(r.oz, r.fz[k / 3], a.box));
                     }
                 }
             }

@@ -61,6 +61,30 @@ struct ForceOp {
     }
 };
 
+// Pair operation of the pass that writes the neighbour lists: the force as
+// ForceOp, and every candidate the walk visits (all within the list radius)
+// appended to the home atom's list at this lane's next free entry.
+template <bool ENERGY>
+struct RecordOp {
+    const SimArgs& a;
+    const char* base;   // tile at the lane's span start
+    const char* cbase;  // list entries of the staged atoms at the same place (4 bytes each)
+    float xi, yi, zi;
+    uint32_t* row;      // the home atom's list: entry k at row[4 n (k / 4) + k % 4]
+    int next;
+    float fx = 0.f, fy = 0.f, fz = 0.f, u_loc = 0.f, w_loc = 0.f;
+    __device__ __forceinline__ void operator()(uint32_t off, bool live) {
+        const float4 q = *reinterpret_cast<const float4*>(base + off);
+        pair_force<ENERGY>(a, q, xi, yi, zi, live, fx, fy, fz, u_loc, w_loc);
+        if (live) {
+            if (next < a.nlist_cap)
+                row[4 * static_cast<size_t>(a.n) * (next >> 2) + (next & 3)] =
+                    *reinterpret_cast<const uint32_t*>(cbase + (off >> 2));
+            ++next;
+        }
+    }
+};
+
 // Neighbour export from the force kernel's own staging, screen and walk: every
 // pair the walk visits and the exact FP32 cutoff test of pair_force accepts
 // appends the partner's user index to the home atom's row (row order follows
@@ -136,6 +160,10 @@ __device__ __forceinline__ void kept_words(const uint4* rows, const uint4& w0, i
 // which add exact zeros, so the sums are bitwise those of the screen. A cell
 // with more than kListSpans spans per lane, or more than one pass, screens as
 // usual (and with the plain bound).
+// LIST 3: the screen takes the list radius and every candidate it accepts
+// goes to the home atom's neighbour list (raw: the staged atoms' list
+// entries, 4 bytes each); the slices of an atom append in slice order per
+// span, so an atom's list is written without atomics.
 // EXPORT: no forces; the pairs the walk accepts go to the neighbour rows of
 // ex (raw: a second tile of untranslated positions).
 template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT, bool SKIN = false, int LIST = 0, bool EXPORT = false,
@@ -166,7 +194,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         home_first = rh.home_first;
         n_home = rh.n_home;
         home_pos = rh.home_pos;
-        if (wv == 0) stage_rows<EXPORT ? SECOND_RAW : SECOND_NONE>(a, rh, tile, raw);
+        if (wv == 0) stage_rows<EXPORT ? SECOND_RAW : (LIST == 3 ? SECOND_CODE : SECOND_NONE)>(a, rh, tile, raw);
     }
     // a cell on an x face: the same one-pass staging from a table of row pieces
     RowPieces rp;
@@ -180,7 +208,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         home_first = rp.home_first;
         n_home = rp.n_home;
         home_pos = rp.home_pos;
-        if (wv == 0) stage_pieces<EXPORT ? SECOND_RAW : SECOND_NONE>(a, rp, tile, raw);
+        if (wv == 0) stage_pieces<EXPORT ? SECOND_RAW : (LIST == 3 ? SECOND_CODE : SECOND_NONE)>(a, rp, tile, raw);
     }
     if (!rows) {
         load_neighbourhood(a, c, nb, ox, oy, oz);
@@ -221,12 +249,12 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         if ((KICK || ENERGY) && lead) vel = a.vel0[home_first + h0 + h];
         float4 pref = pi;  // LIST: position when the lists were recorded
         if (LIST == 2 && SKIN && lead) pref = a.posref[home_first + h0 + h];
-        if (LIST == 1 && lead) a.posref[home_first + h0 + h] = pi;
+        if ((LIST == 1 || LIST == 3) && lead) a.posref[home_first + h0 + h] = pi;
         const float xi = pi.x - ox, yi = pi.y - oy, zi = pi.z - oz;
         const float ai = fmaf(zi, zi, fmaf(yi, yi, xi * xi));
         // idle lanes get a bound no candidate can meet (q.w - thr_i = +inf)
         // (the list radius only where the words are kept: other cells sum as the plain screen does)
-        const float thr_i = act ? ((LIST == 1 && list_fits) ? a.list_screen2 : a.screen2) - ai
+        const float thr_i = act ? (((LIST == 1 && list_fits) || LIST == 3) ? a.list_screen2 : a.screen2) - ai
                                 : -__builtin_huge_valf();
         const float mx = -2.0f * xi, my = -2.0f * yi, mz = -2.0f * zi;
         // matrix-core operands: this lane's element of B (component s of
@@ -234,6 +262,8 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         const float bval = s == 3 ? 1.0f : (act ? (s == 0 ? mx : (s == 1 ? my : mz)) : 0.0f);
         const float cneg = -thr_i;
         float fx = 0.f, fy = 0.f, fz = 0.f, u_loc = 0.f, w_loc = 0.f;
+        int lcount = 0, rec_next = 0;  // LIST 3: the atom's entries so far; this lane's next one
+        uint32_t* lrow_list = LIST == 3 ? a.nlist + 4 * static_cast<size_t>(home_first + h0 + h) : nullptr;
         for (int t0 = 0; t0 < total; t0 += a.tile_cap) {
             const int tn = min(a.tile_cap, total - t0);
             if (!rows) {
@@ -241,6 +271,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                 if (wv == 0) {
                     if (EXPORT) stage_tile<false, true>(a, nb, tile, t0, tn, a.pos0, raw);
                     else stage_tile<false>(a, nb, tile, t0, tn);
+                    if (LIST == 3) stage_codes(a, nb, reinterpret_cast<uint32_t*>(raw), t0, tn);
                 }
             }
             if (wv == 0)
@@ -249,8 +280,32 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
             const int self_t = home_pos + h0 + h - t0;  // the home atom's own tile index (may be outside)
             // the walk over one span's words; the lane's candidates are cand0,
             // cand0 + ns_, cand0 + 2 ns_, ...
+            // LIST 3: this lane's first entry for the span's accepted
+            // candidates (after those of the atom's lower slices)
+            auto list_base = [&](const uint32_t (&wd)[kWords]) {
+                if (LIST != 3) return;
+                const int cnt = __popc(wd[0]) + __popc(wd[1]) + __popc(wd[2]) + __popc(wd[3]);
+                int pre = 0, tot = 0;
+                for (int q = 0; q < ns; ++q) {
+                    const int v = __shfl(cnt, h + q * hstride);
+                    pre += q < s ? v : 0;
+                    tot += v;
+                }
+                rec_next = lcount + pre;
+                lcount += tot;
+            };
             auto walk = [&](int ns_, int cand0, uint32_t (&wd)[kWords]) {
-                if (EXPORT) {
+                if (LIST == 3) {
+                    const char* codes = reinterpret_cast<const char*>(reinterpret_cast<const uint32_t*>(raw) + cand0);
+                    RecordOp<ENERGY> op{a,  reinterpret_cast<const char*>(tile + cand0), codes, xi, yi, zi, lrow_list,
+                                        rec_next, fx, fy, fz, u_loc, w_loc};
+                    walk_bits(ns_, wd[0], wd[1], wd[2], wd[3], op);
+                    fx = op.fx;
+                    fy = op.fy;
+                    fz = op.fz;
+                    u_loc = op.u_loc;
+                    w_loc = op.w_loc;
+                } else if (EXPORT) {
                     ExportOp op{a, reinterpret_cast<const char*>(tile + cand0), reinterpret_cast<const char*>(raw + cand0),
                                 xi, yi, zi, __float_as_int(pi.w), ex};
                     walk_bits(ns_, wd[0], wd[1], wd[2], wd[3], op);
@@ -281,6 +336,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                         screen_mfma(tile, 16 * b0, nblk, bval, cneg, wd);
                         if (act) clear_self(self_t - 16 * b0, s, 4, 4 * nblk, wd);
                         if (LIST == 1 && list_fits) keep_words(lwords, n_rec, wd);
+                        list_base(wd);
                     }
                     // the lane's candidates are tile + 16 b0 + s + 4 g, as for four VALU slices
                     walk(4, 16 * b0 + s, wd);
@@ -309,6 +365,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                     }
                     if (act) clear_self(self_t, first, ns, groups, wd);
                     if (LIST == 1 && list_fits) keep_words(lwords, n_rec, wd);
+                    list_base(wd);
                 }
                 walk(ns, first, wd);
             }
@@ -330,6 +387,10 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         int c_next = -1;  // DRIFT: the home atom's next cell, -1 on lanes without one
         float4 p_next = pi, v_next = make_float4(0.f, 0.f, 0.f, 0.f);
         if (lead) {
+            if (LIST == 3) {  // the atom's list length (the entries past the capacity were not kept)
+                a.ncount[k] = min(lcount, a.nlist_cap);
+                if (lcount > a.nlist_cap) over = true;
+            }
             float gx = 0.f, gy = 0.f, gz = 0.f, gu = 0.f, gw = 0.f;
             for (int w = 0; w < nw; ++w) {
                 const float* part = red + 5 * kWave * w;
@@ -385,7 +446,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         if (DRIFT && !SKIN && wv == 0) bin_atom(a, p_next, v_next, c_next);  // all lanes of wavefront 0
     }
     if (LIST == 1) a.plist_n[lrow] = list_fits ? n_rec : kListSpans + 1;  // kept words of several passes are not used
-    if (EXPORT && over) atomicOr(&a.hdr[HDR_ERROR], DEV_NB_OVERFLOW);
+    if ((EXPORT || LIST == 3) && over) atomicOr(&a.hdr[HDR_ERROR], DEV_NB_OVERFLOW);
     if (bad) atomicOr(&a.hdr[HDR_ERROR], DEV_NONFINITE);
     if (SKIN && skin_out) atomicOr(&a.hdr[HDR_ERROR], DEV_SKIN);
     if (ENERGY) {
@@ -437,6 +498,128 @@ __global__ void __launch_bounds__(kWave) k_forces_list(SimArgs a) {
     __shared__ Neighbourhood nb;
     force_cell<true, ENERGY, false, true, !BIN, RECORD ? 1 : 2>(a, xcd_block_order(blockIdx.x, a.ncells), tile, nb,
                                                                 reinterpret_cast<float*>(tile));
+}
+
+// md_step_nlist, right after a rebuild: forces, kick and the next drift as
+// k_forces_list, and every atom's neighbour list within the list radius.
+template <bool ENERGY, bool BIN>
+__global__ void __launch_bounds__(kWave) k_forces_record(SimArgs a) {
+    if (a.hdr[HDR_ERROR] & DEV_ORDER) return;
+    extern __shared__ float4 tile[];  // a.tile_cap + kTilePad positions, then as many 4-byte list entries
+    __shared__ Neighbourhood nb;
+    force_cell<true, ENERGY, false, true, !BIN, 3>(a, xcd_block_order(blockIdx.x, a.ncells), tile, nb,
+                                                   reinterpret_cast<float*>(tile), tile + (a.tile_cap + kTilePad));
+}
+
+// md_step_nlist between rebuilds: kListLanes lanes per atom (sorted slots,
+// in the XCD order of the cell kernels) walk the atom's neighbour list, lane
+// s taking entry groups s, s + kListLanes, ...: partner j at x_j + s L (s
+// from the entry's image code), the truncated, shifted force of section 2
+// for r < r_c; the lanes' partials are added in a fixed order, then the
+// first lane of each atom applies the kick and the next half kick and drift
+// as the cell passes do (BIN: wrap and bin for the next rebuild; else
+// unwrapped into pos2/vel2 with the displacement check against the
+// positions the lists were written at). The displacement is formed as
+// (x_i - max(sL, 0)) - (x_j + min(sL, 0)): an image shift is taken off the
+// coordinate that lies within a cell of the far box face, where the
+// subtraction is exact, so d carries only the rounding of small numbers (as
+// the frame translation of the cell passes does).
+constexpr int kListBlock = 256;
+constexpr int kListLanes = 4;
+constexpr int kListAtoms = kListBlock / kListLanes;
+
+template <bool BIN>
+__global__ void __launch_bounds__(kListBlock) k_nlist_forces(SimArgs a) {
+    if (a.hdr[HDR_ERROR] & DEV_ORDER) return;
+    // max(s L, 0) and min(s L, 0) of each image code (the five code bits
+    // index 32 entries; codes past 26 never occur and shift by nothing)
+    constexpr int kCenter = 13;  // (0, 0, 0)
+    __shared__ float4 shp[32], shm[32];
+    if (threadIdx.x < 32) {
+        const int code = threadIdx.x < 27 ? threadIdx.x : kCenter;
+        const float sx = static_cast<float>(code % 3 - 1) * a.box, sy = static_cast<float>((code / 3) % 3 - 1) * a.box,
+                    sz = static_cast<float>(code / 9 - 1) * a.box;
+        shp[threadIdx.x] = make_float4(fmaxf(sx, 0.f), fmaxf(sy, 0.f), fmaxf(sz, 0.f), 0.f);
+        shm[threadIdx.x] = make_float4(fminf(sx, 0.f), fminf(sy, 0.f), fminf(sz, 0.f), 0.f);
+    }
+    __syncthreads();
+    const int lane = __lane_id();
+    const char* pbase = reinterpret_cast<const char*>(a.pos0);
+    const int last = a.n - 1;
+    const int sl = threadIdx.x % kListLanes;
+    const int i = xcd_block_order(blockIdx.x, gridDim.x) * kListAtoms + static_cast<int>(threadIdx.x) / kListLanes;
+    const bool valid = i < a.n;
+    float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
+    int cnt = 0;
+    if (valid) {
+        pi = a.pos0[i];
+        cnt = min(max(a.ncount[i], 0), a.nlist_cap);
+    }
+    // entries 4 g .. 4 g + 3 of every atom are one uint4, and the atoms' uint4
+    // of one group are consecutive
+    const uint4* col = reinterpret_cast<const uint4*>(a.nlist) + (valid ? i : 0);
+    float fx = 0.f, fy = 0.f, fz = 0.f, u_loc = 0.f, w_loc = 0.f;
+    for (int g = sl; 4 * g < cnt; g += kListLanes) {  // the capacity is a multiple of 4: whole uint4 loads
+        const uint4 e4 = col[static_cast<size_t>(a.n) * g];
+        const uint32_t e[4] = {e4.x, e4.y, e4.z, e4.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool in = 4 * g + u < cnt;
+            // entries past the count are not this atom's: read the atom itself, masked
+            const uint32_t ej = in ? e[u] : (static_cast<uint32_t>(i) | (kCenter << kSlotBits));
+            const uint32_t off = static_cast<uint32_t>(min(static_cast<int>(ej & kSlotMask), last)) << 4;
+            float4 q = *reinterpret_cast<const float4*>(pbase + off);
+            const int code = static_cast<int>(ej >> kSlotBits);
+            float xi = pi.x, yi = pi.y, zi = pi.z;
+            if (__any(code != kCenter)) {  // pairs across a box face (rare): the image shifts
+                const float4 hp = shp[code], hm = shm[code];
+                q.x += hm.x;
+                q.y += hm.y;
+                q.z += hm.z;
+                xi -= hp.x;
+                yi -= hp.y;
+                zi -= hp.z;
+            }
+            pair_force<false>(a, q, xi, yi, zi, in, fx, fy, fz, u_loc, w_loc);
+        }
+    }
+    // the atom's lanes are consecutive: sum (s0 + s1) + (s2 + s3)
+#pragma unroll
+    for (int off = 1; off < kListLanes; off <<= 1) {
+        fx += __shfl_xor(fx, off);
+        fy += __shfl_xor(fy, off);
+        fz += __shfl_xor(fz, off);
+    }
+    // the epilogue on one lane per atom: atom lane l of the wave's 16 from lane
+    // kListLanes * l, so that consecutive atoms sit in consecutive lanes (the
+    // binning's runs)
+    const int src = (lane * kListLanes) & (kWave - 1);
+    const float gx = __shfl(fx, src), gy = __shfl(fy, src), gz = __shfl(fz, src);
+    const int ia = (i - static_cast<int>(threadIdx.x % kWave) / kListLanes) + lane;  // the wave's first atom + lane
+    const bool own = lane < kWave / kListLanes && ia < a.n;
+    bool bad = false;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f), p_next = v;
+    if (own) {
+        p_next = a.pos0[ia];
+        v = a.vel0[ia];
+        bad = !finite3(gx, gy, gz);
+        v.x += a.hdt_m * gx;
+        v.y += a.hdt_m * gy;
+        v.z += a.hdt_m * gz;
+    }
+    if (BIN) {
+        int c_next = -1;
+        if (own) c_next = half_kick_drift(a, p_next, v, gx, gy, gz);
+        bin_atom(a, p_next, v, c_next);  // all lanes
+    } else if (own) {
+        const float4 pref = a.posref[ia];
+        half_kick_drift_unwrapped(a, p_next, v, gx, gy, gz);
+        a.pos2[ia] = p_next;
+        a.vel2[ia] = v;
+        const float ex = p_next.x - pref.x, ey = p_next.y - pref.y, ez = p_next.z - pref.z;
+        if (ex * ex + ey * ey + ez * ez > a.disp_half * a.disp_half) atomicOr(&a.hdr[HDR_ERROR], DEV_SKIN);
+    }
+    if (bad) atomicOr(&a.hdr[HDR_ERROR], DEV_NONFINITE);
 }
 
 // Batched forces: one workgroup per listed cell (global cell indices of the
@@ -635,6 +818,31 @@ hipError_t launch_forces_list(const SimArgs& a_in, bool energy, bool record, boo
         }
     }
 #undef MD_LIST
+    return hipGetLastError();
+}
+
+hipError_t launch_forces_record(const SimArgs& a_in, bool energy, bool bin, int par, hipStream_t st) {
+    SimArgs a = a_in;
+    a.par = par;
+    const dim3 g(a.ncells), b(kWave);
+    const size_t entries = static_cast<size_t>(a.tile_cap + kTilePad);
+    const size_t lds = sizeof(float4) * entries + sizeof(uint32_t) * entries;
+    if (energy) {
+        if (bin) hipLaunchKernelGGL((k_forces_record<true, true>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((k_forces_record<true, false>), g, b, lds, st, a);
+    } else {
+        if (bin) hipLaunchKernelGGL((k_forces_record<false, true>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((k_forces_record<false, false>), g, b, lds, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_nlist_forces(const SimArgs& a_in, bool bin, int par, hipStream_t st) {
+    SimArgs a = a_in;
+    a.par = par;
+    const dim3 g((a.n + kListAtoms - 1) / kListAtoms), b(kListBlock);
+    if (bin) hipLaunchKernelGGL(k_nlist_forces<true>, g, b, 0, st, a);
+    else hipLaunchKernelGGL(k_nlist_forces<false>, g, b, 0, st, a);
     return hipGetLastError();
 }
 

@@ -55,8 +55,11 @@ md_status validate(const md_params* p) {
     if (!(std::isfinite(p->dt) && p->dt >= 0.f)) return fail(MD_ERR_ARG, "dt must be finite and >= 0");
     if (!(std::isfinite(p->cell_min) && p->cell_min >= 0.f))
         return fail(MD_ERR_ARG, "cell_min must be finite and >= 0");
+    if (!(std::isfinite(p->list_radius) && p->list_radius >= 0.f))
+        return fail(MD_ERR_ARG, "list_radius must be finite and >= 0");
     if (p->shift_mode != 0 && p->shift_mode != 1) return fail(MD_ERR_ARG, "shift_mode must be 0 or 1");
-    if ((p->flags & ~MD_FLAG_PAIR_LISTS) != 0) return fail(MD_ERR_ARG, "flags hold unknown bits 0x%x", p->flags);
+    if ((p->flags & ~(MD_FLAG_PAIR_LISTS | MD_FLAG_ATOM_LISTS)) != 0)
+        return fail(MD_ERR_ARG, "flags hold unknown bits 0x%x", p->flags);
     if (p->waves_per_cell != 0 && p->waves_per_cell != 1 && p->waves_per_cell != 2 && p->waves_per_cell != 4)
         return fail(MD_ERR_ARG, "waves_per_cell must be 0, 1, 2 or 4 (got %d)", p->waves_per_cell);
     const float rc = cutoff(p);
@@ -107,6 +110,15 @@ void take_build_arrays(Layout& L, size_t n, size_t ncells, int cap, Take& take) 
     L.start = take(4 * (ncells + 1) + 16);
 }
 
+// Entries per atom of the neighbour lists: 1.5 x the mean number of atoms
+// within the list radius (the cell side) plus 32, in multiples of 32.
+int atom_list_capacity(int n, float box, float side) {
+    const double rho = static_cast<double>(n) / (static_cast<double>(box) * box * box);
+    const double mean = rho * (4.0 / 3.0) * 3.14159265358979 * static_cast<double>(side) * side * side;
+    const int cap = static_cast<int>(std::ceil((1.5 * mean + 32.0) / 32.0)) * 32;
+    return std::min(std::max(cap, 64), 4096);
+}
+
 md_status make_layout(const md_params* p, Layout& L) {
     md_status s = validate(p);
     if (s != MD_OK) return s;
@@ -118,6 +130,8 @@ md_status make_layout(const md_params* p, Layout& L) {
     L.nforce_blocks = L.ncells;
     L.s = p->box / nc;
     L.inv_s = nc / p->box;
+    if (p->list_radius != 0.f && !(p->list_radius > cutoff(p) && p->list_radius <= L.s))
+        return fail(MD_ERR_ARG, "list_radius %g outside (r_c, cell side] = (%g, %g]", p->list_radius, cutoff(p), L.s);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t o = off;
@@ -133,10 +147,15 @@ md_status make_layout(const md_params* p, Layout& L) {
     L.force = take(16 * n);
     L.pos2 = take(16 * n);
     L.vel2 = take(16 * n);
+    if (p->flags & (MD_FLAG_PAIR_LISTS | MD_FLAG_ATOM_LISTS)) L.posref = take(16 * n);
     if (p->flags & MD_FLAG_PAIR_LISTS) {  // md_step_list's arrays, only where asked for
-        L.posref = take(16 * n);
         L.plist = take(16 * static_cast<size_t>(L.ncells) * kWaveLanes * kListSpans);
         L.plist_n = take(4 * static_cast<size_t>(L.ncells) * kWaveLanes);
+    }
+    if (p->flags & MD_FLAG_ATOM_LISTS) {  // md_step_nlist's arrays
+        L.nlist_cap = atom_list_capacity(p->n, p->box, p->list_radius > 0.f ? p->list_radius : L.s);
+        L.nlist = take(4 * n * static_cast<size_t>(L.nlist_cap));
+        L.ncount = take(4 * n);
     }
     take_build_arrays(L, n, static_cast<size_t>(L.ncells), bucket_capacity(static_cast<double>(p->n) / L.ncells),
                       take);
@@ -188,6 +207,9 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     a.posref = L.posref ? reinterpret_cast<float4*>(b + L.posref) : nullptr;
     a.plist = L.plist ? reinterpret_cast<uint32_t*>(b + L.plist) : nullptr;
     a.plist_n = L.plist_n ? reinterpret_cast<int*>(b + L.plist_n) : nullptr;
+    a.nlist = L.nlist ? reinterpret_cast<uint32_t*>(b + L.nlist) : nullptr;
+    a.ncount = L.ncount ? reinterpret_cast<int*>(b + L.ncount) : nullptr;
+    a.nlist_cap = L.nlist_cap;
     a.counts = reinterpret_cast<int*>(b + L.counts);
     a.bstart = reinterpret_cast<int*>(b + L.bstart);
     a.bpos = reinterpret_cast<float4*>(b + L.bpos);
@@ -234,8 +256,11 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     a.skin_half = static_cast<float>(std::max(0.0, 0.5 * (static_cast<double>(L.s) - rc) * (1.0 - std::ldexp(1.0, -20))));
     // pair lists: candidates within the cell side when the words are kept;
     // valid while no atom has moved by half the side's margin over r_c
-    a.list_screen2 = screen_bound(static_cast<double>(L.s), L.s);
-    a.disp_half = a.skin_half;
+    // pair and neighbour lists: candidates within r_V when recorded; valid
+    // while no atom has moved by half of r_V - r_c (less a relative 2^-20)
+    const double rv = p->list_radius > 0.f ? static_cast<double>(p->list_radius) : static_cast<double>(L.s);
+    a.list_screen2 = screen_bound(rv, L.s);
+    a.disp_half = static_cast<float>(std::max(0.0, 0.5 * (rv - rc) * (1.0 - std::ldexp(1.0, -20))));
     a.tile_cap = tile_capacity(p->n, L.ncells);
     a.waves = waves_per_cell(p);
     a.dt = p->dt;
@@ -668,6 +693,66 @@ md_status md_step_list(const md_params* p, void* ws, size_t ws_bytes, int32_t ns
             MD_TRY_HIP(launch_forces(cur, true, energy, true, true, false, (b + 1) & 1, stream), "forces");
         } else {
             MD_TRY_HIP(launch_forces_list(cur, energy, rebuild_now, rebuild_next, (b + 1) & 1, stream), "forces");
+            if (!rebuild_next) live_alt = !live_alt;
+        }
+        if (energy)
+            MD_TRY_HIP(launch_energy_final(a, thermo + 3 * static_cast<size_t>(k / thermo_every - 1), stream),
+                       "energy");
+    }
+    if (nsteps > 0) MD_TRY_HIP(launch_zero_blocks(a, b & 1, stream), "counter clear");
+    return MD_OK;
+}
+
+md_status md_step_nlist(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps, int32_t rebuild_every,
+                        int32_t thermo_every, double* thermo, hipStream_t stream) {
+    Layout L{};
+    md_status s = make_layout(p, L);
+    if (s != MD_OK) return s;
+    if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
+    if (nsteps < 0) return fail(MD_ERR_ARG, "nsteps must be >= 0");
+    if (rebuild_every < 1) return fail(MD_ERR_ARG, "rebuild_every must be >= 1");
+    if (thermo_every < 0) return fail(MD_ERR_ARG, "thermo_every must be >= 0");
+    if (thermo_every > 0 && !thermo) return fail(MD_ERR_ARG, "thermo_every > 0 needs a thermo buffer");
+    if (!(p->flags & MD_FLAG_ATOM_LISTS))
+        return fail(MD_ERR_ARG, "md_step_nlist needs a workspace laid out with MD_FLAG_ATOM_LISTS");
+    const SimArgs a = make_args(p, L, ws);
+    SimArgs alt = a;
+    std::swap(alt.pos0, alt.pos2);
+    std::swap(alt.vel0, alt.vel2);
+    // The schedule of md_step_every; the force pass right after a rebuild
+    // writes the neighbour lists, the others walk them (thermo steps screen).
+    int b = 0;
+    bool live_alt = false;
+    bool lists = false;  // lists written since the last rebuild
+    for (int32_t k = 1; k <= nsteps; ++k) {
+        const bool energy = thermo && thermo_every > 0 && (k % thermo_every) == 0;
+        const bool last = k == nsteps;
+        const bool rebuild_now = k == 1 || last || (k - 1) % rebuild_every == 0;
+        const bool rebuild_next = !last && (k + 1 == nsteps || k % rebuild_every == 0);
+        if (k == 1) MD_TRY_HIP(launch_integrate(a, stream), "integrate");
+        if (rebuild_now) {
+            if (k > 1) ++b;
+            if ((s = rebuild(a, b & 1, true, stream)) != MD_OK) return s;
+            live_alt = false;
+            lists = false;
+        }
+        const SimArgs& cur = live_alt ? alt : a;
+        const int par = (b + 1) & 1;
+        if (last) {
+            MD_TRY_HIP(launch_forces(cur, true, energy, true, true, false, par, stream), "forces");
+        } else if (rebuild_now) {
+            MD_TRY_HIP(launch_forces_record(cur, energy, rebuild_next, par, stream), "forces");
+            lists = true;
+            if (!rebuild_next) live_alt = !live_alt;
+        } else if (energy || !lists) {
+            if (rebuild_next) {
+                MD_TRY_HIP(launch_forces(cur, true, energy, false, true, true, par, stream), "forces");
+            } else {
+                MD_TRY_HIP(launch_forces_skin(cur, energy, stream), "forces");
+                live_alt = !live_alt;
+            }
+        } else {
+            MD_TRY_HIP(launch_nlist_forces(cur, rebuild_next, par, stream), "forces");
             if (!rebuild_next) live_alt = !live_alt;
         }
         if (energy)

@@ -30,6 +30,8 @@ constexpr int kDirectBlocks = 2048;
 // covers 128 candidates of a lane; a liquid-density neighbourhood of about
 // 400 atoms needs one span with four slices, two with two or three).
 constexpr int kListSpans = 4;  // kept accept-word spans (16 bytes each) per lane of a cell
+constexpr int kSlotBits = 27;  // neighbour-list entry: sorted slot, then the image shift code
+constexpr uint32_t kSlotMask = (1u << kSlotBits) - 1u;
 
 // Device error bits (same values as the public MD_DEV_* macros).
 enum : int { DEV_NONFINITE = 1, DEV_ORDER = 2, DEV_NB_OVERFLOW = 4, DEV_SKIN = 8 };
@@ -55,6 +57,16 @@ struct SimArgs {
     uint32_t* plist;
     int* plist_n;
     float4* posref;
+    // Per-atom neighbour lists (md_step_nlist): atom slot i's partners within
+    // the list radius are its first ncount[i] entries; entry k of atom i is
+    // nlist[4 (n (k / 4) + i) + k % 4] (groups of four entries, atoms
+    // consecutive within a group), each the partner's sorted slot (low
+    // kSlotBits bits) and its periodic image (shift code (sx + 1) +
+    // 3 (sy + 1) + 9 (sz + 1) in the high bits; the partner is taken at
+    // x_j + s L).
+    uint32_t* nlist;
+    int* ncount;
+    int nlist_cap;
     float list_screen2;  // screen bound when the words are kept (cell side^2 plus the screen margin)
     float disp_half;     // largest displacement since recording: (side - r_c) / 2
     // Cell build: per-cell histogram, zero between builds; a binned atom's
@@ -118,7 +130,9 @@ struct Layout {
     float s, inv_s;
     int nblocks, cap;
     int nbstride;
-    size_t hdr, pos0, vel0, pos1, vel1, force, pos2, vel2, posref, plist, plist_n, counts, bstart, bcounts, bpos, bvel,
+    int nlist_cap;
+    size_t hdr, pos0, vel0, pos1, vel1, force, pos2, vel2, posref, plist, plist_n, nlist, ncount, counts, bstart, bcounts,
+        bpos, bvel,
         ovf_cell, ovf_rank, ovf_idx, start, epart, total;
 };
 
@@ -138,6 +152,11 @@ hipError_t launch_forces(const SimArgs& a, bool kick, bool energy, bool write_fo
 hipError_t launch_forces_skin(const SimArgs& a, bool energy, hipStream_t st);
 // Pair-list steps (md_step_list): record (right after a rebuild) or use the
 // lists; the drift bins for a rebuild (bin) or goes to pos2/vel2.
+// md_step_nlist: the force pass right after a rebuild, writing the per-atom
+// neighbour lists (one wavefront per cell, as the other cell passes), and the
+// pass that walks them (one lane per atom); BIN as for launch_forces_list.
+hipError_t launch_forces_record(const SimArgs& a, bool energy, bool bin, int par, hipStream_t st);
+hipError_t launch_nlist_forces(const SimArgs& a, bool bin, int par, hipStream_t st);
 hipError_t launch_forces_list(const SimArgs& a, bool energy, bool record, bool bin, int par, hipStream_t st);
 hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st);
 // out[0] = kcoef K + wcoef W from the partials of an energy pass.

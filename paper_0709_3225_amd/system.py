@@ -23,10 +23,11 @@ class LJSystem:
     """Cubic periodic LJ system of n particles in a box of side ``box``."""
 
     def __init__(self, n, box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_over_sigma=2.5, dt=0.005,
-                 cell_min=0.0, shift_mode=0, pair_lists=False, waves_per_cell=0, device="cuda"):
-        flags = L.MD_FLAG_PAIR_LISTS if pair_lists else 0
+                 cell_min=0.0, shift_mode=0, pair_lists=False, atom_lists=False, waves_per_cell=0, list_radius=0.0,
+                 device="cuda"):
+        flags = (L.MD_FLAG_PAIR_LISTS if pair_lists else 0) | (L.MD_FLAG_ATOM_LISTS if atom_lists else 0)
         self.params = L.make_params(n, box, epsilon, sigma, mass, rc_over_sigma, dt, cell_min, shift_mode, flags,
-                                    waves_per_cell)
+                                    waves_per_cell, list_radius)
         self.cells_per_dim, self.cell_side = L.md_cell_grid(self.params)  # raises on invalid params
         self.nbytes = L.md_workspace_bytes(self.params)
         self.device = torch.device(device)
@@ -77,6 +78,15 @@ class LJSystem:
         if thermo_every > 0 and nsteps >= thermo_every:
             thermo = torch.empty((nsteps // thermo_every, 3), dtype=torch.float64, device=self.device)
         L.md_step_list(self.params, self.ws, nsteps, rebuild_every, thermo_every if thermo is not None else 0, thermo)
+        return thermo
+
+    def step_nlist(self, nsteps: int, rebuild_every: int, thermo_every: int = 0):
+        """md_step_nlist: as step_every, with per-atom neighbour lists written
+        at each rebuild and walked in between (needs ``atom_lists=True``)."""
+        thermo = None
+        if thermo_every > 0 and nsteps >= thermo_every:
+            thermo = torch.empty((nsteps // thermo_every, 3), dtype=torch.float64, device=self.device)
+        L.md_step_nlist(self.params, self.ws, nsteps, rebuild_every, thermo_every if thermo is not None else 0, thermo)
         return thermo
 
     def energy(self) -> torch.Tensor:

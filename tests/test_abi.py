@@ -74,10 +74,14 @@ def test_cell_min_parameter():
     (dict(mass=float("inf")), _lib.MD_ERR_ARG),
     (dict(dt=-0.1), _lib.MD_ERR_ARG),
     (dict(shift_mode=2), _lib.MD_ERR_ARG),
-    (dict(flags=2), _lib.MD_ERR_ARG),
+    (dict(flags=4), _lib.MD_ERR_ARG),
     (dict(waves_per_cell=3), _lib.MD_ERR_ARG),
     (dict(waves_per_cell=-1), _lib.MD_ERR_ARG),
     (dict(waves_per_cell=8), _lib.MD_ERR_ARG),
+    (dict(list_radius=-1.0), _lib.MD_ERR_ARG),
+    (dict(list_radius=float("nan")), _lib.MD_ERR_ARG),
+    (dict(list_radius=2.4), _lib.MD_ERR_ARG),  # not above r_c = 2.5
+    (dict(list_radius=3.5), _lib.MD_ERR_ARG),  # beyond the cell side 10 / 3
     (dict(rc_over_sigma=float("nan")), _lib.MD_ERR_ARG),
 ])
 def test_invalid_params_rejected_on_host(kw, code):
@@ -145,6 +149,28 @@ def test_pair_list_arrays_only_on_request():
     fake = ctypes.c_void_p(1 << 40)
     assert lib.md_step_list(ctypes.byref(plain), fake, b0, 4, 2, 0, None, None) == _lib.MD_ERR_ARG
     assert b"MD_FLAG_PAIR_LISTS" in lib.md_last_error()
+
+
+def test_atom_list_arrays_only_on_request():
+    """md_step_nlist's per-atom lists are laid out only with
+    MD_FLAG_ATOM_LISTS (4 B per entry: 1.5 x the mean number of atoms within
+    the cell side, plus 32, in multiples of 32; 128 entries at rho = 0.8442
+    on the 26^3 grid), and md_step_nlist refuses a workspace without them."""
+    import ctypes
+
+    lib = _lib.lib()
+    plain = md.make_params(256000, 67.18385)
+    lists = md.make_params(256000, 67.18385, flags=_lib.MD_FLAG_ATOM_LISTS)
+    both = md.make_params(256000, 67.18385, flags=_lib.MD_FLAG_ATOM_LISTS | _lib.MD_FLAG_PAIR_LISTS)
+    b0, b1, b2 = md.md_workspace_bytes(plain), md.md_workspace_bytes(lists), md.md_workspace_bytes(both)
+    extra = b1 - b0
+    # lists (128 entries) + counts + reference positions, each array 256-byte aligned
+    assert 256000 * (128 * 4 + 4 + 16) <= extra <= 256000 * (128 * 4 + 4 + 16) + 1024
+    assert b2 > b1 > b0
+    fake = ctypes.c_void_p(1 << 40)
+    assert lib.md_step_nlist(ctypes.byref(plain), fake, b0, 4, 2, 0, None, None) == _lib.MD_ERR_ARG
+    assert b"MD_FLAG_ATOM_LISTS" in lib.md_last_error()
+    assert lib.md_step_nlist(ctypes.byref(lists), fake, b1, 4, 0, 0, None, None) == _lib.MD_ERR_ARG  # rebuild_every
 
 
 def test_status_names():

@@ -223,17 +223,18 @@ def test_step_every_flags_a_thin_skin():
 
 # ---- pair lists (md_step_list): the screen's candidates cached between rebuilds
 
-def _run_modes(pos4, vel4, box, n, cell_min, nsteps, every, modes, dt=0.005):
+def _run_modes(pos4, vel4, box, n, cell_min, nsteps, every, modes, dt=0.005, thermo_every=1):
     from paper_0709_3225_amd import LJSystem
 
     out = {}
     for mode in modes:
         # the pair-list passes take one wavefront per cell; so does the
         # screening run they are compared with
-        s = LJSystem(n, box, dt=dt, cell_min=cell_min, pair_lists=(mode == "list"), waves_per_cell=1)
+        s = LJSystem(n, box, dt=dt, cell_min=cell_min, pair_lists=(mode == "list"), atom_lists=(mode == "nlist"),
+                     waves_per_cell=1)
         s.load(_dev(pos4), None if vel4 is None else _dev(vel4))
-        run = {"every": s.step_every, "list": s.step_list}[mode]
-        th = run(nsteps, every, thermo_every=1)
+        run = {"every": s.step_every, "list": s.step_list, "nlist": s.step_nlist}[mode]
+        th = run(nsteps, every, thermo_every=thermo_every)
         flags = s.check(raise_on_error=False)
         p, v = s.state()
         out[mode] = (th.cpu().numpy(), p.cpu().numpy(), v.cpu().numpy(), s.forces().cpu().numpy(), flags)
@@ -307,3 +308,107 @@ def test_step_list_flags_displacement():
     _say("md_step_list thin skin lj4k 40 steps")
     out = _run_modes(pos4, vel4, box, w.n, 0.0, 40, 1000, ("list",))
     assert out["list"][4] == 8
+
+
+# ---- per-atom Verlet neighbour lists (md_step_nlist)
+
+@pytest.mark.parametrize("cell_min,every", [(0.0, 3), (2.9, 5), (2.9, 10)])
+def test_step_nlist_tracks_oracle_and_step_every(orc, cell_min, every):
+    """Neighbour lists written at each rebuild and walked by one lane per atom
+    in between (section 3's Verlet list: partners within the cell side, valid
+    while no atom has moved by half the margin over r_c): 40 steps of the
+    jittered lj4k fluid, thermo every 4 steps (a thermo step between rebuilds
+    screens the cells instead). Energies within 1e-5 of the oracle's
+    integrator over the first 20 steps and of md_step_every (the same
+    schedule, other summation order) over all 40; positions within 1e-3 of
+    md_step_every's; no displacement or overflow flag; the final state
+    (rebuilt and wrapped) has the oracle's forces."""
+    w = ljsynth.WORKLOADS["lj4k"]
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05)
+    _say(f"md_step_nlist vs md_step_every and oracle lj4k cell_min={cell_min} e={every} 40 steps")
+    out = _run_modes(pos4, vel4, box, w.n, cell_min, 40, every, ("every", "nlist"), thermo_every=4)
+    te, pe = out["every"][0], out["every"][1]
+    tn, pn, _, fn, flags = out["nlist"]
+    assert flags == 0
+    _, _, tho = orc.run(orc.params(box, dt=w.dt), pos4, vel4, 40)
+    eo = tho[4::4, 0] + tho[4::4, 1]
+    en = tn[:, 0] + tn[:, 1]
+    assert np.abs(en[:5] - eo[:5]).max() / abs(eo[0]) < 1e-5
+    assert np.abs(en - (te[:, 0] + te[:, 1])).max() / abs(eo[0]) < 1e-5
+    d = pn[:, :3] - pe[:, :3]
+    d -= box * np.round(d / box)
+    assert np.abs(d).max() < 1e-3
+    fo, U, W = orc.forces(orc.params(box), pn)
+    assert rel_l2(fn[:, :3].astype(np.float64), fo) <= FORCE_TOL
+
+
+def test_step_nlist_full_size():
+    """N = 256,000 on the 24^3 grid (0.30 sigma margin; the jittered start
+    moves some atoms by more than half the default grid's 0.084 sigma within
+    three steps), rebuilds every 3 steps, 12 steps with thermo every 4:
+    energies within 1e-6 of md_step_every's, positions within 1e-4, no
+    flag."""
+    w = ljsynth.WORKLOADS["lj256k"]
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05)
+    _say("md_step_nlist vs md_step_every lj256k cell_min=2.7 e=3 12 steps")
+    out = _run_modes(pos4, vel4, box, w.n, 2.7, 12, 3, ("every", "nlist"), thermo_every=4)
+    te, pe = out["every"][0], out["every"][1]
+    tn, pn, _, _, flags = out["nlist"]
+    assert flags == 0
+    e_e = te[:, 0] + te[:, 1]
+    assert np.abs(tn[:, 0] + tn[:, 1] - e_e).max() / abs(e_e[0]) < 1e-6
+    d = pn[:, :3] - pe[:, :3]
+    d -= box * np.round(d / box)
+    assert np.abs(d).max() < 1e-4
+
+
+def test_step_nlist_flags_list_overflow():
+    """The dense block (local density 6.7, lists sized for the box's mean of
+    0.77): atoms with more partners than their list holds raise
+    MD_DEV_NB_OVERFLOW, and the run still ends on a finite state."""
+    g = np.arange(0.3, 5.9, 0.53)
+    pts = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    pts = pts + np.random.default_rng(9).uniform(-0.002, 0.002, pts.shape)
+    clump = np.zeros((len(pts), 4), np.float32)
+    clump[:, :3] = pts
+    _say(f"md_step_nlist dense block n={len(clump)} e=3 6 steps")
+    out = _run_modes(clump, None, 12.0, len(clump), 0.0, 6, 3, ("nlist",), dt=1e-5, thermo_every=2)
+    tn, pn, vn, _, flags = out["nlist"]
+    assert flags & 4
+    assert np.isfinite(pn).all() and np.isfinite(vn).all()
+
+
+@pytest.mark.parametrize("lists", ["nlist", "list"])
+def test_short_list_radius_wca_tracks_oracle(orc, lists):
+    """WCA on occupancy-sized cells (about 14 atoms, side 2.3 sigma for a
+    cutoff of 1.12 sigma) with lists of radius r_c + 0.3 sigma, far inside
+    the cell: the lists hold about 10 partners per atom instead of the 27
+    cells' 380 candidates. 60 steps, rebuilds every 5 (the fastest atoms of
+    the repulsive fluid cover the 0.15 sigma half skin in about 9 steps),
+    thermo every 5:
+    energies within 1e-5 of the oracle's integrator over the first 20 steps,
+    no displacement or overflow flag, final forces (rebuilt state) within
+    1e-5 of the oracle's."""
+    from paper_0709_3225_amd import LJSystem, occupancy_cell_min
+
+    w = ljsynth.wca_workload(n_fcc=10)
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05)
+    rc = w.rc_over_sigma
+    cm = occupancy_cell_min(w.n, box, rc)
+    rv = rc + 0.3
+    _say(f"wca {lists} list radius {rv:.3f} cell_min {cm:.3f} n={w.n} 60 steps e=5")
+    s = LJSystem(w.n, box, rc_over_sigma=rc, shift_mode=1, dt=w.dt, cell_min=cm, list_radius=rv,
+                 pair_lists=(lists == "list"), atom_lists=(lists == "nlist"), waves_per_cell=1)
+    assert s.cell_side > rv + 0.5
+    s.load(_dev(pos4), _dev(vel4))
+    run = s.step_nlist if lists == "nlist" else s.step_list
+    th = run(60, 5, thermo_every=5).cpu().numpy()
+    assert s.check(raise_on_error=False) == 0
+    _, _, tho = orc.run(orc.params(box, rc=rc, dt=w.dt, shift_mode=1), pos4, vel4, 60)
+    eo = tho[5::5, 0] + tho[5::5, 1]
+    en = th[:, 0] + th[:, 1]
+    assert np.abs(en[:4] - eo[:4]).max() / abs(eo[0]) < 1e-5
+    p, _ = s.state()
+    pc = p.cpu().numpy()
+    fo, _, _ = orc.forces(orc.params(box, rc=rc, shift_mode=1), pc)
+    assert rel_l2(s.forces().cpu().numpy()[:, :3].astype(np.float64), fo) <= FORCE_TOL
