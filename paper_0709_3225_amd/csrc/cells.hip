@@ -296,19 +296,20 @@ __global__ void __launch_bounds__(kOrderBlock) k_cell_order(SimArgs a, bool from
     const int blk = xcd_block_order(blockIdx.x, gridDim.x);
     const int c0 = blk * kOrderCells, c = c0 + cl;
     const int nct = a.ncells;
-    // Everything the first window needs is requested at once: the first 32
-    // bucket entries of the cell (the capacity is at least 32; entries past
-    // the count are never used), its count, and the block offset (or the
-    // block counts before this block).
-    float4 pa0 = make_float4(0.f, 0.f, 0.f, 0.f), va0 = pa0, pb0 = pa0, vb0 = pa0;
-    if (c < nct) {
-        const size_t e = static_cast<size_t>(c) * a.cap + sub;
-        pa0 = a.bpos[e];
-        va0 = a.bvel[e];
-        pb0 = a.bpos[e + kOrderGroup];
-        vb0 = a.bvel[e + kOrderGroup];
-    }
+    // What the first window needs is requested before anything waits: the
+    // cell's count, its first 16 bucket entries (a cell of the headline
+    // density holds about 15 atoms; entries past the count are never used),
+    // and the block offset (or the block counts before this block). Entries
+    // 16..31 are loaded once the count shows that they exist, while the block
+    // counts are still in flight: loading them unconditionally read twice the
+    // bucket bytes the cells hold.
     const int n = c < nct ? a.counts[c] : 0;
+    float4 pa0 = make_float4(0.f, 0.f, 0.f, 0.f), va0 = pa0, pb0 = pa0, vb0 = pa0;
+    const size_t e0 = static_cast<size_t>(c) * a.cap + sub;
+    if (c < nct) {
+        pa0 = a.bpos[e0];
+        va0 = a.bvel[e0];
+    }
     int part = 0;
     if (a.direct) {
         // all loads in flight at once (a loop bounded by blockIdx.x waited for
@@ -321,8 +322,15 @@ __global__ void __launch_bounds__(kOrderBlock) k_cell_order(SimArgs a, bool from
             const int j = tid + u * kOrderBlock;
             v[u] = j < blk ? bc[j] : 0;
         }
+        if (sub + kOrderGroup < n) {  // c < nct whenever n > 0
+            pb0 = a.bpos[e0 + kOrderGroup];
+            vb0 = a.bvel[e0 + kOrderGroup];
+        }
 #pragma unroll
         for (int u = 0; u < kDirectBlocks / kOrderBlock; ++u) part += v[u];
+    } else if (sub + kOrderGroup < n) {
+        pb0 = a.bpos[e0 + kOrderGroup];
+        vb0 = a.bvel[e0 + kOrderGroup];
     }
     const int bs = a.direct ? 0 : a.bstart[blk];
     const int novf = min(a.hdr[HDR_OVF + a.par], a.natoms);
