@@ -123,22 +123,33 @@ def batched_leg(torch, nsteps=200, seq_steps=20):
     }
 
 
+def _timed_gradient(torch, x, v, box, nsteps, **kw):
+    from paper_0709_3225_amd import trajectory_gradients
+
+    trajectory_gradients(x, v, box, nsteps=20, every=20, **kw)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = trajectory_gradients(x, v, box, nsteps=nsteps, every=20, **kw)
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
 def adjoint_leg(torch):
     """Forward + backward of L = K_T/N + W_T/(3V) through 200 Verlet steps at
-    N = 32000 (checkpoints every 20 steps), against plain md_step at the same
-    size. Both in atom-steps/s (N x 200 / time)."""
+    N = 32000 (checkpoints every 20 steps, each segment recomputed on a second
+    stream while the one after it is swept), against plain md_step at the same
+    size. Both in atom-steps/s (N x 200 / time). Also: the same checkpointed
+    gradient on one stream, and with every state kept in the forward (no
+    recomputation)."""
     import ljsynth
-    from paper_0709_3225_amd import LJSystem, trajectory_gradients
+    from paper_0709_3225_amd import LJSystem
 
     w = ljsynth.WORKLOADS["lj32k_adjoint"]
     pos4, vel4, box = ljsynth.make_state(w)
     x, v = torch.from_numpy(pos4).cuda(), torch.from_numpy(vel4).cuda()
-    trajectory_gradients(x, v, box, nsteps=20, every=20)  # warm
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    loss, gr, gv, ge, gs = trajectory_gradients(x, v, box, nsteps=w.steps, every=20)
-    torch.cuda.synchronize()
-    t_adj = time.perf_counter() - t0
+    (loss, gr, gv, ge, gs), t_adj = _timed_gradient(torch, x, v, box, w.steps)
+    _, t_seq = _timed_gradient(torch, x, v, box, w.steps, overlap=False)
+    _, t_kept = _timed_gradient(torch, x, v, box, w.steps, keep_path=True)
     s = LJSystem(w.n, box, dt=w.dt)
     s.load(x, v)
     s.step(20)
@@ -148,26 +159,29 @@ def adjoint_leg(torch):
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     s.check()
-    adj = w.n * w.steps / t_adj
-    plain = w.n * w.steps / t_plain
+    work = w.n * w.steps
+    plain = work / t_plain
     hvp = hvp_roofline(s, torch)
     # the same gradient at the headline size (N = 256,000), where the grid
     # fills the chip: context for how the ratio depends on the size
     wl = ljsynth.WORKLOADS["lj256k"]
     pos4, vel4, boxl = ljsynth.make_state(wl)
     xl, vl = torch.from_numpy(pos4).cuda(), torch.from_numpy(vel4).cuda()
-    trajectory_gradients(xl, vl, boxl, nsteps=20, every=20)  # warm
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    trajectory_gradients(xl, vl, boxl, nsteps=w.steps, every=20)
-    torch.cuda.synchronize()
-    adj_l = wl.n * w.steps / (time.perf_counter() - t0)
+    _, t_l = _timed_gradient(torch, xl, vl, boxl, w.steps)
+    _, t_l_seq = _timed_gradient(torch, xl, vl, boxl, w.steps, overlap=False)
+    _, t_l_kept = _timed_gradient(torch, xl, vl, boxl, w.steps, keep_path=True)
+    work_l = wl.n * w.steps
     return {
         "workload": f"{w.name}: N={w.n}, rho={w.density}, T*={w.temperature}, {w.steps} steps, checkpoints every 20, "
                     "loss K_T/N + W_T/(3V), gradients w.r.t. r0, v0, eps, sigma",
-        "value": adj, "unit": "atom-steps/s (forward + backward)", "plain_value": plain,
-        "ratio_vs_plain": adj / plain, "loss": loss, "dL_deps": ge, "dL_dsigma": gs,
-        "value_at_256k": adj_l,
+        "value": work / t_adj, "unit": "atom-steps/s (forward + backward)", "plain_value": plain,
+        "ratio_vs_plain": work / t_adj / plain, "loss": loss, "dL_deps": ge, "dL_dsigma": gs,
+        "one_stream": {"value": work / t_seq, "ratio_vs_plain": work / t_seq / plain},
+        "kept_path": {"value": work / t_kept, "ratio_vs_plain": work / t_kept / plain,
+                      "path_bytes": w.steps * (16 * w.n + 4 * (s.cells_per_dim ** 3 + 1))},
+        "value_at_256k": work_l / t_l,
+        "at_256k_one_stream": work_l / t_l_seq,
+        "at_256k_kept_path": work_l / t_l_kept,
         "hvp_roofline": hvp,
         "hvp_roofline_at_256k": hvp_roofline(_loaded(torch, wl), torch),
     }

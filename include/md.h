@@ -335,6 +335,46 @@ md_status md_adjoint_segment(const md_params* p, void* ws, size_t ws_bytes, cons
                              float* lam_v4_dev, double* theta_dev, hipStream_t stream);
 
 /*
+ * The two halves of md_adjoint_segment, for callers that overlap them or
+ * keep the whole trajectory. A path of nsteps states is path4_dev
+ * (nsteps * n float4: state j's cell-sorted positions, w = user index bits)
+ * and path_start_dev (nsteps * (n_c^3 + 1) int32: its cell offsets), both
+ * caller-owned.
+ *
+ * md_adjoint_recompute: from the checkpoint (ckpt_pos4_dev, ckpt_vel4_dev),
+ * the checkpoint and the states after its first nsteps - 1 steps into the
+ * path, bitwise those md_step produces. The workspace serves as scratch and
+ * is left without a built state (as md_adjoint_segment leaves it).
+ *
+ * md_adjoint_path: the backward sweep of md_adjoint_segment over a kept path
+ * whose state 0 is the state after step first_step: from state nsteps - 1 back
+ * to state 0, the drift adjoint and the kick adjoint on the state's cell list
+ * (coefficient 2h, or h for the trajectory's step 0); lam_r4_dev, lam_v4_dev
+ * and theta_dev accumulate as for md_adjoint_segment. The workspace must hold
+ * a built state of these parameters (md_build_cells, md_step, ...); it serves
+ * as scratch (its sorted arrays and forces are not touched) and keeps that
+ * state. Calls on different workspaces and paths may run concurrently on
+ * different streams. Force-shift mode only.
+ *
+ * md_step_path: nsteps steps of md_step (no thermo output, nsteps >= 1) that
+ * also keep the states before each step as a path: state 0 is the workspace's
+ * state at the call (copied), state j the state after j steps (sorted
+ * straight into its slice); the workspace ends as after md_step. Needs a
+ * state with forces, as md_step does. md_adjoint_path over this path and a
+ * range of it gives bitwise the results of md_adjoint_segment over the same
+ * range recomputed from a checkpoint (the recomputation is skipped at the
+ * cost of nsteps * (16 n + 4 (n_c^3 + 1)) bytes of device memory).
+ */
+md_status md_adjoint_recompute(const md_params* p, void* ws, size_t ws_bytes, const float* ckpt_pos4_dev,
+                               const float* ckpt_vel4_dev, int32_t nsteps, float* path4_dev,
+                               int32_t* path_start_dev, hipStream_t stream);
+md_status md_adjoint_path(const md_params* p, void* ws, size_t ws_bytes, int32_t first_step, int32_t nsteps,
+                          const float* path4_dev, const int32_t* path_start_dev, float* lam_r4_dev,
+                          float* lam_v4_dev, double* theta_dev, hipStream_t stream);
+md_status md_step_path(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps, float* path4_dev,
+                       int32_t* path_start_dev, hipStream_t stream);
+
+/*
  * Gradient of the loss k_coef * K + w_coef * W at the current workspace
  * state (K = m/2 sum v^2, W = sum over pairs r phi(r)):
  *   g_r4_dev = w_coef * dW/dr, g_v4_dev = k_coef * m * v (both written),

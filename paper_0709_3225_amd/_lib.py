@@ -47,6 +47,9 @@ SYMBOLS = (
     "md_adjoint_kick",
     "md_adjoint_drift",
     "md_adjoint_segment",
+    "md_adjoint_recompute",
+    "md_adjoint_path",
+    "md_step_path",
     "md_loss_grad",
     "md_loss",
     "md_adjoint_seed",
@@ -143,6 +146,9 @@ def lib():
         L.md_adjoint_drift.argtypes = [P, vp, vp, vp]
         L.md_loss_grad.argtypes = [P, vp, sz, ctypes.c_float, ctypes.c_float, vp, vp, vp, vp]
         L.md_adjoint_segment.argtypes = [P, vp, sz, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.md_adjoint_recompute.argtypes = [P, vp, sz, vp, vp, i32, vp, vp, vp]
+        L.md_adjoint_path.argtypes = [P, vp, sz, i32, i32, vp, vp, vp, vp, vp, vp]
+        L.md_step_path.argtypes = [P, vp, sz, i32, vp, vp, vp]
         L.md_loss.argtypes = [P, vp, sz, vp, vp]
         L.md_adjoint_seed.argtypes = [P, vp, sz, ctypes.c_float, vp, vp, vp, vp]
         R = ctypes.POINTER(MDReplica)
@@ -158,7 +164,8 @@ def lib():
         L.md_graph_destroy.argtypes = [vp]
         for name in ("md_cell_grid", "md_build_cells", "md_forces", "md_forces_noalloc", "md_step", "md_step_every", "md_step_list", "md_energy_virial",
                      "md_get_state", "md_neighbors", "md_neighbors_lists", "md_cell_lists", "md_check", "md_adjoint_kick",
-                     "md_adjoint_drift", "md_adjoint_segment", "md_loss_grad", "md_loss", "md_adjoint_seed",
+                     "md_adjoint_drift", "md_adjoint_segment", "md_adjoint_recompute",
+                     "md_adjoint_path", "md_step_path", "md_loss_grad", "md_loss", "md_adjoint_seed",
                      "md_batch_build", "md_batch_forces", "md_batch_step",
                      "md_batch_energy_virial", "md_batch_get_state", "md_batch_graph_create", "md_graph_launch",
                      "md_graph_destroy"):
@@ -401,6 +408,48 @@ def md_adjoint_segment(p: MDParams, ws, ckpt_pos4, ckpt_vel4, first_step: int, n
         _ptr(lam_r4, "lam_r4", torch.float32, (n, 4)),
         _ptr(lam_v4, "lam_v4", torch.float32, (n, 4)),
         None if theta is None else _ptr(theta, "theta", torch.float64), _stream(stream)))
+
+
+def _path_ptrs(p: MDParams, nsteps: int, path4, path_start):
+    import torch
+
+    nc, _ = md_cell_grid(p)
+    if path4.numel() < 4 * p.n * nsteps:
+        raise ValueError(f"path4 needs {nsteps} x {p.n} float4")
+    if path_start.numel() < nsteps * (nc ** 3 + 1):
+        raise ValueError(f"path_start needs {nsteps} x {nc ** 3 + 1} int32")
+    return _ptr(path4, "path4", torch.float32), _ptr(path_start, "path_start", torch.int32)
+
+
+def md_adjoint_recompute(p: MDParams, ws, ckpt_pos4, ckpt_vel4, nsteps: int, path4, path_start, stream=None):
+    """The states of a checkpoint segment into a path (md_adjoint_recompute)."""
+    import torch
+
+    wp, wn = _ws(ws)
+    pp, ps = _path_ptrs(p, nsteps, path4, path_start)
+    _check(lib().md_adjoint_recompute(
+        ctypes.byref(p), wp, wn, _ptr(ckpt_pos4, "ckpt_pos4", torch.float32, (p.n, 4)),
+        _ptr(ckpt_vel4, "ckpt_vel4", torch.float32, (p.n, 4)), int(nsteps), pp, ps, _stream(stream)))
+
+
+def md_adjoint_path(p: MDParams, ws, first_step: int, nsteps: int, path4, path_start, lam_r4, lam_v4, theta=None,
+                    stream=None):
+    """Drift and kick adjoints over a kept path, last state first (md_adjoint_path)."""
+    import torch
+
+    wp, wn = _ws(ws)
+    pp, ps = _path_ptrs(p, nsteps, path4, path_start)
+    _check(lib().md_adjoint_path(
+        ctypes.byref(p), wp, wn, int(first_step), int(nsteps), pp, ps,
+        _ptr(lam_r4, "lam_r4", torch.float32, (p.n, 4)), _ptr(lam_v4, "lam_v4", torch.float32, (p.n, 4)),
+        None if theta is None else _ptr(theta, "theta", torch.float64), _stream(stream)))
+
+
+def md_step_path(p: MDParams, ws, nsteps: int, path4, path_start, stream=None):
+    """nsteps of md_step, keeping the state before each step as a path (md_step_path)."""
+    wp, wn = _ws(ws)
+    pp, ps = _path_ptrs(p, nsteps, path4, path_start)
+    _check(lib().md_step_path(ctypes.byref(p), wp, wn, int(nsteps), pp, ps, _stream(stream)))
 
 
 def md_loss_grad(p: MDParams, ws, k_coef: float, w_coef: float, g_r4, g_v4, theta=None, stream=None):

@@ -357,6 +357,85 @@ md_status steps_impl(const SimArgs& a, int32_t nsteps, int32_t thermo_every, dou
     return MD_OK;
 }
 
+// ---- kept paths of the adjoint --------------------------------------------
+
+// Arguments whose sorted positions and cell offsets are path slice j: a
+// path holds nsteps states, slice j being n float4 and n_c^3 + 1 offsets.
+SimArgs path_slice(const SimArgs& a, float* path4, int32_t* path_start, int32_t j) {
+    SimArgs x = a;
+    x.pos0 = reinterpret_cast<float4*>(path4) + static_cast<size_t>(j) * static_cast<size_t>(a.n);
+    x.start = path_start + static_cast<size_t>(j) * (static_cast<size_t>(a.ncells) + 1);
+    return x;
+}
+
+md_status check_path_args(const md_params* p, int32_t first_step, int32_t nsteps, const float* path4,
+                          const int32_t* path_start, bool adjoint) {
+    if (adjoint && p->shift_mode != 0) return fail(MD_ERR_ARG, "the adjoint needs shift_mode 0 (force shift)");
+    if (nsteps < 1 || first_step < 0) return fail(MD_ERR_ARG, "need nsteps >= 1 and first_step >= 0");
+    if (!path4 || !path_start) return fail(MD_ERR_ARG, "path arrays are NULL");
+    if (!aligned16(path4)) return fail(MD_ERR_ARG, "path4 must be 16-byte aligned");
+    return MD_OK;
+}
+
+md_status check_ckpt(const float* pos4, const float* vel4) {
+    if (!pos4 || !vel4) return fail(MD_ERR_ARG, "checkpoint arrays are NULL");
+    if (!aligned16(pos4) || !aligned16(vel4)) return fail(MD_ERR_ARG, "checkpoint arrays must be 16-byte aligned");
+    return MD_OK;
+}
+
+md_status check_adjoint_vecs(const float* lam_r4, const float* lam_v4) {
+    if (!lam_r4 || !lam_v4) return fail(MD_ERR_ARG, "adjoint vectors are NULL");
+    if (!aligned16(lam_r4) || !aligned16(lam_v4)) return fail(MD_ERR_ARG, "adjoint vectors must be 16-byte aligned");
+    if (lam_r4 == lam_v4) return fail(MD_ERR_ARG, "lam_r and lam_v must not alias");
+    return MD_OK;
+}
+
+// From a checkpoint, the states of a segment into the path: the checkpoint's
+// cells (as md_build_cells), then the steps in md_step's fused order
+// (bitwise the states md_step produces). The last state needs no forces:
+// only its positions are used on the way back. The workspace's own sorted
+// arrays are not written.
+md_status recompute_impl(const SimArgs& a, const float* ckpt_pos4, const float* ckpt_vel4, int32_t nsteps,
+                         float* path4, int32_t* path_start, hipStream_t stream) {
+    const SimArgs a0 = path_slice(a, path4, path_start, 0);
+    MD_TRY_HIP(launch_build_init(a0, stream), "build init");
+    MD_TRY_HIP(launch_load(a0, reinterpret_cast<const float4*>(ckpt_pos4), reinterpret_cast<const float4*>(ckpt_vel4),
+                           stream),
+               "load");
+    md_status s = rebuild(a0, 0, false, stream);
+    if (s != MD_OK) return s;
+    MD_TRY_HIP(launch_zero_blocks(a0, 0, stream), "counter clear");
+    if (nsteps > 1) {
+        MD_TRY_HIP(launch_forces(a0, false, false, true, false, false, 0, stream), "forces");
+        MD_TRY_HIP(launch_integrate(a0, stream), "integrate");
+        for (int32_t k = 1; k < nsteps; ++k) {
+            const SimArgs ak = path_slice(a, path4, path_start, k);
+            if ((s = rebuild(ak, (k - 1) & 1, true, stream)) != MD_OK) return s;
+            if (k + 1 < nsteps) MD_TRY_HIP(launch_forces(ak, true, false, false, true, true, k & 1, stream), "forces");
+        }
+        MD_TRY_HIP(launch_zero_blocks(a, (nsteps - 2) & 1, stream), "counter clear");
+    }
+    return MD_OK;
+}
+
+// From the last state of a kept path back to its first: drift adjoint, then
+// the kick adjoint on state j's cell list, with coefficient 2h, or h for the
+// trajectory's step 0 (h = dt / 2m); the parameter terms are summed per cell
+// over the path and added to theta once. Uses the workspace as scratch only.
+md_status sweep_impl(const SimArgs& a, const md_params* p, int32_t first_step, int32_t nsteps, float* path4,
+                     int32_t* path_start, float* lam_r4, float* lam_v4, double* theta, hipStream_t stream) {
+    const float h = static_cast<float>(0.5 * p->dt / p->mass);
+    for (int32_t j = nsteps - 1; j >= 0; --j) {
+        const float coef = first_step + j >= 1 ? 2.0f * h : h;
+        MD_TRY_HIP(launch_adjoint_drift_kick(path_slice(a, path4, path_start, j), p->dt,
+                                             reinterpret_cast<float4*>(lam_r4), reinterpret_cast<float4*>(lam_v4), coef,
+                                             j < nsteps - 1, stream),
+                   "adjoint drift and kick");
+    }
+    if (theta) MD_TRY_HIP(launch_theta_final(a, theta, 1.0, stream), "parameter sums");
+    return MD_OK;
+}
+
 // ---- batches of independent replicas -------------------------------------
 
 // The batched force pass runs one launch per tile class: replicas whose
@@ -867,58 +946,73 @@ md_status md_adjoint_segment(const md_params* p, void* ws, size_t ws_bytes, cons
     md_status s = make_layout(p, L);
     if (s != MD_OK) return s;
     if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
-    if (p->shift_mode != 0) return fail(MD_ERR_ARG, "the adjoint needs shift_mode 0 (force shift)");
-    if (nsteps < 1 || first_step < 0) return fail(MD_ERR_ARG, "need nsteps >= 1 and first_step >= 0");
-    if (!ckpt_pos4 || !ckpt_vel4 || !path4 || !path_start || !lam_r4 || !lam_v4)
-        return fail(MD_ERR_ARG, "segment arrays are NULL");
-    if (!aligned16(ckpt_pos4) || !aligned16(ckpt_vel4) || !aligned16(path4) || !aligned16(lam_r4) ||
-        !aligned16(lam_v4))
-        return fail(MD_ERR_ARG, "segment arrays must be 16-byte aligned");
-    const size_t start_n = static_cast<size_t>(L.ncells) + 1;
-    const float h = static_cast<float>(0.5 * p->dt / p->mass);
-    // State j of the segment is cell-sorted straight into path slice j: the
-    // rebuild that produces it writes its sorted positions and cell offsets
-    // there, the force pass and the kick adjoint at r_j read them from there,
-    // so nothing is copied.
+    if ((s = check_path_args(p, first_step, nsteps, path4, path_start, true)) != MD_OK) return s;
+    if ((s = check_ckpt(ckpt_pos4, ckpt_vel4)) != MD_OK) return s;
+    if ((s = check_adjoint_vecs(lam_r4, lam_v4)) != MD_OK) return s;
     const SimArgs a = make_args(p, L, ws);
-    auto at = [&](int32_t j) {
-        SimArgs x = a;
-        x.pos0 = reinterpret_cast<float4*>(path4) + static_cast<size_t>(j) * static_cast<size_t>(p->n);
-        x.start = path_start + static_cast<size_t>(j) * start_n;
-        return x;
-    };
-    // Recompute: the checkpoint's cells (as md_build_cells), then the steps in
-    // md_step's fused order (bitwise the states md_step produces). The last
-    // state needs no forces: only its positions are used on the way back.
-    const SimArgs a0 = at(0);
-    MD_TRY_HIP(launch_build_init(a0, stream), "build init");
-    MD_TRY_HIP(launch_load(a0, reinterpret_cast<const float4*>(ckpt_pos4), reinterpret_cast<const float4*>(ckpt_vel4),
-                           stream),
-               "load");
-    if ((s = rebuild(a0, 0, false, stream)) != MD_OK) return s;
-    MD_TRY_HIP(launch_zero_blocks(a0, 0, stream), "counter clear");
-    if (nsteps > 1) {
-        MD_TRY_HIP(launch_forces(a0, false, false, true, false, false, 0, stream), "forces");
-        MD_TRY_HIP(launch_integrate(a0, stream), "integrate");
-        for (int32_t k = 1; k < nsteps; ++k) {
-            const SimArgs ak = at(k);
-            if ((s = rebuild(ak, (k - 1) & 1, true, stream)) != MD_OK) return s;
-            if (k + 1 < nsteps) MD_TRY_HIP(launch_forces(ak, true, false, false, true, true, k & 1, stream), "forces");
-        }
-        MD_TRY_HIP(launch_zero_blocks(a, (nsteps - 2) & 1, stream), "counter clear");
-    }
-    // from the last step of the segment back to its first: drift adjoint, then
-    // the kick adjoint on state j's kept cell list; the parameter terms are
-    // summed per cell over the segment and added to theta once
-    for (int32_t j = nsteps - 1; j >= 0; --j) {
-        const float coef = first_step + j >= 1 ? 2.0f * h : h;
-        MD_TRY_HIP(launch_adjoint_drift_kick(at(j), p->dt, reinterpret_cast<float4*>(lam_r4),
-                                             reinterpret_cast<float4*>(lam_v4), coef, j < nsteps - 1, stream),
-                   "adjoint drift and kick");
-    }
-    if (theta) MD_TRY_HIP(launch_theta_final(a, theta, 1.0, stream), "parameter sums");
+    if ((s = recompute_impl(a, ckpt_pos4, ckpt_vel4, nsteps, path4, path_start, stream)) != MD_OK) return s;
+    if ((s = sweep_impl(a, p, first_step, nsteps, path4, path_start, lam_r4, lam_v4, theta, stream)) != MD_OK) return s;
     // the workspace's own sorted arrays were not written: it holds no state now
     MD_TRY_HIP(launch_set_state(a, STATE_BUILDING, stream), "state reset");
+    return MD_OK;
+}
+
+md_status md_adjoint_recompute(const md_params* p, void* ws, size_t ws_bytes, const float* ckpt_pos4,
+                               const float* ckpt_vel4, int32_t nsteps, float* path4, int32_t* path_start,
+                               hipStream_t stream) {
+    Layout L{};
+    md_status s = make_layout(p, L);
+    if (s != MD_OK) return s;
+    if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
+    if ((s = check_path_args(p, 0, nsteps, path4, path_start, true)) != MD_OK) return s;
+    if ((s = check_ckpt(ckpt_pos4, ckpt_vel4)) != MD_OK) return s;
+    const SimArgs a = make_args(p, L, ws);
+    if ((s = recompute_impl(a, ckpt_pos4, ckpt_vel4, nsteps, path4, path_start, stream)) != MD_OK) return s;
+    MD_TRY_HIP(launch_set_state(a, STATE_BUILDING, stream), "state reset");
+    return MD_OK;
+}
+
+md_status md_adjoint_path(const md_params* p, void* ws, size_t ws_bytes, int32_t first_step, int32_t nsteps,
+                          const float* path4, const int32_t* path_start, float* lam_r4, float* lam_v4,
+                          double* theta, hipStream_t stream) {
+    Layout L{};
+    md_status s = make_layout(p, L);
+    if (s != MD_OK) return s;
+    if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
+    if ((s = check_path_args(p, first_step, nsteps, path4, path_start, true)) != MD_OK) return s;
+    if ((s = check_adjoint_vecs(lam_r4, lam_v4)) != MD_OK) return s;
+    const SimArgs a = make_args(p, L, ws);
+    return sweep_impl(a, p, first_step, nsteps, const_cast<float*>(path4), const_cast<int32_t*>(path_start), lam_r4,
+                      lam_v4, theta, stream);
+}
+
+md_status md_step_path(const md_params* p, void* ws, size_t ws_bytes, int32_t nsteps, float* path4,
+                       int32_t* path_start, hipStream_t stream) {
+    Layout L{};
+    md_status s = make_layout(p, L);
+    if (s != MD_OK) return s;
+    if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
+    if ((s = check_path_args(p, 0, nsteps, path4, path_start, false)) != MD_OK) return s;
+    const SimArgs a = make_args(p, L, ws);
+    // state 0 is the workspace's own (cells built, forces computed): its
+    // sorted positions and offsets are copied once; every later state is
+    // sorted straight into its slice, as in the recompute
+    MD_TRY_HIP(hipMemcpyAsync(path4, a.pos0, static_cast<size_t>(p->n) * sizeof(float4), hipMemcpyDeviceToDevice,
+                              stream),
+               "path copy");
+    MD_TRY_HIP(hipMemcpyAsync(path_start, a.start, (static_cast<size_t>(L.ncells) + 1) * sizeof(int32_t),
+                              hipMemcpyDeviceToDevice, stream),
+               "path copy");
+    // md_step's sequence; the rebuild before step k + 1 writes state k into
+    // slice k, the last one into the workspace, which ends as after md_step
+    for (int32_t k = 1; k <= nsteps; ++k) {
+        const bool last = k == nsteps;
+        const SimArgs ak = last ? a : path_slice(a, path4, path_start, k);
+        if (k == 1) MD_TRY_HIP(launch_integrate(a, stream), "integrate");
+        if ((s = rebuild(ak, (k - 1) & 1, true, stream)) != MD_OK) return s;
+        MD_TRY_HIP(launch_forces(ak, true, false, last, true, !last, k & 1, stream), "forces");
+    }
+    MD_TRY_HIP(launch_zero_blocks(a, (nsteps - 1) & 1, stream), "counter clear");
     return MD_OK;
 }
 

@@ -136,6 +136,38 @@ def test_workspace_and_pointer_checks_on_host():
         == _lib.MD_ERR_ARG  # the two adjoint vectors alias
 
 
+def test_path_entry_points_validate_on_host():
+    """md_step_path, md_adjoint_recompute and md_adjoint_path refuse empty
+    paths, NULL or misaligned arrays, aliased adjoint vectors and the
+    energy-shift mode before any HIP call."""
+    import ctypes
+
+    lib = _lib.lib()
+    p = md.make_params(100, 10.0)
+    need = md.md_workspace_bytes(p)
+    fake = ctypes.c_void_p(1 << 40)  # never dereferenced: validation fails first
+    other = ctypes.c_void_p((1 << 40) + 4096)
+    odd = ctypes.c_void_p((1 << 40) + 8)
+    ERR = _lib.MD_ERR_ARG
+    assert lib.md_step_path(ctypes.byref(p), fake, need, 0, fake, fake, None) == ERR
+    assert lib.md_step_path(ctypes.byref(p), fake, need, 3, None, fake, None) == ERR
+    assert lib.md_step_path(ctypes.byref(p), fake, need, 3, fake, None, None) == ERR
+    assert lib.md_step_path(ctypes.byref(p), fake, need, 3, odd, fake, None) == ERR
+    assert lib.md_step_path(ctypes.byref(p), None, need, 3, fake, fake, None) == _lib.MD_ERR_WORKSPACE
+    assert lib.md_adjoint_recompute(ctypes.byref(p), fake, need, fake, fake, 0, fake, fake, None) == ERR
+    assert lib.md_adjoint_recompute(ctypes.byref(p), fake, need, None, fake, 2, fake, fake, None) == ERR
+    assert lib.md_adjoint_recompute(ctypes.byref(p), fake, need, fake, odd, 2, fake, fake, None) == ERR
+    assert lib.md_adjoint_path(ctypes.byref(p), fake, need, -1, 2, fake, fake, fake, other, None, None) == ERR
+    assert lib.md_adjoint_path(ctypes.byref(p), fake, need, 0, 0, fake, fake, fake, other, None, None) == ERR
+    assert lib.md_adjoint_path(ctypes.byref(p), fake, need, 0, 2, fake, fake, fake, fake, None, None) == ERR
+    assert lib.md_adjoint_path(ctypes.byref(p), fake, need, 0, 2, fake, fake, None, other, None, None) == ERR
+    assert lib.md_adjoint_path(ctypes.byref(p), fake, need, 0, 2, fake, fake, odd, other, None, None) == ERR
+    e = md.make_params(100, 10.0, shift_mode=1)
+    assert lib.md_adjoint_path(ctypes.byref(e), fake, md.md_workspace_bytes(e), 0, 2, fake, fake, fake, other,
+                               None, None) == ERR
+    assert b"shift_mode 0" in lib.md_last_error()
+
+
 def test_pair_list_arrays_only_on_request():
     """md_step_list's arrays are laid out only with MD_FLAG_PAIR_LISTS, and
     md_step_list refuses a workspace without them (host check)."""

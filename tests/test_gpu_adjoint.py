@@ -211,6 +211,36 @@ def test_autograd_function_matches_direct_call():
     assert float(e.grad) == ge and float(sg.grad) == gs
 
 
+@pytest.mark.parametrize("wl,nsteps,every", [("lj4k", 45, 10), ("lj32k_adjoint", 40, 20)])
+def test_backward_modes_bitwise_equal(wl, nsteps, every):
+    """Three ways to run the backward pass give bitwise the same loss and
+    gradients: one md_adjoint_segment call per segment on one stream; the
+    overlapped form (md_adjoint_recompute of the next segment on a second
+    stream and workspace while md_adjoint_path sweeps the current one, two
+    path buffers alternating); and the kept path (md_step_path in the
+    forward, md_adjoint_path over slices of it, no recomputation). A short
+    last segment is included (45 = 4 x 10 + 5)."""
+    torch = _torch()
+    from paper_0709_3225_amd import trajectory_gradients
+
+    w = ljsynth.WORKLOADS[wl]
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05)
+    x, v = _dev(pos4), _dev(vel4)
+    out = {}
+    for mode, kw in (("segment", dict(overlap=False)), ("overlap", dict(overlap=True)),
+                     ("kept", dict(keep_path=True))):
+        _say(f"backward mode {mode} n={len(pos4)} T={nsteps} every={every}")
+        out[mode] = trajectory_gradients(x, v, box, dt=w.dt, nsteps=nsteps, every=every, **kw)
+        torch.cuda.synchronize()
+    ref = out["segment"]
+    assert np.isfinite(ref[0]) and float(ref[1].abs().sum()) > 0.0
+    for mode in ("overlap", "kept"):
+        got = out[mode]
+        assert got[0] == ref[0], mode
+        assert torch.equal(got[1], ref[1]) and torch.equal(got[2], ref[2]), mode
+        assert got[3] == ref[3] and got[4] == ref[4], mode
+
+
 @pytest.mark.parametrize("first_step", [0, 3])
 def test_segment_equals_composed_calls(first_step):
     """md_adjoint_segment is the composition of the public calls it stands
