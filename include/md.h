@@ -89,6 +89,16 @@ typedef struct md_params {
                               skin), r_c < r_V <= cell side; 0 selects the cell
                               side. The lists stay valid while no atom has
                               moved by more than (r_V - r_c) / 2. */
+    int32_t tile_cap;      /* atoms staged per LDS pass of the force and pair
+                              passes: 0 selects 1.1 x the mean 27-cell
+                              neighbourhood + 32, rounded up to a multiple of
+                              64 within [128, 2048]; else a multiple of 64 in
+                              [128, 2048]. A neighbourhood larger than the tile
+                              takes several passes; a smaller tile leaves LDS
+                              for more wavefronts per CU. Results do not depend
+                              on it except through the order of passes (bitwise
+                              reproducible for a fixed value). The batch calls
+                              ignore it (each replica takes the formula). */
 } md_params;
 
 /* md_params.flags: lay the workspace out with md_step_list's pair-list
@@ -118,6 +128,11 @@ size_t md_workspace_bytes(const md_params* p);
  * Returns MD_ERR_BOX if L < 2 r_c.
  */
 md_status md_cell_grid(const md_params* p, int32_t* cells_per_dim, float* cell_side);
+
+/* The LDS tile (atoms per pass) the force pass takes for these parameters:
+ * p->tile_cap, or the formula's value when it is 0. Returns 0 for invalid
+ * parameters (md_last_error says why). */
+int32_t md_tile_capacity(const md_params* p);
 
 /*
  * Load a state and build the cell list (section 3: cells of side >= r_c;

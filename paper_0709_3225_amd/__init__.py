@@ -21,11 +21,12 @@ from ._lib import (  # noqa: F401
     md_step,
     md_step_every,
     md_step_list,
+    md_tile_capacity,
     md_workspace_bytes,
 )
 from .system import LJSystem, occupancy_cell_min  # noqa: F401
 from .adjoint import LJTrajectory, trajectory_gradients  # noqa: F401
 from .batch import BatchedLJ  # noqa: F401
-from .tune import grid_options, tune_batch, tune_cell_min, tune_system  # noqa: F401
+from .tune import grid_options, tile_options, tune_batch, tune_cell_min, tune_system  # noqa: F401
 
 lib()

@@ -32,6 +32,7 @@ MD_FLAG_ATOM_LISTS = 2
 SYMBOLS = (
     "md_workspace_bytes",
     "md_cell_grid",
+    "md_tile_capacity",
     "md_build_cells",
     "md_forces",
     "md_forces_noalloc",
@@ -88,6 +89,7 @@ class MDParams(ctypes.Structure):
         ("flags", ctypes.c_int32),
         ("waves_per_cell", ctypes.c_int32),
         ("list_radius", ctypes.c_float),
+        ("tile_cap", ctypes.c_int32),
     ]
 
 
@@ -107,9 +109,10 @@ def replica_table(reps):
 
 
 def make_params(n, box, epsilon=1.0, sigma=1.0, mass=1.0, rc_over_sigma=2.5, dt=0.005, cell_min=0.0,
-                shift_mode=0, flags=0, waves_per_cell=0, list_radius=0.0) -> MDParams:
+                shift_mode=0, flags=0, waves_per_cell=0, list_radius=0.0, tile_cap=0) -> MDParams:
     return MDParams(int(n), float(box), float(epsilon), float(sigma), float(mass), float(rc_over_sigma),
-                    float(dt), float(cell_min), int(shift_mode), int(flags), int(waves_per_cell), float(list_radius))
+                    float(dt), float(cell_min), int(shift_mode), int(flags), int(waves_per_cell), float(list_radius),
+                    int(tile_cap))
 
 
 _lib = None
@@ -129,6 +132,8 @@ def lib():
         L.md_workspace_bytes.argtypes = [P]
         L.md_workspace_bytes.restype = sz
         L.md_cell_grid.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
+        L.md_tile_capacity.argtypes = [P]
+        L.md_tile_capacity.restype = i32
         L.md_build_cells.argtypes = [P, vp, sz, vp, vp, vp]
         L.md_forces.argtypes = [P, vp, sz, vp, vp]
         L.md_forces_noalloc.argtypes = [P, vp, vp, vp]
@@ -235,6 +240,14 @@ def md_cell_grid(p: MDParams):
     side = ctypes.c_float()
     _check(lib().md_cell_grid(ctypes.byref(p), ctypes.byref(nc), ctypes.byref(side)))
     return nc.value, side.value
+
+
+def md_tile_capacity(p: MDParams) -> int:
+    """Atoms per LDS pass of the force pass for these parameters."""
+    t = lib().md_tile_capacity(ctypes.byref(p))
+    if t == 0:
+        raise MDError(MD_ERR_ARG, lib().md_last_error().decode())
+    return int(t)
 
 
 def md_build_cells(p: MDParams, ws, pos4, vel4=None, stream=None):

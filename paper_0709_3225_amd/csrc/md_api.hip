@@ -62,6 +62,8 @@ md_status validate(const md_params* p) {
         return fail(MD_ERR_ARG, "flags hold unknown bits 0x%x", p->flags);
     if (p->waves_per_cell != 0 && p->waves_per_cell != 1 && p->waves_per_cell != 2 && p->waves_per_cell != 4)
         return fail(MD_ERR_ARG, "waves_per_cell must be 0, 1, 2 or 4 (got %d)", p->waves_per_cell);
+    if (p->tile_cap != 0 && (p->tile_cap < 128 || p->tile_cap > 2048 || p->tile_cap % 64 != 0))
+        return fail(MD_ERR_ARG, "tile_cap must be 0 or a multiple of 64 in [128, 2048] (got %d)", p->tile_cap);
     const float rc = cutoff(p);
     if (!(rc > 0.f) || !std::isfinite(rc)) return fail(MD_ERR_ARG, "cutoff must be finite and > 0");
     if (!(p->box >= 2.0f * rc)) return fail(MD_ERR_BOX, "box %g is shorter than two cutoffs (2 * %g)", p->box, rc);
@@ -261,7 +263,7 @@ SimArgs make_args(const md_params* p, const Layout& L, void* ws) {
     const double rv = p->list_radius > 0.f ? static_cast<double>(p->list_radius) : static_cast<double>(L.s);
     a.list_screen2 = screen_bound(rv, L.s);
     a.disp_half = static_cast<float>(std::max(0.0, 0.5 * (rv - rc) * (1.0 - std::ldexp(1.0, -20))));
-    a.tile_cap = tile_capacity(p->n, L.ncells);
+    a.tile_cap = p->tile_cap != 0 ? p->tile_cap : tile_capacity(p->n, L.ncells);
     a.waves = waves_per_cell(p);
     a.dt = p->dt;
     a.hdt_m = static_cast<float>(0.5 * p->dt / p->mass);
@@ -631,6 +633,12 @@ md_status md_cell_grid(const md_params* p, int32_t* cells_per_dim_out, float* ce
     if (cells_per_dim_out) *cells_per_dim_out = L.nc;
     if (cell_side) *cell_side = L.s;
     return MD_OK;
+}
+
+int32_t md_tile_capacity(const md_params* p) {
+    Layout L{};
+    if (make_layout(p, L) != MD_OK) return 0;
+    return p->tile_cap != 0 ? p->tile_cap : tile_capacity(p->n, L.ncells);
 }
 
 md_status md_build_cells(const md_params* p, void* ws, size_t ws_bytes, const float* pos4, const float* vel4,

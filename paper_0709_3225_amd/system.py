@@ -24,10 +24,10 @@ class LJSystem:
 
     def __init__(self, n, box, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_over_sigma=2.5, dt=0.005,
                  cell_min=0.0, shift_mode=0, pair_lists=False, atom_lists=False, waves_per_cell=0, list_radius=0.0,
-                 device="cuda"):
+                 tile_cap=0, device="cuda"):
         flags = (L.MD_FLAG_PAIR_LISTS if pair_lists else 0) | (L.MD_FLAG_ATOM_LISTS if atom_lists else 0)
         self.params = L.make_params(n, box, epsilon, sigma, mass, rc_over_sigma, dt, cell_min, shift_mode, flags,
-                                    waves_per_cell, list_radius)
+                                    waves_per_cell, list_radius, tile_cap)
         self.cells_per_dim, self.cell_side = L.md_cell_grid(self.params)  # raises on invalid params
         self.nbytes = L.md_workspace_bytes(self.params)
         self.device = torch.device(device)

@@ -7,7 +7,9 @@ but fill more lanes of the one-wavefront-per-cell kernel; which wins depends
 on the occupancy of the cells, so it is measured, not modelled. The force
 pass may also split a cell's candidates over two or four wavefronts
 (md_params.waves_per_cell), which pays only where the grid has too few cells
-to fill the GPU; tune_system measures both knobs on one system.
+to fill the GPU, and its LDS tile (md_params.tile_cap) trades passes over
+large neighbourhoods against wavefronts per CU; tune_system measures all
+three knobs on one system.
 
 Replicas are grouped into size buckets (their default grid and its mean
 occupancy). For each bucket the tuner times batched steps of a probe made of
@@ -144,16 +146,35 @@ def tune_cell_min(n: int, box: float, pos4: torch.Tensor, vel4: torch.Tensor, **
     return cms[0], report
 
 
+def tile_options(p: L.MDParams, offsets=(0, 128, -64)):
+    """Candidate LDS tiles of one system: md_params.tile_cap values for the
+    formula's tile T (0) and for T + offset, kept within [128, 2048] and
+    distinct."""
+    t0 = L.md_tile_capacity(p)
+    out = []
+    for off in offsets:
+        t = 0 if off == 0 else t0 + int(off)
+        if t != 0 and (t < 128 or t > 2048 or t % 64 != 0 or t == t0):
+            continue
+        if t not in out:
+            out.append(t)
+    return out
+
+
 def tune_system(n: int, box: float, pos4: torch.Tensor, vel4: torch.Tensor, *, epsilon=1.0, sigma=1.0, mass=1.0,
-                rc_over_sigma=2.5, dt=0.005, shift_mode=0, extra=1, waves=(1, 2, 4), steps=20, warmup=3, repeats=3,
-                min_gain=0.03):
-    """Pick the cell grid and the wavefronts per cell of one system by timing
-    md_step on the system itself (not on copies: a small system's grid holds
-    too few cells to fill the GPU with one wavefront each, which is where
-    several wavefronts per cell pay). Candidates are grid_options x waves; a
-    candidate replaces the default (default grid, one wavefront) only if it
-    is faster per step by at least ``min_gain``. Returns
-    (cell_min, waves_per_cell, report)."""
+                rc_over_sigma=2.5, dt=0.005, shift_mode=0, extra=1, waves=(1, 2, 4), tiles=(0, 128, -64), steps=20,
+                warmup=3, repeats=3, min_gain=0.03):
+    """Pick the cell grid, the wavefronts per cell and the LDS tile of one
+    system by timing md_step on the system itself (not on copies: a small
+    system's grid holds too few cells to fill the GPU with one wavefront
+    each, which is where several wavefronts per cell pay). Candidates are
+    grid_options x waves x tile_options (tile offsets in atoms from the
+    formula's tile of each grid, 0 being the formula); a candidate replaces
+    the default (default grid, one wavefront, the formula's tile) only if it
+    is faster per step by at least ``min_gain``, and its tile replaces the
+    formula's only if it also beats that on the same grid and wavefront count
+    by ``min_gain``. Returns
+    (cell_min, waves_per_cell, tile_cap, report); tile_cap 0 is the formula."""
     from .system import LJSystem
 
     shared = dict(epsilon=epsilon, sigma=sigma, mass=mass, rc_over_sigma=rc_over_sigma, dt=dt, shift_mode=shift_mode)
@@ -161,26 +182,36 @@ def tune_system(n: int, box: float, pos4: torch.Tensor, vel4: torch.Tensor, *, e
     stream = torch.cuda.Stream()
     tried = []
     for nc, cm in grid_options(n, box, rc_over_sigma=rc_over_sigma, sigma=sigma, extra=extra):
+        p = L.make_params(n, box, cell_min=cm, **shared)
         for wv in waves:
-            s = LJSystem(n, box, cell_min=cm, waves_per_cell=wv, **shared)
-            events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                      for _ in range(repeats)]
-            # the workspace was allocated on the caller's stream
-            stream.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(stream):
-                s.load(pos4, vel4)
-                s.step(warmup)
-                for e0, e1 in events:
-                    e0.record(stream)
-                    s.step(steps)
-                    e1.record(stream)
-            stream.synchronize()
-            s.check()
-            best_t = min(e0.elapsed_time(e1) for e0, e1 in events) / 1e3 / steps
-            tried.append({"cells_per_dim": nc, "cell_min": cm, "waves_per_cell": wv, "s_per_step": best_t})
+            for tc in tile_options(p, tiles):
+                s = LJSystem(n, box, cell_min=cm, waves_per_cell=wv, tile_cap=tc, **shared)
+                events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                          for _ in range(repeats)]
+                # the workspace was allocated on the caller's stream
+                stream.wait_stream(torch.cuda.current_stream())
+                with torch.cuda.stream(stream):
+                    s.load(pos4, vel4)
+                    s.step(warmup)
+                    for e0, e1 in events:
+                        e0.record(stream)
+                        s.step(steps)
+                        e1.record(stream)
+                stream.synchronize()
+                s.check()
+                best_t = min(e0.elapsed_time(e1) for e0, e1 in events) / 1e3 / steps
+                tried.append({"cells_per_dim": nc, "cell_min": cm, "waves_per_cell": wv, "tile_cap": tc,
+                              "tile_atoms": L.md_tile_capacity(s.params), "s_per_step": best_t})
     best = min(tried, key=lambda t: t["s_per_step"])
     if best["s_per_step"] >= tried[0]["s_per_step"] * (1.0 - min_gain):
         best = tried[0]
-    report = {"tried": tried, "chosen": {k: best[k] for k in ("cells_per_dim", "cell_min", "waves_per_cell")},
+    # the tile moves off the formula's only if that beats the formula's tile on
+    # the same grid and wavefront count by min_gain as well
+    same = [t for t in tried if t["cell_min"] == best["cell_min"] and t["waves_per_cell"] == best["waves_per_cell"]
+            and t["tile_cap"] == 0]
+    if same and best["s_per_step"] >= same[0]["s_per_step"] * (1.0 - min_gain):
+        best = same[0]
+    report = {"tried": tried,
+              "chosen": {k: best[k] for k in ("cells_per_dim", "cell_min", "waves_per_cell", "tile_cap", "tile_atoms")},
               "seconds": time.perf_counter() - t_start}
-    return best["cell_min"], best["waves_per_cell"], report
+    return best["cell_min"], best["waves_per_cell"], best["tile_cap"], report

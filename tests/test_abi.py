@@ -136,6 +136,38 @@ def test_workspace_and_pointer_checks_on_host():
         == _lib.MD_ERR_ARG  # the two adjoint vectors alias
 
 
+def test_tile_cap_parameter():
+    """md_params.tile_cap: 0 takes the formula (1.1 x the mean 27-cell
+    neighbourhood + 32, rounded up to a multiple of 64 in [128, 2048]), other
+    values must be multiples of 64 in [128, 2048]; md_tile_capacity reports
+    the tile and 0 for invalid parameters; the tile leaves the workspace
+    layout alone."""
+    import ctypes
+    import math
+
+    for n, box in ((256000, 67.18385), (4000, 16.79596), (32000, 33.59192), (2048000, 134.3677)):
+        p = md.make_params(n, box)
+        nc, _ = md.md_cell_grid(p)
+        hood = 27.0 * n / nc ** 3
+        want = min(2048, max(128, math.ceil((1.1 * hood + 32.0) / 64.0) * 64))
+        assert md.md_tile_capacity(p) == want
+        q = md.make_params(n, box, tile_cap=768)
+        assert md.md_tile_capacity(q) == 768
+        assert md.md_workspace_bytes(q) == md.md_workspace_bytes(p)
+    assert md.md_tile_capacity(md.make_params(256000, 67.18385)) == 512
+    lib = _lib.lib()
+    for bad in (64, 100, 200, 2112, 4096, -64):
+        p = md.make_params(4000, 16.79596, tile_cap=bad)
+        assert md.md_workspace_bytes(p) == 0
+        assert lib.md_tile_capacity(ctypes.byref(p)) == 0
+        assert b"tile_cap" in lib.md_last_error()
+    assert md.tile_options(md.make_params(256000, 67.18385)) == [0, 640, 448]
+    # the formula's floor: 128 atoms for a sparse system, so -64 is dropped
+    sparse = md.make_params(50, 10.0)
+    assert md.md_tile_capacity(sparse) == 128
+    assert md.tile_options(sparse, offsets=(0, -64, 128)) == [0, 256]
+
+
 def test_path_entry_points_validate_on_host():
     """md_step_path, md_adjoint_recompute and md_adjoint_path refuse empty
     paths, NULL or misaligned arrays, aliased adjoint vectors and the

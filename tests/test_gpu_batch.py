@@ -266,6 +266,34 @@ def test_tuner_moves_a_sparse_system_to_larger_cells(orc):
     assert np.linalg.norm(f[sel] - fo) <= 1e-5 * np.linalg.norm(fo)
 
 
+def test_tune_system_picks_measured_knobs(orc):
+    """tune_system times every (grid, wavefronts per cell, LDS tile)
+    candidate on the system itself and returns one of them; the system built
+    with the returned knobs matches the oracle."""
+    _torch()
+    from paper_0709_3225_amd import LJSystem, _lib as L, grid_options, tile_options, tune_system
+
+    w = ljsynth.WORKLOADS["lj4k"]
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05)
+    _say(f"tune one system n={w.n} box={box:.3f}")
+    cm, wv, tc, report = tune_system(w.n, box, _cuda(pos4), _cuda(vel4), waves=(1, 4), steps=4, warmup=1,
+                                     repeats=2)
+    grids = grid_options(w.n, box)
+    tiles = {c: tile_options(L.make_params(w.n, box, cell_min=c)) for _, c in grids}
+    assert len(report["tried"]) == 2 * sum(len(t) for t in tiles.values())
+    assert cm in tiles and wv in (1, 4) and tc in tiles[cm]
+    ch = report["chosen"]
+    assert (ch["cell_min"], ch["waves_per_cell"], ch["tile_cap"]) == (cm, wv, tc)
+    assert all(t["s_per_step"] > 0.0 for t in report["tried"])
+    s = LJSystem(w.n, box, cell_min=cm, waves_per_cell=wv, tile_cap=tc)
+    assert L.md_tile_capacity(s.params) == ch["tile_atoms"]
+    s.load(_cuda(pos4), _cuda(vel4))
+    f = s.forces().cpu().numpy()[:, :3]
+    s.check()
+    fo, _, _ = orc.forces(orc.params(box), pos4)
+    assert np.linalg.norm(f - fo) <= 1e-5 * np.linalg.norm(fo)
+
+
 def test_tile_classes_with_multipass_tiles():
     """One batch whose replicas fall into three LDS tile classes, one of them
     with cells so large (about 148 atoms) that the neighbourhood is staged in

@@ -516,6 +516,61 @@ def test_waves_per_cell_match_oracle(case, waves, orc):
     assert e[1] == e1[1]
 
 
+@pytest.mark.parametrize("tile", [128, 192, 1024])
+@pytest.mark.parametrize("case", ["lj4k_jitter_shuffled", "lj32k_jitter", "dense_clump", "fluid_rho0.4_ragged"])
+def test_tile_cap_matches_oracle(case, tile, orc):
+    """The LDS tile knob: a tile of 128 or 192 atoms splits every 27-cell
+    neighbourhood of the dense states into several passes (the cursor
+    staging of every cell, interior ones included), a 1,024-atom tile keeps
+    the clump's in one; forces and energies against the oracle at the usual
+    bar, and the same pairs as the formula's tile (only the order of the FP32
+    sums differs), in one and in four wavefronts per cell."""
+    from paper_0709_3225_amd import _lib as L
+
+    pos4, box = CASES[case]()
+    _say(f"tile {tile} {case} n={len(pos4)}")
+    vel4 = np.zeros_like(pos4)
+    vel4[:, :3] = np.random.default_rng(6).normal(size=(len(pos4), 3))
+    p = orc.params(box)
+    fo, U, W = orc.forces(p, pos4)
+    K = orc.kinetic(p, vel4)
+    _, f0, e0 = gpu_forces(pos4, box, vel4)
+    for waves in (1, 4):
+        s, f, e = gpu_forces(pos4, box, vel4, tile_cap=tile, waves_per_cell=waves)
+        assert L.md_tile_capacity(s.params) == tile
+        assert rel_l2(f, fo) <= FORCE_TOL
+        assert abs(e[0] - U) <= ENERGY_TOL * abs(U)
+        assert abs(e[1] - K) <= ENERGY_TOL * abs(K)
+        assert abs(e[2] - W) <= ENERGY_TOL * abs(W)
+        assert rel_l2(f, f0) <= 1e-6
+        assert e[1] == e0[1]
+
+
+def test_tile_cap_steps_repeatable(orc):
+    """md_step with a 192-atom tile: one step against the oracle's step and
+    two 20-step runs bitwise equal."""
+    torch = _torch()
+    w = ljsynth.WORKLOADS["lj4k"]
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05, shuffle=True)
+    _say("tile 192 steps lj4k")
+    runs = []
+    for _ in range(2):
+        s = _system(w.n, box, dt=w.dt, tile_cap=192)
+        s.load(_dev(pos4), _dev(vel4))
+        s.step(1)
+        if not runs:
+            pos, vel = s.state()
+            x, v, _ = orc.run(orc.params(box, dt=w.dt), pos4, vel4, 1)
+            d = pos.cpu().numpy()[:, :3] - x
+            d -= box * np.round(d / box)
+            assert np.abs(d).max() < 2e-5
+            assert rel_l2(vel.cpu().numpy()[:, :3], v) < 1e-5
+        s.step(19)
+        assert s.check() == 0
+        runs.append(s.state())
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+
+
 @pytest.mark.parametrize("waves", [2, 4])
 def test_waves_per_cell_steps(waves, orc):
     """md_step with several wavefronts per cell: one step against the oracle's
