@@ -49,13 +49,12 @@ __device__ __forceinline__ PairConsts pair_consts(const SimArgs& a) {
 // sigma times the sigma derivative projected on w_i.
 struct AdjOp {
     const PairConsts& k;
-    const char* base;   // position tile at the lane's span start
-    const char* wbase;  // adjoint-vector tile at the lane's span start
+    uint32_t wdelta;    // LDS distance from the position tile to the adjoint-vector tile
     float xi, yi, zi, wx, wy, wz;
     float jx = 0.f, jy = 0.f, jz = 0.f, fx = 0.f, fy = 0.f, fz = 0.f, sg = 0.f;
-    __device__ __forceinline__ void operator()(uint32_t off, bool live) {
-        const float4 q = *reinterpret_cast<const float4*>(base + off);
-        const float4 wj = *reinterpret_cast<const float4*>(wbase + off);
+    __device__ __forceinline__ void operator()(uint32_t addr, bool live) {
+        const float4 q = lds_load(addr);
+        const float4 wj = lds_load(addr + wdelta);
         const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
         const bool ok = live && (r2 < k.rc2);
@@ -87,11 +86,10 @@ struct AdjOp {
 // plus W and sigma r dphi/dsigma for the parameter derivatives.
 struct VGradOp {
     const PairConsts& k;
-    const char* base;
     float xi, yi, zi;
     float gx = 0.f, gy = 0.f, gz = 0.f, wsum = 0.f, wsig = 0.f;
-    __device__ __forceinline__ void operator()(uint32_t off, bool live) {
-        const float4 q = *reinterpret_cast<const float4*>(base + off);
+    __device__ __forceinline__ void operator()(uint32_t addr, bool live) {
+        const float4 q = lds_load(addr);
         const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
         const bool ok = live && (r2 < k.rc2);
@@ -239,15 +237,14 @@ __global__ void __launch_bounds__(MW * kWave)
                 }
                 if (act) clear_self(self_t, first, ns, groups, wd);
                 if (ADJ) {
-                    AdjOp op{kc, reinterpret_cast<const char*>(tile + first), reinterpret_cast<const char*>(wtile + first),
-                             xi, yi, zi, wi.x, wi.y, wi.z};
+                    AdjOp op{kc, lds_address(wtile) - lds_address(tile), xi, yi, zi, wi.x, wi.y, wi.z};
                     op.jx = v0; op.jy = v1; op.jz = v2; op.fx = v3; op.fy = v4; op.fz = v5; op.sg = v6;
-                    walk_bits(ns, wd[0], wd[1], wd[2], wd[3], op);
+                    walk_bits(ns, lds_address(tile + first), wd[0], wd[1], wd[2], wd[3], op);
                     v0 = op.jx; v1 = op.jy; v2 = op.jz; v3 = op.fx; v4 = op.fy; v5 = op.fz; v6 = op.sg;
                 } else {
-                    VGradOp op{kc, reinterpret_cast<const char*>(tile + first), xi, yi, zi};
+                    VGradOp op{kc, xi, yi, zi};
                     op.gx = v0; op.gy = v1; op.gz = v2; op.wsum = v3; op.wsig = v4;
-                    walk_bits(ns, wd[0], wd[1], wd[2], wd[3], op);
+                    walk_bits(ns, lds_address(tile + first), wd[0], wd[1], wd[2], wd[3], op);
                     v0 = op.gx; v1 = op.gy; v2 = op.gz; v3 = op.wsum; v4 = op.wsig;
                 }
             }

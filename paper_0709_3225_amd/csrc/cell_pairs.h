@@ -565,20 +565,34 @@ __device__ __forceinline__ void screen_span(const float4* tile, int first, int n
     }
 }
 
-// Walk the accepted bits of one span in order, calling op(byte_offset, live)
-// for each: byte_offset locates the accepted candidate relative to
-// tile + first (and the same offset in any parallel tile); live is false for
-// lanes that have spent their bits. The words rotate through four registers
-// (never indexed, which would put them in scratch memory); an exhausted word
-// is replaced by the next one without a branch. Each iteration takes two
-// candidates (the second may come from the next word), so the wave-wide loop
-// test and branch run once per pair; the calls keep the one-at-a-time order,
-// so sums do not depend on the unrolling.
+// The LDS byte address of a pointer into shared memory (the low half of its
+// generic address), and a 16-byte load from such an address: walks that
+// carry absolute LDS addresses read their candidates with no add.
+__device__ __forceinline__ uint32_t lds_address(const void* p) {
+    return static_cast<uint32_t>(reinterpret_cast<uintptr_t>(p));
+}
+typedef float lds_float4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 lds_load(uint32_t addr) {
+    const lds_float4 v = *(const __attribute__((address_space(3))) lds_float4*)(static_cast<uintptr_t>(addr));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+// Walk the accepted bits of one span in order, calling op(address, live) for
+// each: address is the LDS byte address of the accepted candidate, the span's
+// candidate 0 lying at wb0; live is false for lanes that have spent their
+// bits. The
+// words rotate through four registers (never indexed, which would put them
+// in scratch memory); an exhausted word is replaced by the next one without a
+// branch. Each iteration takes two candidates (the second may come from the
+// next word), so the wave-wide loop test and branch run once per pair; the
+// calls keep the one-at-a-time order, so sums do not depend on the
+// unrolling.
 template <class Op>
-__device__ __forceinline__ void walk_bits(int ns, uint32_t m, uint32_t n1, uint32_t n2, uint32_t n3, Op& op) {
+__device__ __forceinline__ void walk_bits(int ns, uint32_t wb0, uint32_t m, uint32_t n1, uint32_t n2, uint32_t n3,
+                                          Op& op) {
     const uint32_t cstep = static_cast<uint32_t>(ns) * sizeof(float4);   // bytes between candidates
     const uint32_t wstep = 32u * cstep;                                  // bytes between words
-    uint32_t wb = 0;                                                     // byte offset of the word's candidate 0
+    uint32_t wb = wb0;                                                   // byte offset of the word's candidate 0
     uint32_t left = __builtin_popcount(m) + __builtin_popcount(n1) + __builtin_popcount(n2) +
                     __builtin_popcount(n3);
     if (!__any(left != 0u)) return;
@@ -594,12 +608,18 @@ __device__ __forceinline__ void walk_bits(int ns, uint32_t m, uint32_t n1, uint3
             n3 = next ? 0u : n3;
             wb = next ? wb + wstep : wb;
             live[u] = m != 0u;
-            const uint32_t k = live[u] ? __builtin_clz(m) : 0u;
-            m &= ~(0x80000000u >> k);
+            // all ones for a spent lane (m = 0): its shift clears no bit of
+            // m, and its offset is replaced below
+            const uint32_t k = __builtin_clzg(m, -1);
+            m &= ~(0x80000000u >> (k & 31u));
             left -= live[u] ? 1u : 0u;
             // a spent lane keeps rotating (wb grows past its span): it reads
             // its span's first candidate instead, which is always staged
-            off[u] = live[u] ? wb + __umul24(k, cstep) : 0u;
+            // (a constant stride, as the matrix-core screen's four slices
+            // give, makes the product one shift-and-add; otherwise the 24-bit
+            // multiply-add; either is garbage for a spent lane, replaced here)
+            const uint32_t step = __builtin_constant_p(cstep) ? k * cstep : __umul24(k, cstep);
+            off[u] = live[u] ? wb + step : wb0;
         }
         op(off[0], live[0]);
         op(off[1], live[1]);

@@ -47,16 +47,14 @@ __device__ __forceinline__ float pair_force(const SimArgs& a, const float4 q, fl
     return r2;
 }
 
-// Pair operation of the force walk: the accepted candidate at a byte offset
-// from the lane's span start.
+// Pair operation of the force walk: the accepted candidate at an LDS address.
 template <bool ENERGY>
 struct ForceOp {
     const SimArgs& a;
-    const char* base;
     float xi, yi, zi;
     float fx = 0.f, fy = 0.f, fz = 0.f, u_loc = 0.f, w_loc = 0.f;
-    __device__ __forceinline__ void operator()(uint32_t off, bool live) {
-        const float4 q = *reinterpret_cast<const float4*>(base + off);
+    __device__ __forceinline__ void operator()(uint32_t addr, bool live) {
+        const float4 q = lds_load(addr);
         pair_force<ENERGY>(a, q, xi, yi, zi, live, fx, fy, fz, u_loc, w_loc);
     }
 };
@@ -67,19 +65,19 @@ struct ForceOp {
 template <bool ENERGY>
 struct RecordOp {
     const SimArgs& a;
-    const char* base;   // tile at the lane's span start
-    const char* cbase;  // list entries of the staged atoms at the same place (4 bytes each)
+    uint32_t tile0;     // LDS address of the tile
+    const char* cbase;  // list entries of the staged atoms (4 bytes each, at a quarter of the tile's offsets)
     float xi, yi, zi;
     uint32_t* row;      // the home atom's list: entry k at row[4 n (k / 4) + k % 4]
     int next;
     float fx = 0.f, fy = 0.f, fz = 0.f, u_loc = 0.f, w_loc = 0.f;
-    __device__ __forceinline__ void operator()(uint32_t off, bool live) {
-        const float4 q = *reinterpret_cast<const float4*>(base + off);
+    __device__ __forceinline__ void operator()(uint32_t addr, bool live) {
+        const float4 q = lds_load(addr);
         pair_force<ENERGY>(a, q, xi, yi, zi, live, fx, fy, fz, u_loc, w_loc);
         if (live) {
             if (next < a.nlist_cap)
                 row[4 * static_cast<size_t>(a.n) * (next >> 2) + (next & 3)] =
-                    *reinterpret_cast<const uint32_t*>(cbase + (off >> 2));
+                    *reinterpret_cast<const uint32_t*>(cbase + ((addr - tile0) >> 2));
             ++next;
         }
     }
@@ -97,14 +95,15 @@ struct ExportArgs {
 
 struct ExportOp {
     const SimArgs& a;
-    const char* base;   // tile at the lane's span start
-    const char* rbase;  // untranslated positions (user index in w) at the same place
+    uint32_t tile0;     // LDS address of the tile
+    const char* rbase;  // untranslated positions (user index in w) at the same offsets
     float xi, yi, zi;
     int idi;
     const ExportArgs& ex;
     bool over = false;
-    __device__ __forceinline__ void operator()(uint32_t off, bool live) {
-        const float4 q = *reinterpret_cast<const float4*>(base + off);
+    __device__ __forceinline__ void operator()(uint32_t addr, bool live) {
+        const uint32_t off = addr - tile0;
+        const float4 q = lds_load(addr);
         const float dx = xi - q.x, dy = yi - q.y, dz = zi - q.z;
         const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
         if (live && r2 < a.rc2) {
@@ -295,25 +294,24 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                 lcount += tot;
             };
             auto walk = [&](int ns_, int cand0, uint32_t (&wd)[kWords]) {
+                const uint32_t tile0 = lds_address(tile);
+                const uint32_t wb0 = tile0 + static_cast<uint32_t>(cand0) * sizeof(float4);
                 if (LIST == 3) {
-                    const char* codes = reinterpret_cast<const char*>(reinterpret_cast<const uint32_t*>(raw) + cand0);
-                    RecordOp<ENERGY> op{a,  reinterpret_cast<const char*>(tile + cand0), codes, xi, yi, zi, lrow_list,
-                                        rec_next, fx, fy, fz, u_loc, w_loc};
-                    walk_bits(ns_, wd[0], wd[1], wd[2], wd[3], op);
+                    RecordOp<ENERGY> op{a,  tile0, reinterpret_cast<const char*>(raw), xi, yi, zi, lrow_list, rec_next,
+                                        fx, fy, fz, u_loc, w_loc};
+                    walk_bits(ns_, wb0, wd[0], wd[1], wd[2], wd[3], op);
                     fx = op.fx;
                     fy = op.fy;
                     fz = op.fz;
                     u_loc = op.u_loc;
                     w_loc = op.w_loc;
                 } else if (EXPORT) {
-                    ExportOp op{a, reinterpret_cast<const char*>(tile + cand0), reinterpret_cast<const char*>(raw + cand0),
-                                xi, yi, zi, __float_as_int(pi.w), ex};
-                    walk_bits(ns_, wd[0], wd[1], wd[2], wd[3], op);
+                    ExportOp op{a, tile0, reinterpret_cast<const char*>(raw), xi, yi, zi, __float_as_int(pi.w), ex};
+                    walk_bits(ns_, wb0, wd[0], wd[1], wd[2], wd[3], op);
                     over = over || op.over;
                 } else {
-                    ForceOp<ENERGY> op{a, reinterpret_cast<const char*>(tile + cand0), xi, yi, zi, fx, fy, fz, u_loc,
-                                       w_loc};
-                    walk_bits(ns_, wd[0], wd[1], wd[2], wd[3], op);
+                    ForceOp<ENERGY> op{a, xi, yi, zi, fx, fy, fz, u_loc, w_loc};
+                    walk_bits(ns_, wb0, wd[0], wd[1], wd[2], wd[3], op);
                     fx = op.fx;
                     fy = op.fy;
                     fz = op.fz;
