@@ -38,10 +38,10 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def _loaded(pos4, box, vel4=None, waves=0):
+def _loaded(pos4, box, vel4=None, waves=0, tile=0):
     from paper_0709_3225_amd import LJSystem
 
-    s = LJSystem(len(pos4), box, waves_per_cell=waves)
+    s = LJSystem(len(pos4), box, waves_per_cell=waves, tile_cap=tile)
     s.load(_dev(pos4), None if vel4 is None else _dev(vel4), forces=False)
     return s
 
@@ -92,6 +92,37 @@ def test_hvp_and_force_parameter_derivatives(name, waves, orc):
     th = theta.cpu().numpy()
     assert th[0] == pytest.approx(de, rel=REL)
     assert th[1] == pytest.approx(ds, rel=REL)
+
+
+@pytest.mark.parametrize("tile", [192, 1024])
+@pytest.mark.parametrize("name", ["lj4k", "lj32k_adjoint"])
+def test_hvp_with_lds_tile(name, tile, orc):
+    """The pair pass with a 192-atom LDS tile (every neighbourhood in several
+    passes, staged through the segment table, with the adjoint vector's tile
+    beside it) and with a 1,024-atom one: Hessian-vector product and loss
+    gradient against the oracle, in one and four wavefronts per cell."""
+    torch = _torch()
+    from paper_0709_3225_amd import _lib as L
+
+    pos4, vel4, box = ljsynth.make_state(HVP_CASES[name](), jitter_amp=0.05, shuffle=True)
+    _say(f"hvp {name} n={len(pos4)} tile={tile}")
+    w = np.zeros_like(pos4)
+    w[:, :3] = np.random.default_rng(9).normal(size=(len(pos4), 3))
+    p = orc.params(box)
+    ref = orc.hvp(p, pos4, w)
+    gref, _, _ = orc.virial_grad(p, pos4)
+    for waves in (1, 4):
+        s = _loaded(pos4, box, waves=waves, tile=tile)
+        assert L.md_tile_capacity(s.params) == tile
+        lam = torch.zeros((len(pos4), 4), dtype=torch.float32, device="cuda")
+        L.md_adjoint_kick(s.params, s.ws, _dev(w), lam, None, 1.0)
+        assert s.check() == 0
+        assert rel_l2(lam.cpu().numpy()[:, :3].astype(np.float64), ref) <= REL
+        gr = torch.zeros((len(pos4), 4), dtype=torch.float32, device="cuda")
+        gv = torch.zeros((len(pos4), 4), dtype=torch.float32, device="cuda")
+        L.md_loss_grad(s.params, s.ws, 0.0, 1.0, gr, gv, None)
+        assert s.check() == 0
+        assert rel_l2(gr.cpu().numpy()[:, :3].astype(np.float64), gref) <= REL
 
 
 def test_hvp_symmetry_and_translation():
