@@ -580,10 +580,9 @@ __device__ __forceinline__ float4 lds_load(uint32_t addr) {
 // Walk the accepted bits of one span in order, calling op(address, live) for
 // each: address is the LDS byte address of the accepted candidate, the span's
 // candidate 0 lying at wb0; live is false for lanes that have spent their
-// bits. The
-// words rotate through four registers (never indexed, which would put them
-// in scratch memory); an exhausted word is replaced by the next one without a
-// branch. Each iteration takes two candidates (the second may come from the
+// bits. The words rotate through four registers (never indexed, which would
+// put them in scratch memory); an exhausted word is replaced by the next one
+// without a branch. Each iteration takes two candidates (the second may come from the
 // next word), so the wave-wide loop test and branch run once per pair; the
 // calls keep the one-at-a-time order, so sums do not depend on the
 // unrolling.
@@ -592,7 +591,7 @@ __device__ __forceinline__ void walk_bits(int ns, uint32_t wb0, uint32_t m, uint
                                           Op& op) {
     const uint32_t cstep = static_cast<uint32_t>(ns) * sizeof(float4);   // bytes between candidates
     const uint32_t wstep = 32u * cstep;                                  // bytes between words
-    uint32_t wb = wb0;                                                   // byte offset of the word's candidate 0
+    uint32_t wb = wb0;                                                   // LDS address of the word's candidate 0
     uint32_t left = __builtin_popcount(m) + __builtin_popcount(n1) + __builtin_popcount(n2) +
                     __builtin_popcount(n3);
     if (!__any(left != 0u)) return;
