@@ -557,29 +557,50 @@ __global__ void __launch_bounds__(kListBlock) k_nlist_forces(SimArgs a) {
     // of one group are consecutive
     const uint4* col = reinterpret_cast<const uint4*>(a.nlist) + (valid ? i : 0);
     float fx = 0.f, fy = 0.f, fz = 0.f, u_loc = 0.f, w_loc = 0.f;
-    for (int g = sl; 4 * g < cnt; g += kListLanes) {  // the capacity is a multiple of 4: whole uint4 loads
-        const uint4 e4 = col[static_cast<size_t>(a.n) * g];
+    // the capacity is a multiple of 4: whole uint4 loads. Each group's four
+    // partners are requested together and the next group's entries are in
+    // flight during this group's arithmetic; image shifts (pairs across a box
+    // face, rare) are applied once all four partners have arrived.
+    int g = sl;
+    uint4 e4 = 4 * g < cnt ? col[static_cast<size_t>(a.n) * g] : make_uint4(0u, 0u, 0u, 0u);
+    for (; 4 * g < cnt; g += kListLanes) {
         const uint32_t e[4] = {e4.x, e4.y, e4.z, e4.w};
+        float4 q[4];
+        int code[4];
+        bool in[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const bool in = 4 * g + u < cnt;
+            in[u] = 4 * g + u < cnt;
             // entries past the count are not this atom's: read the atom itself, masked
-            const uint32_t ej = in ? e[u] : (static_cast<uint32_t>(i) | (kCenter << kSlotBits));
+            const uint32_t ej = in[u] ? e[u] : (static_cast<uint32_t>(i) | (kCenter << kSlotBits));
             const uint32_t off = static_cast<uint32_t>(min(static_cast<int>(ej & kSlotMask), last)) << 4;
-            float4 q = *reinterpret_cast<const float4*>(pbase + off);
-            const int code = static_cast<int>(ej >> kSlotBits);
-            float xi = pi.x, yi = pi.y, zi = pi.z;
-            if (__any(code != kCenter)) {  // pairs across a box face (rare): the image shifts
-                const float4 hp = shp[code], hm = shm[code];
-                q.x += hm.x;
-                q.y += hm.y;
-                q.z += hm.z;
-                xi -= hp.x;
-                yi -= hp.y;
-                zi -= hp.z;
-            }
-            pair_force<false>(a, q, xi, yi, zi, in, fx, fy, fz, u_loc, w_loc);
+            q[u] = *reinterpret_cast<const float4*>(pbase + off);
+            code[u] = static_cast<int>(ej >> kSlotBits);
         }
+        const int gn = g + kListLanes;
+        if (4 * gn < cnt) e4 = col[static_cast<size_t>(a.n) * gn];
+        float xs[4], ys[4], zs[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            xs[u] = pi.x;
+            ys[u] = pi.y;
+            zs[u] = pi.z;
+        }
+        const bool shifted = (code[0] != kCenter) | (code[1] != kCenter) | (code[2] != kCenter) | (code[3] != kCenter);
+        if (__any(shifted)) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float4 hp = shp[code[u]], hm = shm[code[u]];
+                q[u].x += hm.x;
+                q[u].y += hm.y;
+                q[u].z += hm.z;
+                xs[u] -= hp.x;
+                ys[u] -= hp.y;
+                zs[u] -= hp.z;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pair_force<false>(a, q[u], xs[u], ys[u], zs[u], in[u], fx, fy, fz, u_loc, w_loc);
     }
     // the atom's lanes are consecutive: sum (s0 + s1) + (s2 + s3)
 #pragma unroll
