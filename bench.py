@@ -519,10 +519,11 @@ def recorded_traffic(workload):
     return float(rec["traffic_bytes_per_launch"])
 
 
-def cpu_cell_list(pos4, vel4, box, headline, steps=3):
+def cpu_cell_list(pos4, vel4, box, headline, steps=10):
     """Algorithm-matched CPU baseline: the same cell-list method in C with
-    OpenMP on the host cores (built here for this host's CPU), FP32 and FP64,
-    on the same state; per-step time from runs of `steps` and 0 steps."""
+    OpenMP threads and SIMD pair loops on the host cores (built here for this
+    host's CPU), FP32 and FP64, on the same state; per-step time from runs of
+    `steps` and 0 steps."""
     import cpu_cells
 
     cpu_cells.build(force=True, native=True)
@@ -533,7 +534,7 @@ def cpu_cell_list(pos4, vel4, box, headline, steps=3):
             model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
     except OSError:
         pass
-    out = {"unit": "atom-steps/s", "cores": cores, "kind": "cell list (C, OpenMP)", "cpu_model": model,
+    out = {"unit": "atom-steps/s", "cores": cores, "kind": "cell list (C, OpenMP threads, SIMD pair loops)", "cpu_model": model,
            "affinity_cpus": len(os.sched_getaffinity(0)),
            "sample": f"{steps} velocity-Verlet steps of the N={len(pos4)} state, cell list rebuilt every step"}
 

@@ -1,6 +1,7 @@
 /*
  * Algorithm-matched CPU baseline: cell-list LJ molecular dynamics on the
- * host cores (OpenMP), in FP32 (cc_run_f32) and FP64 (cc_run_f64). It is a
+ * host cores (OpenMP threads, SIMD pair loops), in FP32 (cc_run_f32) and FP64
+ * (cc_run_f64). It is a
  * performance reference for the GPU library, independent of it and of the
  * brute-force oracle; a test pins its forces to the oracle's.
  */
