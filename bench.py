@@ -590,7 +590,65 @@ def cpu_baseline(pos4, box, target_s):
         "kind": "oracle",
         "sample": f"{rows_done} uniformly sampled force rows of the N={n} state, each against all N atoms "
                   f"(FP64 brute force, minimum image), {el:.1f} s on the host; an oracle step costs one row per atom",
+        "more": oracle_timings(pos4, box),
     }
+
+
+_ONE_CORE_ROWS = """
+import json, sys, time
+import numpy as np
+import oracle
+pos4 = np.load(sys.argv[1])
+p = oracle.params(float(sys.argv[2]))
+rows = np.random.default_rng(7).choice(len(pos4), size=int(sys.argv[3]), replace=False)
+oracle.forces_rows(p, pos4, rows[:8])
+t0 = time.perf_counter()
+oracle.forces_rows(p, pos4, rows)
+print(json.dumps({"rows": len(rows), "seconds": time.perf_counter() - t0, "cores": oracle.num_threads()}))
+"""
+
+
+def oracle_timings(pos4, box):
+    """The oracle's other timings: one core on rows of the same state (a
+    child process with one OpenMP thread), the full 100 steps of the N = 4,000
+    workload, and 4,096 force rows of the N = 2,048,000 state."""
+    import subprocess
+    import sys
+    import tempfile
+
+    import numpy as np
+
+    import ljsynth
+    import oracle
+
+    out = {}
+    with tempfile.TemporaryDirectory() as tmp:
+        f = os.path.join(tmp, "pos4.npy")
+        np.save(f, pos4)
+        env = dict(os.environ, OMP_NUM_THREADS="1", PYTHONPATH=ROOT)
+        res = subprocess.run([sys.executable, "-c", _ONE_CORE_ROWS, f, repr(float(box)), "1024"], env=env,
+                             capture_output=True, text=True, timeout=300, check=True)
+        r = json.loads(res.stdout.strip().splitlines()[-1])
+        out["one_core"] = {"value": r["rows"] / r["seconds"], "unit": "atom-steps/s", "cores": r["cores"],
+                           "sample": f"{r['rows']} force rows of the N={len(pos4)} state in {r['seconds']:.1f} s"}
+    w = ljsynth.WORKLOADS["lj4k"]
+    p4, v4, b4 = ljsynth.make_state(w)
+    p = oracle.params(b4, dt=w.dt)
+    t0 = time.perf_counter()
+    oracle.run(p, p4, v4, w.steps)
+    t = time.perf_counter() - t0
+    out["lj4k_full_run"] = {"value": w.n * w.steps / t, "unit": "atom-steps/s", "cores": oracle.num_threads(),
+                            "sample": f"all {w.steps} velocity-Verlet steps of N={w.n} in {t:.2f} s"}
+    w = ljsynth.WORKLOADS["lj2m"]
+    p2, _, b2 = ljsynth.make_state(w)
+    rows = np.random.default_rng(9).choice(w.n, size=4096, replace=False)
+    p = oracle.params(b2)
+    t0 = time.perf_counter()
+    oracle.forces_rows(p, p2, rows)
+    t = time.perf_counter() - t0
+    out["lj2m_rows"] = {"value": len(rows) / t, "unit": "atom-steps/s", "cores": oracle.num_threads(),
+                        "sample": f"{len(rows)} force rows of the N={w.n} state in {t:.1f} s"}
+    return out
 
 
 def main():
