@@ -272,6 +272,66 @@ def test_backward_modes_bitwise_equal(wl, nsteps, every):
         assert got[3] == ref[3] and got[4] == ref[4], mode
 
 
+@pytest.mark.parametrize("waves,tile", [(1, 0), (4, 192)])
+def test_step_path_equals_recomputed_path(waves, tile):
+    """md_step_path keeps, from the state after step 0, bitwise the path that
+    md_adjoint_recompute rebuilds from that state's checkpoint (positions in
+    cell order with the user index, cell offsets), and ends on the state
+    md_step reaches; md_adjoint_path over the kept path equals
+    md_adjoint_segment from the checkpoint, bitwise, with one or four
+    wavefronts per cell and the formula's or a 192-atom LDS tile."""
+    torch = _torch()
+    from paper_0709_3225_amd import _lib as L, LJSystem
+
+    w = ljsynth.WORKLOADS["lj4k"]
+    pos4, vel4, box = ljsynth.make_state(w, jitter_amp=0.05, shuffle=True)
+    n, k = len(pos4), 7
+    _say(f"step path vs recompute n={n} steps={k} waves={waves} tile={tile}")
+    nc = LJSystem(n, box).cells_per_dim
+    mk = lambda: (torch.empty((k, n, 4), dtype=torch.float32, device="cuda"),
+                  torch.full((k, nc ** 3 + 1), -1, dtype=torch.int32, device="cuda"))
+    a = LJSystem(n, box, dt=w.dt, waves_per_cell=waves, tile_cap=tile)
+    a.load(_dev(pos4), _dev(vel4))
+    cp, cv = a.state()
+    cp, cv = cp.contiguous(), cv.contiguous()
+    path_a, start_a = mk()
+    L.md_step_path(a.params, a.ws, k, path_a, start_a)
+    assert a.check() == 0
+    b = LJSystem(n, box, dt=w.dt, waves_per_cell=waves, tile_cap=tile)
+    path_b, start_b = mk()
+    L.md_adjoint_recompute(b.params, b.ws, cp, cv, k, path_b, start_b)
+    assert b.check() == 0
+    assert torch.equal(start_a, start_b)
+    assert torch.equal(path_a, path_b)
+    # the workspace ends as after md_step
+    c = LJSystem(n, box, dt=w.dt, waves_per_cell=waves, tile_cap=tile)
+    c.load(_dev(pos4), _dev(vel4))
+    c.step(k)
+    pa, va = a.state()
+    pc, vc = c.state()
+    assert torch.equal(pa, pc) and torch.equal(va, vc)
+    # the sweep over the kept path against the segment call
+    rng = np.random.default_rng(12)
+    lr0, lv0 = rng.standard_normal((n, 4)), rng.standard_normal((n, 4))
+    out = []
+    for kept in (True, False):
+        lr, lv = _dev(lr0), _dev(lv0)
+        th = torch.zeros(2, dtype=torch.float64, device="cuda")
+        if kept:
+            L.md_adjoint_path(a.params, a.ws, 2, k, path_a, start_a, lr, lv, th)
+            assert a.check() == 0
+        else:
+            path, start = mk()
+            L.md_adjoint_segment(b.params, b.ws, cp, cv, 2, k, path, start, lr, lv, th)
+            assert b.check() == 0
+        out.append((lr, lv, th))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+    assert torch.equal(out[0][2], out[1][2])
+    # md_adjoint_path left the workspace's state in place
+    pa2, va2 = a.state()
+    assert torch.equal(pa, pa2) and torch.equal(va, va2)
+
+
 @pytest.mark.parametrize("first_step", [0, 3])
 def test_segment_equals_composed_calls(first_step):
     """md_adjoint_segment is the composition of the public calls it stands
