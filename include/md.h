@@ -15,7 +15,9 @@
  *   - velocity-Verlet time integration (section 2).
  *
  * Conventions for every entry point:
- *   - All functions are C ABI, never throw, and return an md_status.
+ *   - All functions are C ABI and never throw; all return an md_status
+ *     except the queries md_workspace_bytes and md_tile_capacity (0 for
+ *     invalid parameters), md_last_error and md_status_name.
  *   - Pointers named *_dev, ws and every particle array are DEVICE pointers
  *     owned by the caller; the library never allocates or frees memory.
  *   - Work is enqueued asynchronously on `stream` (0 = the null stream);
