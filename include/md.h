@@ -264,6 +264,15 @@ md_status md_step_nlist(const md_params* p, void* ws, size_t ws_bytes, int32_t n
 md_status md_energy_virial(const md_params* p, void* ws, size_t ws_bytes, double* out3_dev,
                            hipStream_t stream);
 
+/*
+ * md_energy_virial plus the temperature and the pressure of the state:
+ * out5_dev[0..2] = U, K, W as there, out5_dev[3] = T = 2 K / (3 N - 3)
+ * (k_B = 1, momentum conserved; 0 for N = 1) and out5_dev[4] =
+ * P = (2 K + W) / (3 V), V = L^3 (the virial pressure). Device doubles, FP64
+ * from the same fixed-order sums.
+ */
+md_status md_thermo(const md_params* p, void* ws, size_t ws_bytes, double* out5_dev, hipStream_t stream);
+
 /* Copy the current positions (wrapped) and velocities out in user order;
  * either pointer may be NULL. float4 [n], w = 0. */
 md_status md_get_state(const md_params* p, const void* ws, size_t ws_bytes, float* pos4_dev,

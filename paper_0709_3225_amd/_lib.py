@@ -41,6 +41,7 @@ SYMBOLS = (
     "md_step_list",
     "md_step_nlist",
     "md_energy_virial",
+    "md_thermo",
     "md_get_state",
     "md_neighbors",
     "md_neighbors_lists",
@@ -142,6 +143,7 @@ def lib():
         L.md_step_list.argtypes = [P, vp, sz, i32, i32, i32, vp, vp]
         L.md_step_nlist.argtypes = [P, vp, sz, i32, i32, i32, vp, vp]
         L.md_energy_virial.argtypes = [P, vp, sz, vp, vp]
+        L.md_thermo.argtypes = [P, vp, sz, vp, vp]
         L.md_get_state.argtypes = [P, vp, sz, vp, vp, vp]
         L.md_neighbors.argtypes = [P, vp, sz, vp, vp, i32, vp]
         L.md_neighbors_lists.argtypes = [P, vp, sz, vp, vp, i32, i32, vp]
@@ -167,8 +169,9 @@ def lib():
         L.md_batch_graph_create.argtypes = [P, R, i32, vp, sz, i32, i32, vp, vp, ctypes.POINTER(vp)]
         L.md_graph_launch.argtypes = [vp, vp]
         L.md_graph_destroy.argtypes = [vp]
-        for name in ("md_cell_grid", "md_build_cells", "md_forces", "md_forces_noalloc", "md_step", "md_step_every", "md_step_list", "md_energy_virial",
-                     "md_get_state", "md_neighbors", "md_neighbors_lists", "md_cell_lists", "md_check", "md_adjoint_kick",
+        for name in ("md_cell_grid", "md_build_cells", "md_forces", "md_forces_noalloc", "md_step",
+                     "md_step_every", "md_step_list", "md_energy_virial", "md_thermo", "md_get_state",
+                     "md_neighbors", "md_neighbors_lists", "md_cell_lists", "md_check", "md_adjoint_kick",
                      "md_adjoint_drift", "md_adjoint_segment", "md_adjoint_recompute",
                      "md_adjoint_path", "md_step_path", "md_loss_grad", "md_loss", "md_adjoint_seed",
                      "md_batch_build", "md_batch_forces", "md_batch_step",
@@ -338,6 +341,14 @@ def md_energy_virial(p: MDParams, ws, out3, stream=None):
     _check(lib().md_energy_virial(ctypes.byref(p), wp, wn, _ptr(out3, "out3", torch.float64, (3,)),
                                   _stream(stream)))
 
+
+
+def md_thermo(p: MDParams, ws, out5, stream=None):
+    """out5 = (U, K, W, T, P) in FP64 on the device (md_thermo)."""
+    import torch
+
+    wp, wn = _ws(ws)
+    _check(lib().md_thermo(ctypes.byref(p), wp, wn, _ptr(out5, "out5", torch.float64, (5,)), _stream(stream)))
 
 def md_get_state(p: MDParams, ws, pos4=None, vel4=None, stream=None):
     import torch

@@ -691,7 +691,10 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ e, int n
         }
     }
 }
-// LOSS: out3[0] = kcoef K + wcoef W instead of (U, K, W).
+// LOSS: out3[0] = kcoef K + wcoef W instead of (U, K, W). With kcoef and
+// wcoef nonzero otherwise, also out3[3] = kcoef K and out3[4] = wcoef (2 K + W)
+// (the temperature and the pressure, with kcoef = 2 / (3 N - 3) and
+// wcoef = 1 / (3 V)).
 template <bool LOSS>
 __global__ void __launch_bounds__(kFinalBlock) k_energy_final(SimArgs a, double* out3, bool from_step, double kcoef,
                                                               double wcoef) {
@@ -719,6 +722,10 @@ __global__ void __launch_bounds__(kFinalBlock) k_energy_final(SimArgs a, double*
             out3[0] = 0.5 * su[0];
             out3[1] = sk[0];
             out3[2] = 0.5 * sw[0];
+            if (wcoef != 0.0) {
+                out3[3] = kcoef * sk[0];
+                out3[4] = wcoef * (2.0 * sk[0] + 0.5 * sw[0]);
+            }
         }
     }
 }
@@ -867,6 +874,11 @@ hipError_t launch_nlist_forces(const SimArgs& a_in, bool bin, int par, hipStream
 
 hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st) {
     hipLaunchKernelGGL(k_energy_final<false>, dim3(1), dim3(kFinalBlock), 0, st, a, out3, true, 0.0, 0.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_thermo_final(const SimArgs& a, double t_coef, double p_coef, double* out5, hipStream_t st) {
+    hipLaunchKernelGGL(k_energy_final<false>, dim3(1), dim3(kFinalBlock), 0, st, a, out5, true, t_coef, p_coef);
     return hipGetLastError();
 }
 

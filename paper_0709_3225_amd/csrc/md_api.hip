@@ -862,6 +862,21 @@ md_status md_energy_virial(const md_params* p, void* ws, size_t ws_bytes, double
     return MD_OK;
 }
 
+md_status md_thermo(const md_params* p, void* ws, size_t ws_bytes, double* out5, hipStream_t stream) {
+    Layout L{};
+    md_status s = make_layout(p, L);
+    if (s != MD_OK) return s;
+    if ((s = check_ws(L, ws, ws_bytes)) != MD_OK) return s;
+    if (!out5) return fail(MD_ERR_ARG, "output is NULL");
+    const SimArgs a = make_args(p, L, ws);
+    const double box = static_cast<double>(p->box);
+    const double t_coef = p->n > 1 ? 2.0 / (3.0 * static_cast<double>(p->n) - 3.0) : 0.0;
+    const double p_coef = 1.0 / (3.0 * box * box * box);
+    MD_TRY_HIP(launch_forces(a, false, true, false, false, false, 0, stream), "energy pass");
+    MD_TRY_HIP(launch_thermo_final(a, t_coef, p_coef, out5, stream), "thermo");
+    return MD_OK;
+}
+
 md_status md_get_state(const md_params* p, const void* ws, size_t ws_bytes, float* pos4, float* vel4,
                        hipStream_t stream) {
     Layout L{};

@@ -159,6 +159,8 @@ hipError_t launch_forces_record(const SimArgs& a, bool energy, bool bin, int par
 hipError_t launch_nlist_forces(const SimArgs& a, bool bin, int par, hipStream_t st);
 hipError_t launch_forces_list(const SimArgs& a, bool energy, bool record, bool bin, int par, hipStream_t st);
 hipError_t launch_energy_final(const SimArgs& a, double* out3, hipStream_t st);
+// U, K, W as launch_energy_final, then out5[3] = t_coef K, out5[4] = p_coef (2 K + W).
+hipError_t launch_thermo_final(const SimArgs& a, double t_coef, double p_coef, double* out5, hipStream_t st);
 // out[0] = kcoef K + wcoef W from the partials of an energy pass.
 hipError_t launch_loss_final(const SimArgs& a, double kcoef, double wcoef, double* out, hipStream_t st);
 hipError_t launch_gather_user(const SimArgs& a, float4* pos_out, float4* vel_out, float4* force_out,

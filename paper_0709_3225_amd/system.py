@@ -94,6 +94,13 @@ class LJSystem:
         L.md_energy_virial(self.params, self.ws, out)
         return out
 
+    def thermo(self) -> torch.Tensor:
+        """(U, K, W, T, P) of the current state, FP64 on the device: T =
+        2K / (3N - 3), P = (2K + W) / (3V) (md_thermo)."""
+        out = torch.empty(5, dtype=torch.float64, device=self.device)
+        L.md_thermo(self.params, self.ws, out)
+        return out
+
     def state(self):
         pos = torch.empty((self.n, 4), dtype=torch.float32, device=self.device)
         vel = torch.empty((self.n, 4), dtype=torch.float32, device=self.device)

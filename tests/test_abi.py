@@ -132,6 +132,7 @@ def test_workspace_and_pointer_checks_on_host():
     assert lib.md_check(None, 0, None, None) == _lib.MD_ERR_WORKSPACE
     assert b"workspace" in lib.md_last_error()
     assert lib.md_loss(ctypes.byref(p), fake, need, None, None) == _lib.MD_ERR_ARG
+    assert lib.md_thermo(ctypes.byref(p), fake, need, None, None) == _lib.MD_ERR_ARG
     assert lib.md_adjoint_seed(ctypes.byref(p), fake, need, ctypes.c_float(1.0), fake, fake, None, None) \
         == _lib.MD_ERR_ARG  # the two adjoint vectors alias
 

@@ -640,6 +640,30 @@ def test_waves_per_cell_batched(orc):
         off += len(p4)
 
 
+@pytest.mark.parametrize("case", ["lj4k_jitter_shuffled", "lj32k_jitter", "fluid_rho0.4_ragged"])
+def test_thermo_temperature_and_pressure(case, orc):
+    """md_thermo: U, K, W bitwise those of md_energy_virial, and T =
+    2K / (3N - 3), P = (2K + W) / (3V) against the oracle's K and W."""
+    pos4, box = CASES[case]()
+    n = len(pos4)
+    _say(f"thermo {case} n={n}")
+    vel4 = np.zeros_like(pos4)
+    vel4[:, :3] = np.random.default_rng(8).normal(scale=0.8, size=(n, 3))
+    s = _system(n, box)
+    s.load(_dev(pos4), _dev(vel4))
+    t5 = s.thermo().cpu().numpy()
+    e3 = s.energy().cpu().numpy()
+    assert s.check() == 0
+    assert np.array_equal(t5[:3], e3)
+    p = orc.params(box)
+    _, U, W = orc.forces(p, pos4)
+    K = orc.kinetic(p, vel4)
+    V = float(np.float32(box)) ** 3
+    assert abs(t5[3] - 2.0 * K / (3 * n - 3)) <= ENERGY_TOL * (2.0 * K / (3 * n - 3))
+    pref = (2.0 * K + W) / (3.0 * V)
+    assert abs(t5[4] - pref) <= ENERGY_TOL * (2.0 * K + abs(W)) / (3.0 * V)
+
+
 def test_edge_small_systems(orc):
     _say("edge: one atom, two atoms across the boundary")
     s, f, e = gpu_forces(np.array([[1.0, 2.0, 3.0, 0.0]], np.float32), 6.0)
