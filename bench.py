@@ -90,9 +90,10 @@ def batched_leg(torch, nsteps=200, seq_steps=20):
 
     b = BatchedLJ(table)
     t_batch = graph_time(b)
-    # cell grids picked per replica-size bucket by measurement, same run
-    cms, rep = tune_batch(table, pos, vel)
-    bt = BatchedLJ([(n, box, cm) for (n, box), cm in zip(table, cms)])
+    # cell grid, wavefronts per cell and LDS tile picked per replica-size
+    # bucket by measurement, same run
+    cms, rep = tune_batch(table, pos, vel, waves=(1, 4), tiles=(0, -64))
+    bt = BatchedLJ(rep["table"])
     t_tuned = graph_time(bt)
     del bt
     # the same replicas one after another (md_step per replica)
@@ -119,7 +120,10 @@ def batched_leg(torch, nsteps=200, seq_steps=20):
         "sequential_value": seq, "ratio_vs_sequential": value / seq,
         "autotuned": {"value": ntot * nsteps / t_tuned, "ms_per_launch": t_tuned * 1e3,
                       "tune_seconds": rep["seconds"], "buckets": len(rep["buckets"]),
-                      "replicas_on_coarser_grids": sum(1 for cm in cms if cm > 0.0)},
+                      "knobs": "cell side x waves per cell (1, 4) x LDS tile (formula, -64 atoms) per bucket",
+                      "replicas_on_coarser_grids": sum(1 for cm in cms if cm > 0.0),
+                      "replicas_on_4_waves": sum(1 for r in rep["table"] if r[3] == 4),
+                      "replicas_on_smaller_tiles": sum(1 for r in rep["table"] if r[4] != 0)},
     }
 
 

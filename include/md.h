@@ -439,21 +439,26 @@ md_status md_adjoint_seed(const md_params* p, void* ws, size_t ws_bytes, float s
  * captures a whole multi-step run into one graph that md_graph_launch starts
  * with a single call. Each replica follows exactly the arithmetic of md_step
  * on that system alone (same cell grid, LDS pass length and summation order),
- * so its results are bitwise those of a solo run with the same
- * waves_per_cell (taken from p for the whole batch).
+ * so its results are bitwise those of a solo run with the same cell side,
+ * wavefronts per cell and LDS tile. The force pass runs one launch per class
+ * of replicas sharing a tile band and a wavefront count.
  *
  * Shared parameters (epsilon, sigma, mass, rc_over_sigma, dt, shift_mode)
- * come from p; p->n and p->box are ignored. The minimum cell side is the
- * replica's own cell_min when that is nonzero, else p->cell_min; the grid
- * rule is that of md_cell_grid. Replica b owns atoms
+ * come from p; p->n, p->box and p->tile_cap are ignored. Per replica: the
+ * minimum cell side is its own cell_min when that is nonzero, else
+ * p->cell_min (the grid rule is that of md_cell_grid); the wavefronts per
+ * cell its own waves_per_cell when nonzero, else p->waves_per_cell; the LDS
+ * tile its own tile_cap when nonzero, else the formula of md_params.tile_cap. Replica b owns atoms
  * [A_b, A_b + n_b) of the concatenated float4 arrays, A_b = n_0 + ... +
  * n_(b-1); every replica needs box >= 2 r_c. The table is re-validated on
  * every call and must not change between calls on one workspace.
  */
 typedef struct md_replica {
-    int32_t n;       /* atoms of this replica, >= 1 */
-    float box;       /* its cubic periodic box side */
-    float cell_min;  /* its minimum cell side (finite, >= 0); 0 takes p->cell_min */
+    int32_t n;              /* atoms of this replica, >= 1 */
+    float box;              /* its cubic periodic box side */
+    float cell_min;         /* its minimum cell side (finite, >= 0); 0 takes p->cell_min */
+    int32_t waves_per_cell; /* 0 (p->waves_per_cell), 1, 2 or 4 */
+    int32_t tile_cap;       /* 0 (the formula) or a multiple of 64 in [128, 2048] */
 } md_replica;
 
 /* Workspace bytes for this batch (0 if invalid). Host only. */

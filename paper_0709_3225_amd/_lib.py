@@ -95,17 +95,21 @@ class MDParams(ctypes.Structure):
 
 
 class MDReplica(ctypes.Structure):
-    _fields_ = [("n", ctypes.c_int32), ("box", ctypes.c_float), ("cell_min", ctypes.c_float)]
+    _fields_ = [("n", ctypes.c_int32), ("box", ctypes.c_float), ("cell_min", ctypes.c_float),
+                ("waves_per_cell", ctypes.c_int32), ("tile_cap", ctypes.c_int32)]
 
 
 def replica_table(reps):
-    """ctypes array of md_replica from (n, box) or (n, box, cell_min) tuples
-    (cell_min 0: the batch's shared cell_min)."""
+    """ctypes array of md_replica from (n, box[, cell_min[, waves_per_cell[,
+    tile_cap]]]) tuples (0 for any of the last three: the batch's shared
+    cell_min and waves_per_cell, the formula's tile)."""
     arr = (MDReplica * len(reps))()
     for i, r in enumerate(reps):
         arr[i].n = int(r[0])
         arr[i].box = float(r[1])
         arr[i].cell_min = float(r[2]) if len(r) > 2 else 0.0
+        arr[i].waves_per_cell = int(r[3]) if len(r) > 3 else 0
+        arr[i].tile_cap = int(r[4]) if len(r) > 4 else 0
     return arr
 
 

@@ -19,9 +19,12 @@ from . import _lib as L
 class BatchedLJ:
     def __init__(self, replicas, *, epsilon=1.0, sigma=1.0, mass=1.0, rc_over_sigma=2.5, dt=0.005, cell_min=0.0,
                  shift_mode=0, waves_per_cell=0, device="cuda"):
-        """replicas: sequence of (n, box) or (n, box, cell_min); a replica's
-        nonzero cell_min replaces the shared one (tune.tune_batch picks them)."""
-        self.replicas = [(int(r[0]), float(r[1]), float(r[2]) if len(r) > 2 else 0.0) for r in replicas]
+        """replicas: sequence of (n, box[, cell_min[, waves_per_cell[,
+        tile_cap]]]); a replica's nonzero cell_min and waves_per_cell replace
+        the shared ones and its nonzero tile_cap the formula's tile
+        (tune.tune_batch picks them)."""
+        self.replicas = [(int(r[0]), float(r[1]), float(r[2]) if len(r) > 2 else 0.0,
+                          int(r[3]) if len(r) > 3 else 0, int(r[4]) if len(r) > 4 else 0) for r in replicas]
         self.count = len(self.replicas)
         self.table = L.replica_table(self.replicas)
         self.params = L.make_params(1, 1.0, epsilon, sigma, mass, rc_over_sigma, dt, cell_min, shift_mode, 0,

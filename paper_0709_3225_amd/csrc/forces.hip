@@ -888,10 +888,11 @@ hipError_t launch_loss_final(const SimArgs& a, double kcoef, double wcoef, doubl
 }
 
 hipError_t launch_batch_forces(const SimArgs& base_in, const Replica* reps, const int* cell_rep, const int* cells,
-                               int ncl, int tile_cap, bool kick, bool energy, bool write_force, bool drift, int par,
-                               hipStream_t st) {
+                               int ncl, int tile_cap, int waves, bool kick, bool energy, bool write_force, bool drift,
+                               int par, hipStream_t st) {
     SimArgs base = base_in;
     base.par = par;
+    base.waves = waves;
     const dim3 g(ncl), b(kWave * base.waves);
     const size_t lds = sizeof(float4) * cell_lds_entries(tile_cap, base.waves);
 #define MD_FORCES(K, E, W, D)                                                                                      \

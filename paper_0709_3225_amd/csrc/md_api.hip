@@ -441,15 +441,20 @@ md_status sweep_impl(const SimArgs& a, const md_params* p, int32_t first_step, i
 // ---- batches of independent replicas -------------------------------------
 
 // The batched force pass runs one launch per tile class: replicas whose
-// neighbourhood tile (tile_capacity) falls into the same band share a launch
-// whose LDS fits the band's largest tile, so a few replicas with crowded
-// cells do not cut the number of resident waves for all the others (about 16
-// per CU with tiles of up to 512 atoms, 9 with 1,024). Band upper bounds:
+// neighbourhood tile falls into the same band, and that take the same
+// number of wavefronts per cell, share a launch whose LDS fits the band's
+// largest tile, so a few replicas with crowded cells do not cut the number
+// of resident waves for all the others (about 16 per CU with tiles of up to
+// 512 atoms, 9 with 1,024). Band upper bounds:
 constexpr int kTileBands[] = {512, 640, 768, 1024, 2048};
 constexpr int kNumTileBands = sizeof(kTileBands) / sizeof(kTileBands[0]);
+constexpr int kWaveChoices[] = {1, 2, 4};  // wavefronts per cell, one class each
+constexpr int kNumWaveChoices = 3;
+constexpr int kNumClasses = kNumTileBands * kNumWaveChoices;
 
 struct TileClass {
     int first = 0, ncells = 0, tile_cap = 0;  // range in the class cell list; largest tile_cap
+    int waves = 1;
 };
 
 struct BatchPlan {
@@ -458,13 +463,20 @@ struct BatchPlan {
     double max_mean = 0.0;  // largest mean cell occupancy of any replica
     size_t reps = 0, atom_rep = 0, cell_rep = 0, class_cells = 0;
     std::vector<Replica> table;  // host copy of the replica table
-    TileClass classes[kNumTileBands];
+    std::vector<int> waves;      // wavefronts per cell of each replica
+    TileClass classes[kNumClasses];
 };
 
 int tile_band(int tile_cap) {
     for (int k = 0; k < kNumTileBands; ++k)
         if (tile_cap <= kTileBands[k]) return k;
-    return kNumTileBands - 1;  // tile_capacity never exceeds the last band
+    return kNumTileBands - 1;  // no tile exceeds the last band
+}
+
+// Class of a replica: its tile band and its wavefront count.
+int tile_class(int tile_cap, int waves) {
+    const int w = waves == 4 ? 2 : waves - 1;
+    return tile_band(tile_cap) * kNumWaveChoices + w;
 }
 
 constexpr int32_t kMaxReplicas = 1 << 16;
@@ -477,12 +489,21 @@ md_status batch_plan(const md_params* p, const md_replica* reps, int32_t count, 
     if (count < 1 || count > kMaxReplicas) return fail(MD_ERR_ARG, "replica count %d outside [1, 65536]", count);
     B.count = count;
     B.table.resize(count);
+    B.waves.resize(count);
     int64_t ntot = 0, ctot = 0;
     for (int32_t b = 0; b < count; ++b) {
         md_params q = *p;
         q.n = reps[b].n;
         q.box = reps[b].box;
+        q.tile_cap = 0;
         if (reps[b].cell_min != 0.f) q.cell_min = reps[b].cell_min;  // validated by make_layout
+        const int32_t rw = reps[b].waves_per_cell, rt = reps[b].tile_cap;
+        if (rw != 0 && rw != 1 && rw != 2 && rw != 4)
+            return fail(MD_ERR_ARG, "replica %d: waves_per_cell must be 0, 1, 2 or 4 (got %d)", b, rw);
+        if (rt != 0 && (rt < 128 || rt > 2048 || rt % 64 != 0))
+            return fail(MD_ERR_ARG, "replica %d: tile_cap must be 0 or a multiple of 64 in [128, 2048] (got %d)", b,
+                        rt);
+        if (rw != 0) q.waves_per_cell = rw;
         Layout Lb{};
         const md_status s = make_layout(&q, Lb);
         if (s != MD_OK) {
@@ -496,7 +517,8 @@ md_status batch_plan(const md_params* p, const md_replica* reps, int32_t count, 
         r.nc = Lb.nc;
         r.ncells = Lb.ncells;
         r.cbase = static_cast<int>(ctot);
-        r.tile_cap = tile_capacity(q.n, Lb.ncells);
+        r.tile_cap = rt != 0 ? rt : tile_capacity(q.n, Lb.ncells);
+        B.waves[b] = waves_per_cell(&q);
         r.box = q.box;
         r.s = Lb.s;
         r.inv_s = Lb.inv_s;
@@ -507,9 +529,11 @@ md_status batch_plan(const md_params* p, const md_replica* reps, int32_t count, 
         if (ntot > kMaxAtoms) return fail(MD_ERR_ARG, "batch holds more than 2^27 atoms");
         if (ctot > (int64_t{1} << 30)) return fail(MD_ERR_ARG, "batch holds more than 2^30 cells");
     }
-    // tile classes: each band's replicas in table order, bands one after another
-    for (const Replica& r : B.table) {
-        TileClass& t = B.classes[tile_band(r.tile_cap)];
+    // tile classes: each class's replicas in table order, classes one after another
+    for (int k = 0; k < kNumClasses; ++k) B.classes[k].waves = kWaveChoices[k % kNumWaveChoices];
+    for (int32_t b = 0; b < count; ++b) {
+        const Replica& r = B.table[b];
+        TileClass& t = B.classes[tile_class(r.tile_cap, B.waves[b])];
         t.ncells += r.ncells;
         t.tile_cap = std::max(t.tile_cap, r.tile_cap);
     }
@@ -518,9 +542,10 @@ md_status batch_plan(const md_params* p, const md_replica* reps, int32_t count, 
         t.first = first;
         first += t.ncells;
     }
-    int fill[kNumTileBands] = {};
-    for (Replica& r : B.table) {
-        const int k = tile_band(r.tile_cap);
+    int fill[kNumClasses] = {};
+    for (int32_t b = 0; b < count; ++b) {
+        Replica& r = B.table[b];
+        const int k = tile_class(r.tile_cap, B.waves[b]);
         r.lbase = B.classes[k].first + fill[k];
         fill[k] += r.ncells;
     }
@@ -580,7 +605,7 @@ hipError_t batch_forces(const BatchPlan& B, const BatchArgs& ba, bool kick, bool
     for (const TileClass& t : B.classes) {
         if (t.ncells == 0) continue;
         const hipError_t e = launch_batch_forces(ba.base, ba.reps, ba.cell_rep, ba.class_cells + t.first, t.ncells,
-                                                 t.tile_cap, kick, energy, write_force, drift, par, st);
+                                                 t.tile_cap, t.waves, kick, energy, write_force, drift, par, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

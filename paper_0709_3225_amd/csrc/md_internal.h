@@ -196,10 +196,11 @@ hipError_t launch_batch_load(const SimArgs& base, const Replica* reps, const int
                              const float4* vel_in, hipStream_t st);
 hipError_t launch_batch_integrate(const SimArgs& base, const Replica* reps, const int* atom_rep, hipStream_t st);
 // One launch over the ncl global cells listed at cells (a tile class), with
-// LDS for tile_cap staged atoms (at least every listed replica's tile_cap).
+// LDS for tile_cap staged atoms (at least every listed replica's tile_cap)
+// and waves wavefronts per cell.
 hipError_t launch_batch_forces(const SimArgs& base, const Replica* reps, const int* cell_rep, const int* cells,
-                               int ncl, int tile_cap, bool kick, bool energy, bool write_force, bool drift, int par,
-                               hipStream_t st);
+                               int ncl, int tile_cap, int waves, bool kick, bool energy, bool write_force, bool drift,
+                               int par, hipStream_t st);
 hipError_t launch_batch_energy_final(const SimArgs& base, const Replica* reps, int count, double* out, hipStream_t st);
 
 }  // namespace mdlj

@@ -1,4 +1,4 @@
-"""Cell-side autotuner for batches of replicas.
+"""Autotuner for batches of replicas and single systems.
 
 The only geometric choice the method leaves open is the cell side: section 3
 asks for cells of side at least r_c, and section 3.2 takes the finest such
@@ -9,7 +9,8 @@ pass may also split a cell's candidates over two or four wavefronts
 (md_params.waves_per_cell), which pays only where the grid has too few cells
 to fill the GPU, and its LDS tile (md_params.tile_cap) trades passes over
 large neighbourhoods against wavefronts per CU; tune_system measures all
-three knobs on one system.
+three knobs on one system, and tune_batch, given candidate wavefront counts
+and tile offsets, per replica-size bucket of a batch.
 
 Replicas are grouped into size buckets (their default grid and its mean
 occupancy). For each bucket the tuner times batched steps of a probe made of
@@ -66,10 +67,10 @@ def bucket_key(n: int, nc0: int):
     return nc0, int(round(n / nc0 ** 3))
 
 
-def _time_probe(n, box, cell_min, p4, v4, copies, steps, warmup, repeats, shared, stream):
+def _time_probe(n, box, cell_min, p4, v4, copies, steps, warmup, repeats, shared, stream, waves=0, tile=0):
     """Seconds per atom-step of a probe batch: the fastest of ``repeats``
     timed runs of ``steps`` steps after ``warmup`` untimed ones."""
-    table = [(n, box, cell_min)] * copies
+    table = [(n, box, cell_min, waves, tile)] * copies
     b = BatchedLJ(table, **shared)
     pos = p4.repeat(copies, 1).contiguous()
     vel = v4.repeat(copies, 1).contiguous()
@@ -89,16 +90,35 @@ def _time_probe(n, box, cell_min, p4, v4, copies, steps, warmup, repeats, shared
     return best / (steps * n * copies)
 
 
+def _offset_tile(n, box, cell_min, offset, shared):
+    """md_params.tile_cap for the formula's tile of this replica plus offset
+    atoms (0: the formula itself, or an offset that leaves [128, 2048])."""
+    if offset == 0:
+        return 0
+    q = {k: v for k, v in shared.items() if k in ("epsilon", "sigma", "mass", "rc_over_sigma", "dt", "shift_mode")}
+    t = L.md_tile_capacity(L.make_params(n, box, cell_min=cell_min, **q)) + int(offset)
+    return t if 128 <= t <= 2048 and t % 64 == 0 else 0
+
+
 def tune_batch(replicas, pos4: torch.Tensor, vel4: torch.Tensor, *, epsilon=1.0, sigma=1.0, mass=1.0,
-               rc_over_sigma=2.5, dt=0.005, shift_mode=0, extra=1, min_atoms=131072, steps=10, warmup=3,
-               repeats=3, min_gain=0.03):
-    """Pick a cell grid per replica.
+               rc_over_sigma=2.5, dt=0.005, shift_mode=0, extra=1, waves=(1,), tiles=(0,), min_atoms=131072,
+               steps=10, warmup=3, repeats=3, min_gain=0.03):
+    """Pick a cell grid, and optionally the wavefronts per cell and the LDS
+    tile, per replica-size bucket.
 
     replicas: sequence of (n, box); pos4/vel4: the batch's concatenated float4
     state on the GPU (each bucket's probe copies one member's own atoms).
-    Returns (cell_mins, report): cell_mins[b] goes into replica b's table
-    entry; report lists, per bucket, the grids tried with their measured
-    seconds per atom-step and the choice."""
+    Candidates per bucket are its grid_options x ``waves`` x ``tiles`` (tile
+    offsets in atoms from each grid's formula tile, 0 being the formula); the
+    defaults search the grid only. A candidate replaces the default (default
+    grid, the first wavefront count, the formula's tile) only if it is faster
+    per atom-step by ``min_gain``, and its tile replaces the formula's only
+    if it also beats that on the same grid and wavefront count by
+    ``min_gain``. Returns (cell_mins, report): cell_mins[b] goes into replica
+    b's table entry; report["table"] holds the full entries (n, box,
+    cell_min, waves_per_cell, tile_cap) for BatchedLJ (waves_per_cell 0 when
+    only one count was tried); report["buckets"] lists, per bucket, the
+    candidates with their measured seconds per atom-step and the choice."""
     shared = dict(epsilon=epsilon, sigma=sigma, mass=mass, rc_over_sigma=rc_over_sigma, dt=dt,
                   shift_mode=shift_mode)
     reps = [(int(n), float(box)) for n, box, *_ in replicas]
@@ -112,6 +132,7 @@ def tune_batch(replicas, pos4: torch.Tensor, vel4: torch.Tensor, *, epsilon=1.0,
     stream = torch.cuda.Stream()
     t_start = time.perf_counter()
     cell_mins = [0.0] * len(reps)
+    table = [(n, box, 0.0, 0, 0) for n, box in reps]
     report = []
     for key, members in sorted(buckets.items()):
         i = members[0]
@@ -121,23 +142,42 @@ def tune_batch(replicas, pos4: torch.Tensor, vel4: torch.Tensor, *, epsilon=1.0,
         copies = max(1, math.ceil(min_atoms / n))
         tried = []
         for nc, cm in options[i]:
-            t = _time_probe(n, box, cm, p4, v4, copies, steps, warmup, repeats, shared, stream)
-            tried.append({"cells_per_dim": nc, "cell_min": cm, "s_per_atom_step": t})
+            for wv in waves:
+                seen = set()
+                for off in tiles:
+                    tc = _offset_tile(n, box, cm, off, shared)
+                    if tc in seen:
+                        continue
+                    seen.add(tc)
+                    t = _time_probe(n, box, cm, p4, v4, copies, steps, warmup, repeats, shared, stream,
+                                    wv if len(waves) > 1 else 0, tc)
+                    tried.append({"cells_per_dim": nc, "cell_min": cm, "waves_per_cell": wv,
+                                  "tile_offset": off if tc else 0, "tile_cap": tc, "s_per_atom_step": t})
         best = tried[0]
         for cand in tried[1:]:
             if cand["s_per_atom_step"] < best["s_per_atom_step"] * (1.0 - min_gain):
                 best = cand
+        same = [t for t in tried if t["cell_min"] == best["cell_min"] and t["waves_per_cell"] == best["waves_per_cell"]
+                and t["tile_cap"] == 0]
+        if same and best["s_per_atom_step"] >= same[0]["s_per_atom_step"] * (1.0 - min_gain):
+            best = same[0]
         for j in members:
             # members share the default grid; the chosen coarser grid is
-            # re-derived for each (same n_c, its own box)
-            if best["cell_min"] == 0.0:
-                continue
-            for nc, cm in options[j]:
-                if nc == best["cells_per_dim"]:
-                    cell_mins[j] = cm
+            # re-derived for each (same n_c, its own box), and the tile from
+            # each member's own formula tile and the chosen offset
+            nj, bj = reps[j]
+            cmj = 0.0
+            if best["cell_min"] != 0.0:
+                for nc, cm in options[j]:
+                    if nc == best["cells_per_dim"]:
+                        cmj = cm
+            cell_mins[j] = cmj
+            table[j] = (nj, bj, cmj, best["waves_per_cell"] if len(waves) > 1 else 0,
+                        _offset_tile(nj, bj, cmj, best["tile_offset"], shared))
         report.append({"bucket": {"cells_per_dim": key[0], "atoms_per_cell": key[1]}, "replicas": len(members),
-                       "tried": tried, "chosen_cells_per_dim": best["cells_per_dim"]})
-    return cell_mins, {"buckets": report, "seconds": time.perf_counter() - t_start}
+                       "tried": tried, "chosen_cells_per_dim": best["cells_per_dim"],
+                       "chosen_waves_per_cell": best["waves_per_cell"], "chosen_tile_offset": best["tile_offset"]})
+    return cell_mins, {"buckets": report, "table": table, "seconds": time.perf_counter() - t_start}
 
 
 def tune_cell_min(n: int, box: float, pos4: torch.Tensor, vel4: torch.Tensor, **kw):

@@ -264,6 +264,15 @@ def test_batch_validation_on_host():
     assert lib.md_batch_graph_create(ctypes.byref(p), ok, 2, fake, need, 10, 0, None, None, ctypes.byref(g)) \
         == _lib.MD_ERR_ARG
     assert lib.md_graph_destroy(None) == 0
+    # per-replica wavefronts and tiles: valid values lay the workspace out the
+    # same way, invalid ones are refused with the replica named
+    knobs = _lib.replica_table([(100, 10.0, 0.0, 4, 192), (4000, 16.8, 0.0, 2, 0)])
+    assert lib.md_batch_workspace_bytes(ctypes.byref(p), knobs, 2) == need
+    for bad_knob in ((100, 10.0, 0.0, 3, 0), (100, 10.0, 0.0, 0, 100), (100, 10.0, 0.0, 0, 4096)):
+        t = _lib.replica_table([(4000, 16.8), bad_knob])
+        assert lib.md_batch_workspace_bytes(ctypes.byref(p), t, 2) == 0
+        assert lib.md_batch_build(ctypes.byref(p), t, 2, None, 0, None, None, None) == _lib.MD_ERR_ARG
+        assert b"replica 1" in lib.md_last_error()
 
 
 def test_batch_replica_cell_min_on_host():

@@ -83,6 +83,51 @@ def test_each_replica_bitwise_equals_solo_run():
         assert torch.equal(th[:, i, :], sth), i
 
 
+# per-replica knobs: (cell_min, waves_per_cell, tile_cap) of the SMALL replicas
+MIXED_KNOBS = [(0.0, 4, 0), (0.0, 1, 192), (0.0, 2, 0), (0.0, 4, 256), (0.0, 1, 0), (0.0, 2, 1024)]
+
+
+def test_mixed_replica_knobs_bitwise_equal_solo_runs():
+    """Replicas with their own wavefronts per cell and LDS tile (six classes
+    of tile band and wavefront count in one batch) stay bitwise equal to
+    solo runs with the same knobs, eager and through a captured graph."""
+    torch = _torch()
+    from paper_0709_3225_amd import BatchedLJ, LJSystem
+
+    ws, table, states = _small_batch()
+    knobbed = [(n, box, cm, wv, tc) for (n, box), (cm, wv, tc) in zip(table, MIXED_KNOBS)]
+    _say(f"batch with mixed knobs vs solo: {len(ws)} replicas, 20 steps")
+    pos = _cuda(np.concatenate([s[0] for s in states]))
+    vel = _cuda(np.concatenate([s[1] for s in states]))
+    b = BatchedLJ(knobbed)
+    b.load(pos, vel)
+    b.step(20)
+    bp, bv = b.state()
+    b.check()
+    stream = torch.cuda.Stream()
+    g = BatchedLJ(knobbed)
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        g.load(pos, vel)
+        graph, _ = g.make_graph(20)
+        graph.launch(stream)
+    stream.synchronize()
+    gp, gv = g.state()
+    graph.close()
+    g.check()
+    assert torch.equal(gp, bp) and torch.equal(gv, bv)
+    for i, (w, (p4, v4, box)) in enumerate(zip(ws, states)):
+        cm, wv, tc = MIXED_KNOBS[i]
+        s = LJSystem(w.n, box, cell_min=cm, waves_per_cell=wv, tile_cap=tc)
+        s.load(_cuda(p4), _cuda(v4))
+        s.step(20)
+        sp, sv = s.state()
+        s.check()
+        lo, hi = b.offsets[i], b.offsets[i + 1]
+        assert torch.equal(bp[lo:hi], sp), i
+        assert torch.equal(bv[lo:hi], sv), i
+
+
 def test_graph_replays_equal_eager_runs():
     torch = _torch()
     from paper_0709_3225_amd import BatchedLJ
@@ -292,6 +337,36 @@ def test_tune_system_picks_measured_knobs(orc):
     s.check()
     fo, _, _ = orc.forces(orc.params(box), pos4)
     assert np.linalg.norm(f - fo) <= 1e-5 * np.linalg.norm(fo)
+
+
+def test_tune_batch_per_bucket_knobs(orc):
+    """tune_batch with wavefronts and tile offsets: every bucket times grid x
+    waves x tile candidates, the returned table carries each replica's
+    choice, and the batch built from it matches the oracle on sampled
+    replicas."""
+    torch = _torch()
+    from paper_0709_3225_amd import BatchedLJ, tune_batch
+
+    ws, table, pos, vel = _replicas(12, max_fcc=8)
+    _say(f"tune batch knobs: {len(table)} replicas")
+    cms, report = tune_batch(table, _cuda(pos), _cuda(vel), waves=(1, 4), tiles=(0, 128), steps=3, warmup=1,
+                             repeats=1, min_atoms=16384)
+    assert len(report["table"]) == len(table)
+    for bk in report["buckets"]:
+        assert len(bk["tried"]) >= 2 * 2
+        assert bk["chosen_waves_per_cell"] in (1, 4) and bk["chosen_tile_offset"] in (0, 128)
+    for (n, box), (n2, box2, cm, wv, tc), c in zip(table, report["table"], cms):
+        assert (n, box) == (n2, box2) and cm == c and wv in (1, 4) and (tc == 0 or tc % 64 == 0)
+    b = BatchedLJ(report["table"])
+    b.load(_cuda(pos), _cuda(vel))
+    f = torch.empty((b.n_total, 4), dtype=torch.float32, device="cuda")
+    b.forces(f)
+    b.check()
+    for i in (0, len(table) // 2, len(table) - 1):
+        lo, hi = b.offsets[i], b.offsets[i + 1]
+        fo, _, _ = orc.forces(orc.params(table[i][1]), pos[lo:hi])
+        fb = f[lo:hi].cpu().numpy()[:, :3]
+        assert np.linalg.norm(fb - fo) <= 1e-5 * np.linalg.norm(fo), i
 
 
 def test_tile_classes_with_multipass_tiles():
