@@ -439,11 +439,12 @@ def pair_list_leg(torch, nsteps=100, warm=20, atom_lists=False):
             "value": best["value"] if best else None}
 
 
-def pair_counts(sys_, torch):
+def pair_counts(sys_, torch, chunk=64):
     """Candidate pairs the 27-cell method tests on the current state, split
     into those screened on the VALU and those screened on the matrix cores
-    (home-atom chunks of 11..16 atoms: a cell's atoms in chunks of 64, each
-    chunk against the whole neighbourhood), and the accepted ordered pairs."""
+    (home-atom chunks of 11..16 atoms: a cell's atoms in chunks of `chunk`,
+    each chunk against the whole neighbourhood; the kernels take chunks of
+    64), and the accepted ordered pairs."""
     import numpy as np
 
     start, _ = sys_.cell_lists()
@@ -456,8 +457,11 @@ def pair_counts(sys_, torch):
             for dx in (-1, 0, 1):
                 hood += np.roll(grid, shift=(dz, dy, dx), axis=(0, 1, 2))
     candidates = int((grid * hood).sum())
-    last = grid % 64  # the last chunk; full chunks of 64 take the VALU screen
+    full = grid // chunk  # full chunks: on the matrix cores if 16 atoms, else (64) the VALU
+    last = grid % chunk    # the last chunk
     mfma_home = np.where((last >= MFMA_MIN_HOME) & (last <= MFMA_MAX_HOME), last, 0)
+    if chunk == MFMA_MAX_HOME:
+        mfma_home = mfma_home + chunk * full
     mfma = int((mfma_home * hood).sum())
     counts, _ = sys_.neighbors(max_per_atom=1)  # counts only; rows truncate (flag cleared below)
     accepted = int(counts.sum().item())

@@ -165,8 +165,6 @@ __device__ __forceinline__ void kept_words(const uint4* rows, const uint4& w0, i
 // span, so an atom's list is written without atomics.
 // EXPORT: no forces; the pairs the walk accepts go to the neighbour rows of
 // ex (raw: a second tile of untranslated positions).
-static_assert(5 * kWave <= 4 * kTilePad, "one wavefront's slice partials fit the tile padding");
-
 template <bool KICK, bool ENERGY, bool WRITE, bool DRIFT, bool SKIN = false, int LIST = 0, bool EXPORT = false,
           int MW = 1>
 __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile, Neighbourhood& nb, float* red,
@@ -232,76 +230,8 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         lw0 = lwords[0];
     }
     const bool use_list = LIST == 2 && list_fits && __all(list_n <= kListSpans);
-    int n_use = 0;  // LIST 2: spans replayed (in the order LIST 1 kept them)
-    // The epilogue of home atom k on the lane that holds its sums (lead_):
-    // list length, force store, half kick, energy terms, drift and binning
-    // into the next rebuild's bucket (every lane of wavefront 0 takes part).
-    auto finish = [&](bool lead_, int k, float gx, float gy, float gz, float gu, float gw, float4 pi_,
-                      float4 vel_, float4 pref_, int lcount_) {
-        int c_next = -1;  // DRIFT: the home atom's next cell, -1 on lanes without one
-        float4 p_next = pi_, v_next = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (lead_) {
-            if (LIST == 3) {  // the atom's list length (the entries past the capacity were not kept)
-                a.ncount[k] = min(lcount_, a.nlist_cap);
-                if (lcount_ > a.nlist_cap) over = true;
-            }
-            if (!finite3(gx, gy, gz)) bad = true;
-            if (WRITE) a.force[k] = make_float4(gx, gy, gz, 0.f);
-            if (KICK || ENERGY) {
-                float4 v = vel_;
-                if (KICK) {
-                    v.x += a.hdt_m * gx;
-                    v.y += a.hdt_m * gy;
-                    v.z += a.hdt_m * gz;
-                    if (!DRIFT) a.vel0[k] = v;
-                }
-                if (ENERGY) {
-                    u_acc += static_cast<double>(gu);
-                    w_acc += static_cast<double>(gw);
-                    k_acc += static_cast<double>(a.half_m) * (static_cast<double>(v.x) * v.x +
-                                                              static_cast<double>(v.y) * v.y +
-                                                              static_cast<double>(v.z) * v.z);
-                }
-                if (DRIFT) {
-                    v_next = v;
-                    if (SKIN) {
-                        half_kick_drift_unwrapped(a, p_next, v_next, gx, gy, gz);
-                        a.pos2[k] = p_next;
-                        a.vel2[k] = v_next;
-                        if (LIST != 0) {
-                            const float ex = p_next.x - pref_.x, ey = p_next.y - pref_.y, ez = p_next.z - pref_.z;
-                            if (ex * ex + ey * ey + ez * ez > a.disp_half * a.disp_half) skin_out = true;
-                        } else {
-                            const float ex = fmaxf(fmaxf(ox - p_next.x, p_next.x - (ox + a.s)), 0.f);
-                            const float ey = fmaxf(fmaxf(oy - p_next.y, p_next.y - (oy + a.s)), 0.f);
-                            const float ez = fmaxf(fmaxf(oz - p_next.z, p_next.z - (oz + a.s)), 0.f);
-                            if (ex * ex + ey * ey + ez * ez > a.skin_half * a.skin_half) skin_out = true;
-                        }
-                    } else {
-                        c_next = half_kick_drift(a, p_next, v_next, gx, gy, gz);
-                    }
-                }
-            }
-        }
-        if (DRIFT && !SKIN && wv == 0) bin_atom(a, p_next, v_next, c_next);
-    };
-    // Home chunks. The one-wavefront kernel takes a cell's atoms 16 at a time
-    // (the matrix-core screen's width; the last chunk the remaining 1..16): a
-    // chunk of 17..64 atoms would need the VALU screen over two or three
-    // slices, and the busiest of its long per-lane walks sets the trip count.
-    // Each chunk's slice sums are added through the tile's padding (the staged
-    // atoms stay for the next chunk) and handed to lane l = atom ga + l of the chunk's
-    // group of 64 (ga a multiple of 64), and one epilogue finishes a group
-    // once its last chunk is summed (one binning pass per cell of up to 64
-    // atoms). Several wavefronts take chunks of up to 64 atoms with a
-    // reduction through LDS and an epilogue per chunk.
-    constexpr bool defer = MW == 1;
-    const int kchunk = defer ? 16 : kWave;
-    float4 pe = make_float4(0.f, 0.f, 0.f, 0.f), ve = pe, prefe = pe;  // defer: atom `lane`
-    float egx = 0.f, egy = 0.f, egz = 0.f, egu = 0.f, egw = 0.f;      // defer: its sums
-    int elc = 0;                                                      // defer: its list length
-    for (int h0 = 0; h0 < n_home; h0 += kchunk) {
-        const int nh = min(kchunk, n_home - h0);
+    for (int h0 = 0; h0 < n_home; h0 += kWave) {
+        const int nh = min(kWave, n_home - h0);
         // 11..16 home atoms: matrix-core screen, lane = (atom lane % 16, slice
         // lane / 16); otherwise the VALU screen with ns interleaved slices
         const bool mf = nh >= kMfmaMinHome && nh <= 16;  // uniform
@@ -315,19 +245,9 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
         if (act) pi = a.pos0[home_first + h0 + h];
         float4 vel = make_float4(0.f, 0.f, 0.f, 0.f);  // fetched now, used by the epilogue
-        if ((KICK || ENERGY) && lead && !defer) vel = a.vel0[home_first + h0 + h];
+        if ((KICK || ENERGY) && lead) vel = a.vel0[home_first + h0 + h];
         float4 pref = pi;  // LIST: position when the lists were recorded
-        if (LIST == 2 && SKIN && lead && !defer) pref = a.posref[home_first + h0 + h];
-        // defer: the lanes that finish this chunk's atoms fetch what the epilogue needs
-        const int ga = h0 & ~(kWave - 1);  // the chunk's group of 64 atoms
-        const int el = h0 - ga;            // lanes el .. el + nh - 1 finish its atoms
-        const bool elane = defer && lane >= el && lane < el + nh;
-        if (elane) {
-            pe = a.pos0[home_first + ga + lane];
-            if (KICK || ENERGY) ve = a.vel0[home_first + ga + lane];
-            prefe = pe;
-            if (LIST == 2 && SKIN) prefe = a.posref[home_first + ga + lane];
-        }
+        if (LIST == 2 && SKIN && lead) pref = a.posref[home_first + h0 + h];
         if ((LIST == 1 || LIST == 3) && lead) a.posref[home_first + h0 + h] = pi;
         const float xi = pi.x - ox, yi = pi.y - oy, zi = pi.z - oz;
         const float ai = fmaf(zi, zi, fmaf(yi, yi, xi * xi));
@@ -342,11 +262,9 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
         const float cneg = -thr_i;
         float fx = 0.f, fy = 0.f, fz = 0.f, u_loc = 0.f, w_loc = 0.f;
         int lcount = 0, rec_next = 0;  // LIST 3: the atom's entries so far; this lane's next one
-        int tn_end = 0;                // atoms staged in the last pass
         uint32_t* lrow_list = LIST == 3 ? a.nlist + 4 * static_cast<size_t>(home_first + h0 + h) : nullptr;
         for (int t0 = 0; t0 < total; t0 += a.tile_cap) {
             const int tn = min(a.tile_cap, total - t0);
-            tn_end = tn;
             if (!rows) {
                 __syncthreads();
                 if (wv == 0) {
@@ -411,7 +329,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                     const int nblk = min(8 * kWords, b_hi - b0);
                     uint32_t wd[kWords];
                     if (LIST == 2 && use_list) {
-                        kept_words(lwords, lw0, n_use++, 4 * nblk, wd);
+                        kept_words(lwords, lw0, b0 / (8 * kWords), 4 * nblk, wd);
                     } else {
                         screen_mfma(tile, 16 * b0, nblk, bval, cneg, wd);
                         if (act) clear_self(self_t - 16 * b0, s, 4, 4 * nblk, wd);
@@ -433,7 +351,7 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                 const int first = g0 * ns + (act ? s : 0);
                 uint32_t wd[kWords];
                 if (LIST == 2 && use_list) {
-                    kept_words(lwords, lw0, n_use++, groups, wd);
+                    kept_words(lwords, lw0, g0 / kGroups, groups, wd);
                 } else {
                     switch (ns) {
                         case 2: screen_span<2>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
@@ -441,7 +359,6 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                         case 4: screen_span<4>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
                         case 5: screen_span<5>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
                         case 6: screen_span<6>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
-                        case 16: screen_span<16>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
                         default: screen_span<0>(tile, first, ns, groups, mx, my, mz, thr_i, wd); break;
                     }
                     if (act) clear_self(self_t, first, ns, groups, wd);
@@ -452,61 +369,6 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
             }
         }
         if (EXPORT) continue;
-        if (defer) {
-            // slice sums in slice order on lane h (the lane of slice 0), as
-            // below, but through the padding after the last pass's atoms
-            // (80 entries), so the staged atoms stay for the next chunk; the
-            // next pass writes the padding anew
-            __syncthreads();
-            float* rbuf = reinterpret_cast<float*>(tile + tn_end);
-            rbuf[0 * kWave + lane] = fx;
-            rbuf[1 * kWave + lane] = fy;
-            rbuf[2 * kWave + lane] = fz;
-            if (ENERGY) {
-                rbuf[3 * kWave + lane] = u_loc;
-                rbuf[4 * kWave + lane] = w_loc;
-            }
-            __syncthreads();
-            float gx = 0.f, gy = 0.f, gz = 0.f, gu = 0.f, gw = 0.f;
-            if (lead) {
-                for (int q = 0; q < ns; ++q) {
-                    const int l = h + q * hstride;
-                    gx += rbuf[0 * kWave + l];
-                    gy += rbuf[1 * kWave + l];
-                    gz += rbuf[2 * kWave + l];
-                    if (ENERGY) {
-                        gu += rbuf[3 * kWave + l];
-                        gw += rbuf[4 * kWave + l];
-                    }
-                }
-            }
-            // lane el + h finishes the atom; in a group's first chunk that is
-            // lane h itself
-            int lc = lcount;
-            if (el > 0) {  // uniform
-                const int src = lane - el;
-                gx = __shfl(gx, src);
-                gy = __shfl(gy, src);
-                gz = __shfl(gz, src);
-                if (ENERGY) {
-                    gu = __shfl(gu, src);
-                    gw = __shfl(gw, src);
-                }
-                if (LIST == 3) lc = __shfl(lcount, src);
-            }
-            if (elane) {
-                egx = gx;
-                egy = gy;
-                egz = gz;
-                egu = gu;
-                egw = gw;
-                elc = lc;
-            }
-            if (h0 + nh == n_home || ((h0 + nh) & (kWave - 1)) == 0)  // the group is summed (uniform)
-                finish(lane < min(kWave, n_home - ga), home_first + ga + lane, egx, egy, egz, egu, egw, pe, ve,
-                       prefe, elc);
-            continue;
-        }
         // sum the slice partials of each home atom in slice order (red aliases the
         // tile: every lane has finished its walk at this barrier)
         __syncthreads();
@@ -519,8 +381,15 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
             mine[4 * kWave + lane] = w_loc;
         }
         __syncthreads();
-        float gx = 0.f, gy = 0.f, gz = 0.f, gu = 0.f, gw = 0.f;
+        const int k = home_first + h0 + h;
+        int c_next = -1;  // DRIFT: the home atom's next cell, -1 on lanes without one
+        float4 p_next = pi, v_next = make_float4(0.f, 0.f, 0.f, 0.f);
         if (lead) {
+            if (LIST == 3) {  // the atom's list length (the entries past the capacity were not kept)
+                a.ncount[k] = min(lcount, a.nlist_cap);
+                if (lcount > a.nlist_cap) over = true;
+            }
+            float gx = 0.f, gy = 0.f, gz = 0.f, gu = 0.f, gw = 0.f;
             for (int w = 0; w < nw; ++w) {
                 const float* part = red + 5 * kWave * w;
                 for (int q = 0; q < ns; ++q) {
@@ -534,8 +403,45 @@ __device__ __forceinline__ void force_cell(const SimArgs& a, int c, float4* tile
                     }
                 }
             }
+            if (!finite3(gx, gy, gz)) bad = true;
+            if (WRITE) a.force[k] = make_float4(gx, gy, gz, 0.f);
+            if (KICK || ENERGY) {
+                float4 v = vel;
+                if (KICK) {
+                    v.x += a.hdt_m * gx;
+                    v.y += a.hdt_m * gy;
+                    v.z += a.hdt_m * gz;
+                    if (!DRIFT) a.vel0[k] = v;
+                }
+                if (ENERGY) {
+                    u_acc += static_cast<double>(gu);
+                    w_acc += static_cast<double>(gw);
+                    k_acc += static_cast<double>(a.half_m) * (static_cast<double>(v.x) * v.x +
+                                                              static_cast<double>(v.y) * v.y +
+                                                              static_cast<double>(v.z) * v.z);
+                }
+                if (DRIFT) {
+                    v_next = v;
+                    if (SKIN) {
+                        half_kick_drift_unwrapped(a, p_next, v_next, gx, gy, gz);
+                        a.pos2[k] = p_next;
+                        a.vel2[k] = v_next;
+                        if (LIST != 0) {
+                            const float ex = p_next.x - pref.x, ey = p_next.y - pref.y, ez = p_next.z - pref.z;
+                            if (ex * ex + ey * ey + ez * ez > a.disp_half * a.disp_half) skin_out = true;
+                        } else {
+                            const float ex = fmaxf(fmaxf(ox - p_next.x, p_next.x - (ox + a.s)), 0.f);
+                            const float ey = fmaxf(fmaxf(oy - p_next.y, p_next.y - (oy + a.s)), 0.f);
+                            const float ez = fmaxf(fmaxf(oz - p_next.z, p_next.z - (oz + a.s)), 0.f);
+                            if (ex * ex + ey * ey + ez * ez > a.skin_half * a.skin_half) skin_out = true;
+                        }
+                    } else {
+                        c_next = half_kick_drift(a, p_next, v_next, gx, gy, gz);
+                    }
+                }
+            }
         }
-        finish(lead, home_first + h0 + h, gx, gy, gz, gu, gw, pi, vel, pref, lcount);
+        if (DRIFT && !SKIN && wv == 0) bin_atom(a, p_next, v_next, c_next);  // all lanes of wavefront 0
     }
     if (LIST == 1) a.plist_n[lrow] = list_fits ? n_rec : kListSpans + 1;  // kept words of several passes are not used
     if ((EXPORT || LIST == 3) && over) atomicOr(&a.hdr[HDR_ERROR], DEV_NB_OVERFLOW);
