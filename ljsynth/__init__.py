@@ -172,6 +172,31 @@ def random_fluid(n: int, density: float, seed: int):
     return pos4, box
 
 
+def k_per_cell(k: int, seed: int, nc: int = 4, side: float = 2.6, rc: float = 2.5):
+    """Exactly k <= 27 atoms in every cell of an nc^3 grid of side `side`
+    (>= rc): each cell's atoms on k of the 27 sites of a 3^3 sub-lattice
+    (spacing 0.35 side, 0.3 side across cell faces), picked at random per
+    cell, with a uniform jitter of +-0.03, drawn again (next seed) while any
+    pair lies within 2e-5 of rc. Returns (pos4, box). Every home cell then
+    holds the same number of atoms, which fixes the kernels' lane layout."""
+    box = nc * side
+    u = np.array([0.15, 0.5, 0.85]) * side
+    sites = np.stack(np.meshgrid(u, u, u, indexing="ij"), -1).reshape(-1, 3)
+    cells = np.stack(np.meshgrid(*(np.arange(nc),) * 3, indexing="ij"), -1).reshape(-1, 3) * side
+    for attempt in range(100):
+        rng = np.random.default_rng(seed + 1000 * attempt)
+        pts = np.concatenate([c + sites[rng.choice(27, size=k, replace=False)] for c in cells])
+        pts += rng.uniform(-0.03, 0.03, pts.shape)
+        pos4 = np.zeros((len(pts), 4), np.float32)
+        pos4[:, :3] = pts
+        d = pos4[:, None, :3].astype(np.float64) - pos4[None, :, :3].astype(np.float64)
+        d -= box * np.round(d / box)
+        r = np.sqrt(np.einsum("ijk,ijk->ij", d, d))
+        if not (np.abs(r - rc) < 2e-5).any():
+            return pos4, box
+    raise ValueError("no instance clear of rc")
+
+
 def batched_replicas(count: int = 512, seed: int = 4):
     """Replica table of the batched workload: N = 4 n^3 with n uniform in
     [5, 20], density uniform in [0.70, 0.95], T uniform in [0.7, 1.5]."""

@@ -94,6 +94,34 @@ def test_hvp_and_force_parameter_derivatives(name, waves, orc):
     assert th[1] == pytest.approx(ds, rel=REL)
 
 
+@pytest.mark.parametrize("k", [1, 4, 8, 10, 12, 16, 17, 20, 24])
+def test_hvp_every_home_layout(k, orc):
+    """The pair pass on every home-cell lane layout on its own (exactly k
+    atoms in every cell: the VALU screen with 16 down to 6 slices, the
+    matrix-core screen, three and two slices): Hessian-vector product and
+    virial gradient against the oracle."""
+    torch = _torch()
+    from paper_0709_3225_amd import _lib as L
+
+    pos4, box = ljsynth.k_per_cell(k, 200 + k)
+    _say(f"hvp home layout k={k} n={len(pos4)}")
+    w = np.zeros_like(pos4)
+    w[:, :3] = np.random.default_rng(k).normal(size=(len(pos4), 3))
+    p = orc.params(box)
+    s = _loaded(pos4, box)
+    assert s.cells_per_dim == 4
+    lam = torch.zeros((len(pos4), 4), dtype=torch.float32, device="cuda")
+    L.md_adjoint_kick(s.params, s.ws, _dev(w), lam, None, 1.0)
+    assert s.check() == 0
+    assert rel_l2(lam.cpu().numpy()[:, :3].astype(np.float64), orc.hvp(p, pos4, w)) <= REL
+    gref, _, _ = orc.virial_grad(p, pos4)
+    gr = torch.zeros((len(pos4), 4), dtype=torch.float32, device="cuda")
+    gv = torch.zeros((len(pos4), 4), dtype=torch.float32, device="cuda")
+    L.md_loss_grad(s.params, s.ws, 0.0, 1.0, gr, gv, None)
+    assert s.check() == 0
+    assert rel_l2(gr.cpu().numpy()[:, :3].astype(np.float64), gref) <= REL
+
+
 @pytest.mark.parametrize("tile", [192, 1024])
 @pytest.mark.parametrize("name", ["lj4k", "lj32k_adjoint"])
 def test_hvp_with_lds_tile(name, tile, orc):

@@ -179,31 +179,6 @@ def test_neighbor_sets_exact(case, orc):
     _assert_rows(counts, idx, counts_o, idx_o)
 
 
-def _k_per_cell_state(k, seed, rc=2.5):
-    """Exactly k atoms in every cell of a 4^3 grid of side 2.6 sigma: each
-    cell's atoms on k of the 27 sites of a 3^3 sub-lattice (spacing 0.91,
-    0.78 across cell faces), picked at random per cell, with a small jitter,
-    drawn again (next seed) while any pair lies within 2e-5 of r_c (the
-    oracle's FP32/FP64 guard band on r^2 is 1e-5 relative)."""
-    nc, side = 4, 2.6
-    box = nc * side
-    u = np.array([0.15, 0.5, 0.85]) * side
-    sites = np.stack(np.meshgrid(u, u, u, indexing="ij"), -1).reshape(-1, 3)
-    cells = np.stack(np.meshgrid(*(np.arange(nc),) * 3, indexing="ij"), -1).reshape(-1, 3) * side
-    for attempt in range(100):
-        rng = np.random.default_rng(seed + 1000 * attempt)
-        pts = np.concatenate([c + sites[rng.choice(27, size=k, replace=False)] for c in cells])
-        pts += rng.uniform(-0.03, 0.03, pts.shape)
-        pos4 = np.zeros((len(pts), 4), np.float32)
-        pos4[:, :3] = pts
-        d = pos4[:, None, :3].astype(np.float64) - pos4[None, :, :3].astype(np.float64)
-        d -= box * np.round(d / box)
-        r = np.sqrt(np.einsum("ijk,ijk->ij", d, d))
-        if not (np.abs(r - rc) < 2e-5).any():
-            return pos4, box
-    raise AssertionError("no instance clear of r_c")
-
-
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 16, 17, 20, 21, 22, 24])
 def test_every_home_layout_matches_oracle(k, orc):
     """Every cell holds exactly k atoms, so every home cell takes the same
@@ -213,7 +188,7 @@ def test_every_home_layout_matches_oracle(k, orc):
     every pair dropped or added near r_c moves a force by |f_LJ(r_c)|; forces
     against the oracle, and the pairs the force kernel's walk accepts
     against its brute-force sets."""
-    pos4, box = _k_per_cell_state(k, 100 + k)
+    pos4, box = ljsynth.k_per_cell(k, 100 + k)
     _say(f"home layout k={k} n={len(pos4)}")
     p = orc.params(box, shift_mode=1)
     counts_o, idx_o, guard = orc.neighbors(p, pos4)
