@@ -81,6 +81,15 @@ CASES = {
     "dense_clump": _clump_state,
 }
 
+# exactly k atoms in every cell of a 4^3 grid: the 12-slice VALU layout, three
+# slices, two slices (compressed states with contacts near 0.72 sigma: pair
+# sets and forces, not the energy bound)
+LAYOUT_CASES = {
+    "cells_of_5": lambda: ljsynth.k_per_cell(5, 305),
+    "cells_of_18": lambda: ljsynth.k_per_cell(18, 318),
+    "cells_of_22": lambda: ljsynth.k_per_cell(22, 322),
+}
+
 
 def _gas(n, rho, seed, min_sep=0.0):
     pos4, box = ljsynth.random_fluid(n, rho, seed)
@@ -202,13 +211,14 @@ def test_every_home_layout_matches_oracle(k, orc):
     _assert_rows(counts, idx, counts_o, idx_o)
 
 
-@pytest.mark.parametrize("case", ["lj4k_jitter_shuffled", "lj32k_jitter", "fcc_rho1.2_jitter", "dense_clump"])
+@pytest.mark.parametrize("case", ["lj4k_jitter_shuffled", "lj32k_jitter", "fcc_rho1.2_jitter", "dense_clump",
+                                  "cells_of_5", "cells_of_18", "cells_of_22"])
 def test_neighbor_sets_pair_lists(case, orc):
     """The pair-list path of md_step_list: the pass that screens against the
     list radius and keeps the accept words, then the pass that walks the kept
     words, each export the oracle's sets (the dense clump takes several LDS
     passes and so screens in both)."""
-    pos4, box = CASES[case]()
+    pos4, box = {**CASES, **LAYOUT_CASES}[case]()
     _say(f"neighbors via pair lists {case} n={len(pos4)}")
     counts_o, idx_o, guard = orc.neighbors(orc.params(box), pos4)
     assert guard == 0
