@@ -188,21 +188,23 @@ def test_neighbor_sets_exact(case, orc):
     _assert_rows(counts, idx, counts_o, idx_o)
 
 
+@pytest.mark.parametrize("waves", [1, 4])
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 16, 17, 20, 21, 22, 24])
-def test_every_home_layout_matches_oracle(k, orc):
+def test_every_home_layout_matches_oracle(k, waves, orc):
     """Every cell holds exactly k atoms, so every home cell takes the same
     lane layout: the VALU screen with 16 down to 6 slices (k <= 10), the
     matrix-core screen (11..16), three and two slices (17..24; the larger
     neighbourhoods in more than one LDS pass). With the plain truncated force
     every pair dropped or added near r_c moves a force by |f_LJ(r_c)|; forces
     against the oracle, and the pairs the force kernel's walk accepts
-    against its brute-force sets."""
+    against its brute-force sets. One wavefront per cell, and four that
+    split every pass's candidates between them."""
     pos4, box = ljsynth.k_per_cell(k, 100 + k)
-    _say(f"home layout k={k} n={len(pos4)}")
+    _say(f"home layout k={k} n={len(pos4)} waves={waves}")
     p = orc.params(box, shift_mode=1)
     counts_o, idx_o, guard = orc.neighbors(p, pos4)
     assert guard == 0, "instance has pairs within the FP32/FP64 guard band of r_c"
-    s, f, _ = gpu_forces(pos4, box, shift_mode=1)
+    s, f, _ = gpu_forces(pos4, box, shift_mode=1, waves_per_cell=waves)
     assert s.cells_per_dim == 4
     fo, _, _ = orc.forces(p, pos4)
     assert rel_l2(f, fo) <= FORCE_TOL
